@@ -1,0 +1,155 @@
+#!/usr/bin/env python3
+"""Throughput of the muffin-tin H+S build on one MI355X.
+
+One step = one hsbuild_forward call (matching coefficients, per-atom T
+products and the fused Hermitian H/S contraction) over the full-size
+synthetic cell: 4 atom types x 32 atoms, l_max = 10 (N_L = 121), N_G = 12000,
+complex128.  Inputs are resident in HBM before the timed region.  The value
+is FP64-equivalent TFLOP/s with the algorithmic flop count
+F = 16 k_c N_G (N_G + 1) + 32 N_atoms N_L^2 N_G  (k_c = N_atoms N_L).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+FP64_MFMA_PEAK_TFLOPS = 78.6
+METRIC = "H+S build FP64-equiv TFLOP/s, % FP64 MFMA peak; split/FP64 speedup @1e-10"
+
+
+def log(msg: str) -> None:
+    sys.stderr.write("[bench] %s\n" % msg)
+    sys.stderr.flush()
+
+
+def cpu_baseline(index: int, n_g: int) -> dict:
+    """The oracle as it stands, on a bounded sample of the same workload: the
+    same cell at a reduced basis size."""
+    from threadpoolctl import threadpool_info
+
+    from flapw_cells import make_case
+    from oracle import hs_oracle as o
+    case = make_case(index, n_g=n_g)
+    t0 = time.perf_counter()
+    o.hs(case)
+    dt = time.perf_counter() - t0
+    flops = o.flops_forward(case["n_atoms"], case["n_l"], n_g)
+    threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
+    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+            "sample": "oracle H+S (numpy complex128 over OpenBLAS) on the same cell at N_G=%d "
+                      "(F=%.3g TFLOP, %.1f s)" % (n_g, flops / 1e12, dt)}
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--config", type=int, default=2, help="workload index (default: the full-size cell)")
+    ap.add_argument("--ng", type=int, default=None, help="override the basis size")
+    ap.add_argument("--cpu-ng", type=int, default=3000, help="basis size of the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the H/S tiles would be "
+              "dealt over GPUs with no exchange; see the design notes). Run with --gpus 1.")
+        return 2
+
+    import numpy as np
+    import torch
+
+    from flapw_cells import make_case
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+
+    if not torch.cuda.is_available():
+        log("no HIP device")
+        return 1
+    case = make_case(args.config, n_g=args.ng)
+    n, n_at, n_l = case["n_g"], case["n_atoms"], case["n_l"]
+    k_c = n_at * n_l
+    flops_hs = 16.0 * k_c * n * (n + 1)
+    flops = flops_hs + 32.0 * n_at * n_l * n_l * n
+    log("workload %s: N_G=%d atoms=%d N_L=%d k_c=%d F=%.4g TFLOP" % (case["name"], n, n_at, n_l, k_c, flops / 1e12))
+
+    b = HSBuilder.from_case(case)
+    g, tau, T = case_tensors(case)
+    H = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    S = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    from paper_1712_07206_amd import _native as N
+    ws_bytes = b.workspace_bytes(N.HSB_MODE_FORWARD, [n])
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+    log("workspace %.2f GB, outputs %.2f GB" % (ws_bytes / 1e9, 2 * H.numel() * 16 / 1e9))
+
+    def step():
+        code = b.forward_raw(case["k_frac"], n, g, tau, T, H, S, ws, ws_bytes)
+        if code != N.HSB_OK:
+            raise N.HSBuildError(code, N.last_error(b._h))
+
+    for i in range(args.warmup):
+        step()
+        torch.cuda.synchronize()
+        log("warmup %d done" % i)
+    b.set_timing(True)
+    torch.cuda.synchronize()
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    for _ in range(args.steps):
+        step()
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_total = start.elapsed_time(stop)
+    stage_ms, calls = b.stage_times()
+    b.set_timing(False)
+    ms_step = ms_total / args.steps
+    log("timed %d steps: %.3f ms/step (wall %.3f s); stages ms: coef %.3f, tprod %.3f, hs %.3f over %d calls"
+        % (args.steps, ms_step, wall, stage_ms[0], stage_ms[1], stage_ms[2], calls))
+    tflops = flops / (ms_step * 1e-3) / 1e12
+    hs_tflops = flops_hs / (stage_ms[2] * 1e-3) / 1e12
+
+    result = {
+        "metric": METRIC,
+        "value": round(tflops, 4),
+        "unit": "TFLOP/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: seeded cell, positions, radial values and Hermitian T blocks shaped like the "
+                "paper's workloads (no FLEUR inputs)",
+        "config": {"workload": case["name"], "n_atoms": n_at, "n_types": case["n_types"], "l_max": case["l_max"],
+                   "n_l": n_l, "n_g": n, "k_c": k_c, "precision": "fp64", "flops_per_step": flops},
+        "pct_fp64_mfma_peak": round(100.0 * tflops / FP64_MFMA_PEAK_TFLOPS, 2),
+        "stages_ms": {"coefficients": round(stage_ms[0], 4), "t_products": round(stage_ms[1], 4),
+                      "hs_contraction": round(stage_ms[2], 4)},
+        "roofline": {"kernel": "k_hs_fp64", "bound": "mfma", "achieved": round(hs_tflops, 4),
+                     "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                     "frac": round(hs_tflops / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                     "algorithmic_flops_per_launch": flops_hs},
+        "split_speedup": None,
+    }
+    del H, S, ws
+    torch.cuda.empty_cache()
+    if not args.no_cpu_baseline:
+        log("timing the oracle sample on the host (N_G=%d)" % args.cpu_ng)
+        result["cpu_baseline"] = cpu_baseline(args.config, args.cpu_ng)
+        log("oracle: %.4f TFLOP/s on %d threads" % (result["cpu_baseline"]["value"], result["cpu_baseline"]["cores"]))
+    else:
+        result["cpu_baseline"] = None
+    print(json.dumps(result))
+    sys.stdout.flush()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

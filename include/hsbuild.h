@@ -1,0 +1,159 @@
+/*
+ * hsbuild: muffin-tin Hamiltonian and overlap matrices of the FLAPW method on
+ * one AMD Instinct MI355X (gfx950).
+ *
+ * For one k-point with plane-wave basis {G : |k+G| <= K_max} (Sec. 2.1 of
+ * Davidovic et al., "Accelerating the computation of FLAPW methods on
+ * heterogeneous architectures"), the library builds the complex Hermitian
+ * N_G x N_G matrices
+ *
+ *   S = sum_a A_a^H A_a + B_a^H diag(||udot_l||^2) B_a            (Eq. 4 / Eq. 7)
+ *   H = sum_a [A_a; B_a]^H T_t(a) [A_a; B_a]                       (Eq. 5 / Eq. 6)
+ *
+ * where a runs over atoms, t(a) is the atom's type, A_a, B_a in C^{N_L x N_G}
+ * are the matching coefficients of Eq. 2 and T_t = [[T^AA, T^AB], [T^BA, T^BB]]
+ * (T^BA = (T^AB)^H, Sec. 3) is the type's 2N_L x 2N_L Hermitian block.
+ *
+ * Matching coefficients (Eq. 2 with continuity of value and slope at R_MT,
+ * Sec. 2.1; the paper leaves the formula to the standard LAPW matching):
+ *   K = k + G, x = |K| R_t, W_l = u udot' - udot u'
+ *   a_l = (j_l(x) udot' - |K| j_l'(x) udot) / W_l,  b_l = (|K| j_l'(x) u - j_l(x) u') / W_l
+ *   A^{a,G}_{lm} = (4 pi / sqrt(Omega)) e^{i K.tau_a} i^l conj(Y_lm(K_hat)) a_l,  B likewise with b_l
+ * Y_lm: complex orthonormal spherical harmonics with the Condon-Shortley
+ * phase; compound index L = l^2 + l + m, m = -l..l.  K_hat = z when |K| < 1e-12.
+ *
+ * Conventions for every entry point:
+ *   - complex values are complex128, interleaved (re, im) doubles;
+ *   - matrices are row-major; H and S are indexed [G'][G] in the caller's G
+ *     order, leading dimension N_G; only the upper triangle (column >= row,
+ *     diagonal included) is written, the strict lower triangle is untouched;
+ *   - all arguments are validated on the host before anything is enqueued; on
+ *     an error nothing is launched and the outputs are untouched;
+ *   - calls are asynchronous and stream-ordered on `stream` (a hipStream_t,
+ *     NULL = the default stream); device faults surface at the caller's
+ *     synchronisation;
+ *   - the caller owns every device buffer, the workspace included; the
+ *     library allocates no device memory;
+ *   - a handle is not thread-safe: use one handle per stream.
+ */
+#ifndef HSBUILD_H
+#define HSBUILD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct hsbuild_s* hsbuild_t;
+
+/* Status codes. */
+enum {
+  HSB_OK = 0,
+  HSB_ERR_ARG = -1,         /* null pointer, out-of-range scalar */
+  HSB_ERR_SHAPE = -2,       /* inconsistent sizes (e.g. ng > max_ng) */
+  HSB_ERR_WORKSPACE = -3,   /* workspace smaller than hsbuild_workspace_bytes() */
+  HSB_ERR_DEVICE = -4,      /* no usable gfx950 device, or a launch error */
+  HSB_ERR_UNSUPPORTED = -5, /* valid request this build does not implement */
+  HSB_ERR_NUMERIC = -6      /* singular radial Wronskian at create */
+};
+
+/* Contraction precision. */
+enum { HSB_FP64 = 0, HSB_SPLIT_FP16 = 1, HSB_SPLIT_BF16 = 2 };
+
+/* Workspace modes for hsbuild_workspace_bytes. */
+enum { HSB_MODE_FORWARD = 0, HSB_MODE_BACKWARD = 1, HSB_MODE_BATCH = 2, HSB_MODE_COEFFICIENTS = 3 };
+
+#define HSB_MAX_TYPES 16
+#define HSB_MAX_LMAX 12
+
+/* Static description of the cell; all pointers are host memory and are
+ * copied by hsbuild_create (the caller may free them afterwards). */
+typedef struct {
+  int32_t n_types;            /* 1..HSB_MAX_TYPES */
+  int32_t n_atoms;            /* >= 1 */
+  int32_t l_max;              /* 0..HSB_MAX_LMAX; N_L = (l_max+1)^2 */
+  int32_t max_ng;             /* largest basis size any call will pass */
+  double lattice[9];          /* rows a1, a2, a3 (bohr); Omega = |det| */
+  const int32_t* atom_type;   /* [n_atoms], non-decreasing (atoms grouped by type) */
+  const double* r_mt;         /* [n_types] muffin-tin radii (bohr), > 0 */
+  const double* radial;       /* [n_types][l_max+1][4]: u, u', udot, udot' at R_MT */
+  const double* udot_norm2;   /* [n_types][l_max+1]: ||udot_l||^2 >= 0 */
+  int32_t precision;          /* HSB_FP64, HSB_SPLIT_FP16 or HSB_SPLIT_BF16 */
+  int32_t n_slices;           /* split path only: slices per operand, 3..8 */
+} hsb_config;
+
+/* Create a handle.  Returns HSB_ERR_NUMERIC if some radial Wronskian
+ * |u udot' - udot u'| < 1e-12 (|u udot'| + |udot u'|), HSB_ERR_DEVICE if the
+ * current device is not gfx950.  *out is set only on success. */
+int hsbuild_create(const hsb_config* cfg, hsbuild_t* out);
+
+/* Destroy a handle (NULL is ignored).  Does not synchronise. */
+void hsbuild_destroy(hsbuild_t h);
+
+/* Bytes of device workspace a call needs.  mode: HSB_MODE_*; ng: host array
+ * of n_k basis sizes (n_k = 1 except for HSB_MODE_BATCH).  Returns 0 on an
+ * invalid request (see hsbuild_last_error). */
+size_t hsbuild_workspace_bytes(hsbuild_t h, int32_t mode, int32_t n_k, const int32_t* ng);
+
+/* Matching coefficients only (Eq. 2): coef (device, complex128
+ * [n_atoms][2][N_L][ng]) receives A (index 0) and B (index 1) of every atom.
+ * k_frac: host double[3], k in the reciprocal basis; g: device int32
+ * [ng][3] integer reciprocal vectors; tau: device double [n_atoms][3]
+ * cartesian positions (bohr). */
+int hsbuild_coefficients(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g,
+                         const double* tau, void* coef, void* ws, size_t ws_bytes, void* stream);
+
+/* H and S of one k-point (Eqs. 4-7).  T: device complex128
+ * [n_types][2N_L][2N_L], Hermitian, rows/columns ordered (A|B, L).
+ * H, S: device complex128 [ng][ng]; upper triangle written.
+ * The handle's precision selects the FP64 MFMA contraction or the
+ * split-precision (Ozaki slice) contraction. */
+int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
+                    const void* T, void* H, void* S, void* ws, size_t ws_bytes, void* stream);
+
+/* Adjoint of hsbuild_forward for a real loss L(H, S).  gH, gS: device
+ * complex128 [ng][ng], the full Hermitian gradients dL/dRe H + i dL/dIm H
+ * (likewise S).  Outputs: gT device complex128 [n_types][2N_L][2N_L] =
+ * dL/dRe T + i dL/dIm T with T's entries taken as free; gtau device double
+ * [n_atoms][3] = dL/dtau (cartesian).  Both outputs are overwritten.
+ * The coefficients are recomputed, nothing is kept from the forward. */
+int hsbuild_backward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
+                     const void* T, const void* gH, const void* gS, void* gT, double* gtau, void* ws,
+                     size_t ws_bytes, void* stream);
+
+/* H and S of n_k k-points sharing tau and T.  k_frac: host double[n_k][3];
+ * ng: host int32[n_k]; g: device int32, the n_k G lists concatenated;
+ * out_off: host int64[n_k], element offsets of each k's ng x ng block in H and S. */
+int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t* ng, const int32_t* g,
+                  const int64_t* out_off, const double* tau, const void* T, void* H, void* S, void* ws,
+                  size_t ws_bytes, void* stream);
+
+/* Stage timing with HIP events recorded on the call's stream, for profiling.
+ * hsbuild_set_timing(h, 1) creates an event pool and clears the record;
+ * while enabled, each hsbuild_forward records events around its three stages
+ * (0: coefficients and tables, 1: per-atom T products, 2: the H/S
+ * contraction), for up to HSB_TIMING_CAPACITY calls (later calls are not
+ * recorded).  hsbuild_stage_times waits for the recorded events and returns
+ * the average milliseconds of each stage over the recorded calls (ms_avg[3])
+ * and their number.  hsbuild_set_timing(h, 0) destroys the pool. */
+#define HSB_TIMING_CAPACITY 256
+int hsbuild_set_timing(hsbuild_t h, int32_t enable);
+int hsbuild_stage_times(hsbuild_t h, double* ms_avg, int32_t* n_calls);
+
+/* Message of the last error on h (h = NULL: the last hsbuild_create error of
+ * this thread).  Valid until the next call on the handle. */
+const char* hsbuild_last_error(hsbuild_t h);
+
+/* Host-side evaluation of the device special functions, for checks without a
+ * GPU: j_l(x) and j_l'(x) for l = 0..lmax (out arrays of lmax+1 doubles), and
+ * pre * i^l conj(Y_lm(K_hat)) for L = 0..(lmax+1)^2-1 (complex128 out). */
+int hsbuild_host_bessel(int32_t lmax, double x, double* jl, double* djl);
+int hsbuild_host_angular(int32_t lmax, const double kvec[3], double pre, void* out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HSBUILD_H */

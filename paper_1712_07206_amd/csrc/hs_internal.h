@@ -1,0 +1,65 @@
+// Internal declarations shared by the host library and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+
+#include "hsbuild.h"
+
+namespace hsb {
+
+constexpr int kTileN = 128;  // basis sizes are padded to a multiple of this
+constexpr int kTileK = 16;   // the stacked contraction index is padded to a multiple of this
+
+inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
+
+// Cell description passed by value to the coefficient kernels.
+struct CellArgs {
+  double bvec[9];   // reciprocal basis rows b_j (a_i . b_j = 2 pi delta_ij)
+  double kfrac[3];  // k in the reciprocal basis
+  double pre;       // 4 pi / sqrt(Omega)
+  int n_types, n_atoms, l_max, n_l;
+  int type_start[HSB_MAX_TYPES + 1];  // atoms of type t: [type_start[t], type_start[t+1])
+  double r_mt[HSB_MAX_TYPES];
+};
+
+// Device-side per-type constants, copied into the workspace by each call.
+struct TypeConsts {
+  double radial[HSB_MAX_TYPES][HSB_MAX_LMAX + 1][4];  // u, u', udot, udot' at R_MT
+  double udot2[HSB_MAX_TYPES][HSB_MAX_LMAX + 1];      // ||udot_l||^2
+};
+
+// Placement of one k-point's arrays inside the workspace (byte offsets).
+//   W   : stacked coefficients, complex [K_pad][n_pad]; row k = (atom, A|B, L)
+//         = atom*2N_L + (0 for A, N_L for B) + L; columns G (>= n are zero)
+//   Y   : T_t W per atom, same shape (rows >= K are zero)
+//   ang : pre * i^l conj(Y_lm(K_hat_G)), complex [N_L][n_pad]
+//   ab  : (a_l, b_l) per type, double2 [n_types][l_max+1][n_pad]
+//   kv  : (Kx, Ky, Kz, |K|) per G, double4-like [n_pad][4]
+//   lam : S weight of row k (1 for A rows, ||udot_l||^2 for B rows, 0 for pad)
+struct Layout {
+  int n = 0, n_pad = 0, K = 0, K_pad = 0;
+  size_t W = 0, Y = 0, ang = 0, ab = 0, kv = 0, lam = 0, consts = 0, extra = 0, end = 0;
+};
+
+// ---- kernel launchers (each returns hipGetLastError() after enqueue) ----
+
+// ang, ab, kv (all padded columns written) from the G list.
+hipError_t launch_tables(const CellArgs& c, const TypeConsts* consts, int n, int n_pad, const int32_t* g,
+                         double2* ang, double2* ab, double* kv, hipStream_t s);
+// lam[k] for k in [0, K_pad).
+hipError_t launch_lambda(const CellArgs& c, const TypeConsts* consts, int K_pad, double* lam, hipStream_t s);
+// out[(atom*2N_L + (A|B)*N_L + L) * ld + G] for G < n_store.
+hipError_t launch_assemble(const CellArgs& c, int n_pad, const double2* ang, const double2* ab, const double* kv,
+                           const double* tau, double2* out, int64_t ld, int n_store, hipStream_t s);
+// rows [row0, row1) of a [*][ld] complex array set to zero.
+hipError_t launch_zero_rows(double2* a, int64_t ld, int row0, int row1, hipStream_t s);
+// Y_atom = T_type(atom) W_atom for every atom (rows of W/Y per atom: 2N_L).
+hipError_t launch_tprod(const CellArgs& c, const double2* T, const double2* W, double2* Y, int n_pad,
+                        hipStream_t s);
+// Upper triangles of H = W^H Y and S = W^H diag(lam) W over K_pad rows.
+hipError_t launch_hs_fp64(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
+                          double2* H, double2* S, int64_t ldh, hipStream_t s);
+
+}  // namespace hsb

@@ -1,0 +1,397 @@
+// Host side of the hsbuild C-ABI: validation, workspace layout and launch
+// sequencing.  No exception crosses the ABI and nothing here allocates device
+// memory; the caller owns every device buffer including the workspace.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "hs_internal.h"
+#include "hsbuild.h"
+#include "special.h"
+
+using namespace hsb;
+
+struct hsbuild_s {
+  int device = 0;
+  int n_types = 0, n_atoms = 0, l_max = 0, n_l = 0, max_ng = 0;
+  int precision = HSB_FP64, n_slices = 0;
+  double lattice[9];
+  CellArgs cell;              // kfrac filled per call
+  TypeConsts* consts = nullptr;  // pinned host copy, source of the per-call upload
+  std::string err;
+  // stage timing (hsbuild_set_timing)
+  std::vector<hipEvent_t> events;  // 4 per recorded call
+  int n_timed = 0;
+};
+
+namespace {
+
+thread_local std::string g_create_error;
+
+int fail(hsbuild_t h, int code, const char* fmt, ...) __attribute__((format(printf, 3, 4)));
+int fail(hsbuild_t h, int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (h) h->err = buf;
+  else g_create_error = buf;
+  return code;
+}
+
+size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+Layout make_layout(const hsbuild_s& h, int ng, int mode) {
+  Layout L;
+  L.n = ng;
+  L.n_pad = (int)round_up(ng, kTileN);
+  L.K = 2 * h.n_atoms * h.n_l;
+  L.K_pad = (int)round_up(L.K, kTileK);
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t np = (size_t)L.n_pad;
+  L.consts = take(sizeof(TypeConsts));
+  L.kv = take(np * 4 * sizeof(double));
+  L.ang = take((size_t)h.n_l * np * sizeof(double2));
+  L.ab = take((size_t)h.n_types * (h.l_max + 1) * np * sizeof(double2));
+  if (mode != HSB_MODE_COEFFICIENTS) {
+    L.lam = take((size_t)L.K_pad * sizeof(double));
+    L.W = take((size_t)L.K_pad * np * sizeof(double2));
+    L.Y = take((size_t)L.K_pad * np * sizeof(double2));
+  }
+  L.end = off;
+  return L;
+}
+
+int check_device(hsbuild_t h) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return fail(h, HSB_ERR_DEVICE, "hipGetDevice failed");
+  if (dev != h->device)
+    return fail(h, HSB_ERR_DEVICE, "current device %d is not the handle's device %d", dev, h->device);
+  return HSB_OK;
+}
+
+int check_ws(hsbuild_t h, const Layout& L, void* ws, size_t ws_bytes) {
+  if (!ws) return fail(h, HSB_ERR_ARG, "workspace pointer is null");
+  if (((uintptr_t)ws) & 255) return fail(h, HSB_ERR_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.end)
+    return fail(h, HSB_ERR_WORKSPACE, "workspace has %zu bytes, this call needs %zu", ws_bytes, L.end);
+  return HSB_OK;
+}
+
+int check_ng(hsbuild_t h, int32_t ng) {
+  if (ng < 1) return fail(h, HSB_ERR_SHAPE, "ng must be >= 1 (got %d)", ng);
+  if (ng > h->max_ng) return fail(h, HSB_ERR_SHAPE, "ng=%d exceeds max_ng=%d given at create", ng, h->max_ng);
+  return HSB_OK;
+}
+
+int launched(hsbuild_t h, hipError_t e, const char* what) {
+  if (e != hipSuccess) return fail(h, HSB_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return HSB_OK;
+}
+
+// Records stage boundary `idx` (0..3) of the current call when timing is on.
+void mark(hsbuild_t h, int idx, hipStream_t s) {
+  if (h->events.empty() || h->n_timed >= HSB_TIMING_CAPACITY) return;
+  (void)hipEventRecord(h->events[4 * h->n_timed + idx], s);
+  if (idx == 3) ++h->n_timed;
+}
+
+void destroy_events(hsbuild_t h) {
+  for (hipEvent_t e : h->events) (void)hipEventDestroy(e);
+  h->events.clear();
+  h->n_timed = 0;
+}
+
+// Uploads the type constants and builds K vectors, angular factors and (a, b).
+int enqueue_tables(hsbuild_t h, const Layout& L, const double k_frac[3], const int32_t* g, char* ws,
+                   hipStream_t s, CellArgs& c) {
+  c = h->cell;
+  for (int i = 0; i < 3; ++i) c.kfrac[i] = k_frac[i];
+  TypeConsts* dconsts = (TypeConsts*)(ws + L.consts);
+  hipError_t e = hipMemcpyAsync(dconsts, h->consts, sizeof(TypeConsts), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return launched(h, e, "upload of type constants");
+  e = launch_tables(c, dconsts, L.n, L.n_pad, g, (double2*)(ws + L.ang), (double2*)(ws + L.ab),
+                    (double*)(ws + L.kv), s);
+  return launched(h, e, "k_tables");
+}
+
+// Tables, stacked coefficients W (pad rows zeroed), Y = T W per atom and lam.
+int enqueue_operands(hsbuild_t h, const Layout& L, const double k_frac[3], const int32_t* g, const double* tau,
+                     const void* T, char* ws, hipStream_t s) {
+  CellArgs c;
+  int rc = enqueue_tables(h, L, k_frac, g, ws, s, c);
+  if (rc) return rc;
+  double2* W = (double2*)(ws + L.W);
+  double2* Y = (double2*)(ws + L.Y);
+  rc = launched(h, launch_lambda(c, (const TypeConsts*)(ws + L.consts), L.K_pad, (double*)(ws + L.lam), s),
+                "k_lambda");
+  if (rc) return rc;
+  rc = launched(h, launch_assemble(c, L.n_pad, (const double2*)(ws + L.ang), (const double2*)(ws + L.ab),
+                                   (const double*)(ws + L.kv), tau, W, L.n_pad, L.n_pad, s),
+                "k_assemble");
+  if (rc) return rc;
+  rc = launched(h, launch_zero_rows(W, L.n_pad, L.K, L.K_pad, s), "k_zero_rows");
+  if (rc) return rc;
+  rc = launched(h, launch_zero_rows(Y, L.n_pad, L.K, L.K_pad, s), "k_zero_rows");
+  if (rc) return rc;
+  mark(h, 1, s);
+  rc = launched(h, launch_tprod(c, (const double2*)T, W, Y, L.n_pad, s), "k_tprod");
+  mark(h, 2, s);
+  return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hsbuild_create(const hsb_config* cfg, hsbuild_t* out) {
+  g_create_error.clear();
+  if (!cfg || !out) return fail(nullptr, HSB_ERR_ARG, "null config or output pointer");
+  if (cfg->n_types < 1 || cfg->n_types > HSB_MAX_TYPES)
+    return fail(nullptr, HSB_ERR_ARG, "n_types=%d outside [1, %d]", cfg->n_types, HSB_MAX_TYPES);
+  if (cfg->n_atoms < 1) return fail(nullptr, HSB_ERR_ARG, "n_atoms=%d must be >= 1", cfg->n_atoms);
+  if (cfg->l_max < 0 || cfg->l_max > HSB_MAX_LMAX)
+    return fail(nullptr, HSB_ERR_ARG, "l_max=%d outside [0, %d]", cfg->l_max, HSB_MAX_LMAX);
+  if (cfg->max_ng < 1) return fail(nullptr, HSB_ERR_ARG, "max_ng=%d must be >= 1", cfg->max_ng);
+  if (!cfg->atom_type || !cfg->r_mt || !cfg->radial || !cfg->udot_norm2)
+    return fail(nullptr, HSB_ERR_ARG, "null atom_type, r_mt, radial or udot_norm2");
+  if (cfg->precision != HSB_FP64 && cfg->precision != HSB_SPLIT_FP16 && cfg->precision != HSB_SPLIT_BF16)
+    return fail(nullptr, HSB_ERR_ARG, "unknown precision %d", cfg->precision);
+  if (cfg->precision != HSB_FP64 && (cfg->n_slices < 3 || cfg->n_slices > 8))
+    return fail(nullptr, HSB_ERR_ARG, "n_slices=%d outside [3, 8]", cfg->n_slices);
+  const int n_l = (cfg->l_max + 1) * (cfg->l_max + 1);
+  const int64_t K = 2LL * cfg->n_atoms * n_l;
+  if (K > (1LL << 30) || (int64_t)cfg->max_ng * (int64_t)round_up(cfg->max_ng, kTileN) > (1LL << 40))
+    return fail(nullptr, HSB_ERR_SHAPE, "problem too large");
+  // atoms grouped by type
+  int type_start[HSB_MAX_TYPES + 1];
+  for (int t = 0; t <= cfg->n_types; ++t) type_start[t] = 0;
+  int prev = 0;
+  for (int a = 0; a < cfg->n_atoms; ++a) {
+    const int t = cfg->atom_type[a];
+    if (t < 0 || t >= cfg->n_types) return fail(nullptr, HSB_ERR_ARG, "atom %d has type %d", a, t);
+    if (t < prev) return fail(nullptr, HSB_ERR_ARG, "atom_type must be non-decreasing (atom %d)", a);
+    prev = t;
+  }
+  {
+    int a = 0;
+    for (int t = 0; t < cfg->n_types; ++t) {
+      type_start[t] = a;
+      while (a < cfg->n_atoms && cfg->atom_type[a] == t) ++a;
+    }
+    type_start[cfg->n_types] = cfg->n_atoms;
+  }
+  for (int t = 0; t < cfg->n_types; ++t) {
+    if (!(cfg->r_mt[t] > 0.0) || !std::isfinite(cfg->r_mt[t]))
+      return fail(nullptr, HSB_ERR_ARG, "r_mt[%d] must be positive", t);
+    for (int l = 0; l <= cfg->l_max; ++l) {
+      const double* r = cfg->radial + ((size_t)t * (cfg->l_max + 1) + l) * 4;
+      const double wr = r[0] * r[3] - r[2] * r[1];
+      const double scale = std::fabs(r[0] * r[3]) + std::fabs(r[2] * r[1]);
+      if (!std::isfinite(wr) || !(std::fabs(wr) >= 1e-12 * scale) || scale == 0.0)
+        return fail(nullptr, HSB_ERR_NUMERIC, "radial Wronskian of type %d, l=%d is singular (%g)", t, l, wr);
+      const double u2 = cfg->udot_norm2[(size_t)t * (cfg->l_max + 1) + l];
+      if (!(u2 >= 0.0) || !std::isfinite(u2))
+        return fail(nullptr, HSB_ERR_ARG, "udot_norm2[%d][%d] must be finite and >= 0", t, l);
+    }
+  }
+  // reciprocal basis from the lattice rows
+  const double* A = cfg->lattice;
+  const double det = A[0] * (A[4] * A[8] - A[5] * A[7]) - A[1] * (A[3] * A[8] - A[5] * A[6]) +
+                     A[2] * (A[3] * A[7] - A[4] * A[6]);
+  if (!std::isfinite(det) || std::fabs(det) < 1e-9) return fail(nullptr, HSB_ERR_ARG, "degenerate lattice");
+
+  int dev = -1;
+  hipDeviceProp_t prop;
+  if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess)
+    return fail(nullptr, HSB_ERR_DEVICE, "no HIP device available");
+  if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return fail(nullptr, HSB_ERR_DEVICE, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
+
+  hsbuild_s* h = new (std::nothrow) hsbuild_s();
+  if (!h) return fail(nullptr, HSB_ERR_ARG, "out of host memory");
+  if (hipHostMalloc((void**)&h->consts, sizeof(TypeConsts), hipHostMallocDefault) != hipSuccess) {
+    delete h;
+    return fail(nullptr, HSB_ERR_DEVICE, "pinned host allocation failed");
+  }
+  std::memset(h->consts, 0, sizeof(TypeConsts));
+  h->device = dev;
+  h->n_types = cfg->n_types;
+  h->n_atoms = cfg->n_atoms;
+  h->l_max = cfg->l_max;
+  h->n_l = n_l;
+  h->max_ng = cfg->max_ng;
+  h->precision = cfg->precision;
+  h->n_slices = cfg->n_slices;
+  std::memcpy(h->lattice, cfg->lattice, sizeof h->lattice);
+  for (int t = 0; t < cfg->n_types; ++t)
+    for (int l = 0; l <= cfg->l_max; ++l) {
+      for (int q = 0; q < 4; ++q) h->consts->radial[t][l][q] = cfg->radial[((size_t)t * (cfg->l_max + 1) + l) * 4 + q];
+      h->consts->udot2[t][l] = cfg->udot_norm2[(size_t)t * (cfg->l_max + 1) + l];
+    }
+  CellArgs& c = h->cell;
+  std::memset(&c, 0, sizeof c);
+  // b_j = 2 pi (A^{-1})^T rows: b_j[i] = 2 pi inv(A)[i][j]
+  const double inv[9] = {(A[4] * A[8] - A[5] * A[7]) / det, (A[2] * A[7] - A[1] * A[8]) / det,
+                         (A[1] * A[5] - A[2] * A[4]) / det, (A[5] * A[6] - A[3] * A[8]) / det,
+                         (A[0] * A[8] - A[2] * A[6]) / det, (A[2] * A[3] - A[0] * A[5]) / det,
+                         (A[3] * A[7] - A[4] * A[6]) / det, (A[1] * A[6] - A[0] * A[7]) / det,
+                         (A[0] * A[4] - A[1] * A[3]) / det};
+  const double two_pi = 6.283185307179586476925286766559;
+  for (int j = 0; j < 3; ++j)
+    for (int i = 0; i < 3; ++i) c.bvec[3 * j + i] = two_pi * inv[3 * i + j];
+  c.pre = 4.0 * 3.14159265358979323846264338327950 / std::sqrt(std::fabs(det));
+  c.n_types = cfg->n_types;
+  c.n_atoms = cfg->n_atoms;
+  c.l_max = cfg->l_max;
+  c.n_l = n_l;
+  for (int t = 0; t <= cfg->n_types; ++t) c.type_start[t] = type_start[t];
+  for (int t = 0; t < cfg->n_types; ++t) c.r_mt[t] = cfg->r_mt[t];
+  *out = h;
+  return HSB_OK;
+}
+
+void hsbuild_destroy(hsbuild_t h) {
+  if (!h) return;
+  destroy_events(h);
+  if (h->consts) (void)hipHostFree(h->consts);
+  delete h;
+}
+
+size_t hsbuild_workspace_bytes(hsbuild_t h, int32_t mode, int32_t n_k, const int32_t* ng) {
+  if (!h) return 0;
+  if (!ng || n_k < 1) {
+    fail(h, HSB_ERR_ARG, "ng must point to n_k >= 1 sizes");
+    return 0;
+  }
+  if (mode == HSB_MODE_FORWARD || mode == HSB_MODE_COEFFICIENTS) {
+    if (n_k != 1 || check_ng(h, ng[0])) return 0;
+    return make_layout(*h, ng[0], mode).end;
+  }
+  fail(h, HSB_ERR_UNSUPPORTED, "workspace mode %d is not available in this build", mode);
+  return 0;
+}
+
+int hsbuild_coefficients(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
+                         void* coef, void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return HSB_ERR_ARG;
+  h->err.clear();
+  if (!k_frac || !g || !tau || !coef) return fail(h, HSB_ERR_ARG, "null k_frac, g, tau or coef");
+  int rc = check_ng(h, ng);
+  if (rc) return rc;
+  const Layout L = make_layout(*h, ng, HSB_MODE_COEFFICIENTS);
+  if ((rc = check_ws(h, L, ws, ws_bytes))) return rc;
+  if ((rc = check_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  CellArgs c;
+  if ((rc = enqueue_tables(h, L, k_frac, g, (char*)ws, s, c))) return rc;
+  char* w = (char*)ws;
+  return launched(h, launch_assemble(c, L.n_pad, (const double2*)(w + L.ang), (const double2*)(w + L.ab),
+                                     (const double*)(w + L.kv), tau, (double2*)coef, ng, ng, s),
+                  "k_assemble");
+}
+
+int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
+                    const void* T, void* H, void* S, void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return HSB_ERR_ARG;
+  h->err.clear();
+  if (!k_frac || !g || !tau || !T || !H || !S) return fail(h, HSB_ERR_ARG, "null k_frac, g, tau, T, H or S");
+  if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
+  int rc = check_ng(h, ng);
+  if (rc) return rc;
+  if (h->precision != HSB_FP64)
+    return fail(h, HSB_ERR_UNSUPPORTED, "split-precision contraction is not available in this build");
+  const Layout L = make_layout(*h, ng, HSB_MODE_FORWARD);
+  if ((rc = check_ws(h, L, ws, ws_bytes))) return rc;
+  if ((rc = check_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  mark(h, 0, s);
+  if ((rc = enqueue_operands(h, L, k_frac, g, tau, T, w, s))) return rc;
+  rc = launched(h, launch_hs_fp64((const double2*)(w + L.W), (const double2*)(w + L.Y),
+                                  (const double*)(w + L.lam), L.K_pad, ng, L.n_pad, (double2*)H, (double2*)S, ng, s),
+                "k_hs_fp64");
+  mark(h, 3, s);
+  return rc;
+}
+
+int hsbuild_backward(hsbuild_t h, const double*, int32_t, const int32_t*, const double*, const void*, const void*,
+                     const void*, void*, double*, void*, size_t, void*) {
+  if (!h) return HSB_ERR_ARG;
+  return fail(h, HSB_ERR_UNSUPPORTED, "backward is not available in this build");
+}
+
+int hsbuild_batch(hsbuild_t h, int32_t, const double*, const int32_t*, const int32_t*, const int64_t*,
+                  const double*, const void*, void*, void*, void*, size_t, void*) {
+  if (!h) return HSB_ERR_ARG;
+  return fail(h, HSB_ERR_UNSUPPORTED, "batch is not available in this build");
+}
+
+int hsbuild_set_timing(hsbuild_t h, int32_t enable) {
+  if (!h) return HSB_ERR_ARG;
+  destroy_events(h);
+  if (!enable) return HSB_OK;
+  h->events.resize(4 * HSB_TIMING_CAPACITY);
+  for (size_t i = 0; i < h->events.size(); ++i) {
+    if (hipEventCreate(&h->events[i]) != hipSuccess) {
+      h->events.resize(i);
+      destroy_events(h);
+      return fail(h, HSB_ERR_DEVICE, "hipEventCreate failed");
+    }
+  }
+  return HSB_OK;
+}
+
+int hsbuild_stage_times(hsbuild_t h, double* ms_avg, int32_t* n_calls) {
+  if (!h || !ms_avg || !n_calls) return HSB_ERR_ARG;
+  if (h->events.empty()) return fail(h, HSB_ERR_ARG, "timing is not enabled");
+  double acc[3] = {0.0, 0.0, 0.0};
+  for (int c = 0; c < h->n_timed; ++c) {
+    if (hipEventSynchronize(h->events[4 * c + 3]) != hipSuccess)
+      return fail(h, HSB_ERR_DEVICE, "hipEventSynchronize failed");
+    for (int k = 0; k < 3; ++k) {
+      float ms = 0.0f;
+      if (hipEventElapsedTime(&ms, h->events[4 * c + k], h->events[4 * c + k + 1]) != hipSuccess)
+        return fail(h, HSB_ERR_DEVICE, "hipEventElapsedTime failed");
+      acc[k] += ms;
+    }
+  }
+  for (int k = 0; k < 3; ++k) ms_avg[k] = h->n_timed ? acc[k] / h->n_timed : 0.0;
+  *n_calls = h->n_timed;
+  return HSB_OK;
+}
+
+const char* hsbuild_last_error(hsbuild_t h) { return h ? h->err.c_str() : g_create_error.c_str(); }
+
+int hsbuild_host_bessel(int32_t lmax, double x, double* jl, double* djl) {
+  if (lmax < 0 || lmax > HSB_MAX_LMAX || !(x >= 0.0) || !jl || !djl) return HSB_ERR_ARG;
+  double j[kMaxL + 2];
+  sph_bessel_seq(lmax + 1, x, j);
+  sph_bessel_deriv(lmax, j, djl);
+  for (int l = 0; l <= lmax; ++l) jl[l] = j[l];
+  return HSB_OK;
+}
+
+int hsbuild_host_angular(int32_t lmax, const double kvec[3], double pre, void* out) {
+  if (lmax < 0 || lmax > HSB_MAX_LMAX || !kvec || !out) return HSB_ERR_ARG;
+  double* o = (double*)out;
+  angular_visit(lmax, kvec[0], kvec[1], kvec[2], pre, [&](int L, double re, double im) {
+    o[2 * L] = re;
+    o[2 * L + 1] = im;
+  });
+  return HSB_OK;
+}
+
+}  // extern "C"

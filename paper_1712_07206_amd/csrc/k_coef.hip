@@ -1,0 +1,163 @@
+// Matching coefficients of the LAPW basis (Eq. 2, matched in value and slope
+// at the muffin-tin radius, Sec. 2.1).
+//
+//   k_tables   : per G, K = B(G + k), |K|, the angular factor
+//                pre * i^l conj(Y_lm(K_hat)) for every L, and per type the
+//                radial matching pair (a_l, b_l).  Small and compute-light.
+//   k_assemble : the HBM-write-bound product
+//                W[atom][A|B][L][G] = e^{iK_G.tau_atom} * ang[L][G] * (a|b)_{t,l}(G),
+//                one thread per G (coalesced 16-byte stores along G), one
+//                workgroup row per atom so every atom re-reads ang from L2.
+//   k_lambda   : the overlap weight of each stacked row.
+#include "hs_internal.h"
+#include "special.h"
+
+namespace hsb {
+
+namespace {
+
+__device__ inline int atom_type_of(const CellArgs& c, int atom) {
+  int t = 0;
+  while (t + 1 < c.n_types && atom >= c.type_start[t + 1]) ++t;
+  return t;
+}
+
+__device__ inline void kvec_of(const CellArgs& c, const int32_t* g, int G, double& kx, double& ky, double& kz) {
+  const double n0 = g[3 * G + 0] + c.kfrac[0];
+  const double n1 = g[3 * G + 1] + c.kfrac[1];
+  const double n2 = g[3 * G + 2] + c.kfrac[2];
+  kx = n0 * c.bvec[0] + n1 * c.bvec[3] + n2 * c.bvec[6];
+  ky = n0 * c.bvec[1] + n1 * c.bvec[4] + n2 * c.bvec[7];
+  kz = n0 * c.bvec[2] + n1 * c.bvec[5] + n2 * c.bvec[8];
+}
+
+// blockIdx.y == 0: K vectors and angular factors; blockIdx.y == t+1: (a_l, b_l) of type t.
+__global__ void __launch_bounds__(64) k_tables(CellArgs c, const TypeConsts* __restrict__ consts, int n, int n_pad,
+                                               const int32_t* __restrict__ g, double2* __restrict__ ang,
+                                               double2* __restrict__ ab, double* __restrict__ kv) {
+  const int G = blockIdx.x * blockDim.x + threadIdx.x;
+  if (G >= n_pad) return;
+  const int part = blockIdx.y;
+  const bool valid = G < n;
+  double kx = 0.0, ky = 0.0, kz = 0.0;
+  if (valid) kvec_of(c, g, G, kx, ky, kz);
+  const double kn = sqrt(kx * kx + ky * ky + kz * kz);
+  if (part == 0) {
+    kv[4 * (int64_t)G + 0] = kx;
+    kv[4 * (int64_t)G + 1] = ky;
+    kv[4 * (int64_t)G + 2] = kz;
+    kv[4 * (int64_t)G + 3] = kn;
+    if (valid) {
+      angular_visit(c.l_max, kx, ky, kz, c.pre, [&](int L, double re, double im) {
+        ang[(int64_t)L * n_pad + G] = make_double2(re, im);
+      });
+    } else {
+      for (int L = 0; L < c.n_l; ++L) ang[(int64_t)L * n_pad + G] = make_double2(0.0, 0.0);
+    }
+    return;
+  }
+  const int t = part - 1;
+  double j[kMaxL + 2], dj[kMaxL + 1];
+  if (valid) {
+    sph_bessel_seq(c.l_max + 1, kn * c.r_mt[t], j);
+    sph_bessel_deriv(c.l_max, j, dj);
+  }
+  for (int l = 0; l <= c.l_max; ++l) {
+    double a = 0.0, b = 0.0;
+    if (valid) {
+      const double u = consts->radial[t][l][0], du = consts->radial[t][l][1];
+      const double ud = consts->radial[t][l][2], dud = consts->radial[t][l][3];
+      const double det = u * dud - ud * du;
+      const double val = j[l], slope = kn * dj[l];
+      a = (val * dud - ud * slope) / det;
+      b = (u * slope - du * val) / det;
+    }
+    ab[((int64_t)t * (c.l_max + 1) + l) * n_pad + G] = make_double2(a, b);
+  }
+}
+
+__global__ void __launch_bounds__(256) k_lambda(CellArgs c, const TypeConsts* __restrict__ consts, int K_pad,
+                                                double* __restrict__ lam) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K_pad) return;
+  const int rows = 2 * c.n_l;
+  const int atom = k / rows, r = k % rows;
+  double v = 0.0;
+  if (atom < c.n_atoms) {
+    if (r < c.n_l) {
+      v = 1.0;
+    } else {
+      const int L = r - c.n_l;
+      int l = 0;
+      while ((l + 1) * (l + 1) <= L) ++l;
+      v = consts->udot2[atom_type_of(c, atom)][l];
+    }
+  }
+  lam[k] = v;
+}
+
+// One thread per G, blockIdx.y = atom.  Stores are 16 B per lane, contiguous along G.
+__global__ void __launch_bounds__(256) k_assemble(CellArgs c, int n_pad, const double2* __restrict__ ang,
+                                                  const double2* __restrict__ ab, const double* __restrict__ kv,
+                                                  const double* __restrict__ tau, double2* __restrict__ out,
+                                                  int64_t ld, int n_store) {
+  const int G = blockIdx.x * blockDim.x + threadIdx.x;
+  const int atom = blockIdx.y;
+  if (G >= n_store) return;
+  const int t = atom_type_of(c, atom);
+  const double kx = kv[4 * (int64_t)G + 0], ky = kv[4 * (int64_t)G + 1], kz = kv[4 * (int64_t)G + 2];
+  const double arg = kx * tau[3 * atom + 0] + ky * tau[3 * atom + 1] + kz * tau[3 * atom + 2];
+  double ps, pc;
+  sincos(arg, &ps, &pc);
+  const int64_t rowA = (int64_t)atom * 2 * c.n_l;
+  const int64_t rowB = rowA + c.n_l;
+  const double2* abt = ab + (int64_t)t * (c.l_max + 1) * n_pad + G;
+  int L = 0;
+  for (int l = 0; l <= c.l_max; ++l) {
+    const double2 m = abt[(int64_t)l * n_pad];
+    // phase * (a|b): complex times real
+    const double par = pc * m.x, pai = ps * m.x;
+    const double pbr = pc * m.y, pbi = ps * m.y;
+    for (int mm = 0; mm < 2 * l + 1; ++mm, ++L) {
+      const double2 y = ang[(int64_t)L * n_pad + G];
+      out[(rowA + L) * ld + G] = make_double2(par * y.x - pai * y.y, par * y.y + pai * y.x);
+      out[(rowB + L) * ld + G] = make_double2(pbr * y.x - pbi * y.y, pbr * y.y + pbi * y.x);
+    }
+  }
+}
+
+__global__ void __launch_bounds__(256) k_zero_rows(double2* __restrict__ a, int64_t ld, int row0, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= count) return;
+  a[(int64_t)row0 * ld + i] = make_double2(0.0, 0.0);
+}
+
+}  // namespace
+
+hipError_t launch_tables(const CellArgs& c, const TypeConsts* consts, int n, int n_pad, const int32_t* g,
+                         double2* ang, double2* ab, double* kv, hipStream_t s) {
+  dim3 grid((n_pad + 63) / 64, 1 + c.n_types);
+  hipLaunchKernelGGL(k_tables, grid, dim3(64), 0, s, c, consts, n, n_pad, g, ang, ab, kv);
+  return hipGetLastError();
+}
+
+hipError_t launch_lambda(const CellArgs& c, const TypeConsts* consts, int K_pad, double* lam, hipStream_t s) {
+  hipLaunchKernelGGL(k_lambda, dim3((K_pad + 255) / 256), dim3(256), 0, s, c, consts, K_pad, lam);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble(const CellArgs& c, int n_pad, const double2* ang, const double2* ab, const double* kv,
+                           const double* tau, double2* out, int64_t ld, int n_store, hipStream_t s) {
+  dim3 grid((n_store + 255) / 256, c.n_atoms);
+  hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, c, n_pad, ang, ab, kv, tau, out, ld, n_store);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_rows(double2* a, int64_t ld, int row0, int row1, hipStream_t s) {
+  if (row1 <= row0) return hipSuccess;
+  const int64_t count = (int64_t)(row1 - row0) * ld;
+  hipLaunchKernelGGL(k_zero_rows, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, a, ld, row0, count);
+  return hipGetLastError();
+}
+
+}  // namespace hsb

@@ -1,0 +1,200 @@
+// Fused Hermitian contractions (Eqs. 6-7 after stacking, Sec. 3 / Fig. 1):
+//
+//   S[G'][G] = sum_k conj(W[k][G']) lam[k] W[k][G]     (herk, one triangle)
+//   H[G'][G] = sum_k conj(W[k][G']) Y[k][G]            (herkx, one triangle)
+//
+// over the stacked index k = (atom, A|B, L) of width 2 N_atoms N_L.  The
+// paper's refined algorithm (Alg. 3) gets H from zher2k + zherkx over the
+// A and B halves separately (12 N_A N_L N_G^2 flops); with Y = T W already
+// formed per atom, one herkx over the full stacked width gives the same H in
+// 8 N_A N_L N_G^2, and S shares its left operand W.
+//
+// Complex FP64 on v_mfma_f64_16x16x4f64 (four real MFMAs per complex MAC):
+//   Re += Wr^T Yr + Wi^T Yi,  Im += Wr^T Yi - Wi^T Yr.
+// Workgroup: 256 threads = 4 waves, output tile 128 (G') x 64 (G) for both H
+// and S; each wave owns 64 x 32 of each (4 x 2 MFMA blocks, 16 accumulators
+// of 4 doubles per matrix).  K is staged 16 rows at a time through
+// double-buffered LDS with a register prefetch of the next chunk.  Only tiles
+// that touch the upper triangle are launched; they are numbered row-major
+// over 128 x 128 super-tiles and the numbering is dealt to the eight XCDs in
+// contiguous ranges so tiles sharing a row strip share an L2.
+#include "hs_internal.h"
+
+namespace hsb {
+
+namespace {
+
+typedef double d4 __attribute__((ext_vector_type(4)));
+typedef double d2 __attribute__((ext_vector_type(2)));
+
+constexpr int BM = 128, BN = 64, BK = 16, NTHR = 256;
+constexpr int kXcds = 8;
+
+// Workgroup id -> position in a numbering where each XCD (dispatch is
+// round-robin over XCDs) owns one contiguous range.
+__device__ inline int xcd_remap(int w, int num) {
+  const int xcd = w % kXcds, local = w / kXcds;
+  const int per = num / kXcds, rem = num % kXcds;
+  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+}
+
+// s -> (bi, bj), bj >= bi, row-major over the upper triangle of an nb x nb grid.
+__device__ inline void tri_decode(int s, int nb, int& bi, int& bj) {
+  const double b = 2.0 * nb + 1.0;
+  int i = (int)((b - sqrt(b * b - 8.0 * s)) * 0.5);
+  if (i < 0) i = 0;
+  if (i > nb - 1) i = nb - 1;
+  auto start = [nb](int r) { return r * nb - r * (r - 1) / 2; };
+  while (i > 0 && start(i) > s) --i;
+  while (i + 1 < nb && start(i + 1) <= s) ++i;
+  bi = i;
+  bj = i + (s - start(i));
+}
+
+#define MFMA(a, b, c) __builtin_amdgcn_mfma_f64_16x16x4f64((a), (b), (c), 0, 0, 0)
+
+__global__ void __launch_bounds__(NTHR, 1) k_hs_fp64(const d2* __restrict__ W, const d2* __restrict__ Y,
+                                                     const double* __restrict__ lam, int K_pad, int n, int n_pad,
+                                                     int nbr, int num_wg, double2* __restrict__ H,
+                                                     double2* __restrict__ S, int64_t ldh) {
+  __shared__ d2 sL[2][BK][BM];
+  __shared__ d2 sR[2][BK][BN];
+  __shared__ d2 sY[2][BK][BN];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;
+  const int w = xcd_remap(blockIdx.x, num_wg);
+  int bi, sj;
+  tri_decode(w >> 1, nbr, bi, sj);
+  const int row0 = bi * BM, col0 = sj * BM + (w & 1) * BN;
+  if (col0 >= n) return;
+
+  // staging map: left chunk 16 x 128 (8 per thread), right chunks 16 x 64 (4 per thread)
+  d2 pl[8], pr[4], py[4];
+  double pm[4];
+#define HS_GLOAD(kc)                                                             \
+  do {                                                                           \
+    _Pragma("unroll") for (int i = 0; i < 8; ++i) {                              \
+      const int e = tid + NTHR * i;                                              \
+      pl[i] = W[(int64_t)((kc) + (e >> 7)) * n_pad + row0 + (e & 127)];          \
+    }                                                                            \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                              \
+      const int e = tid + NTHR * i;                                              \
+      const int64_t off = (int64_t)((kc) + (e >> 6)) * n_pad + col0 + (e & 63);  \
+      pr[i] = W[off];                                                            \
+      py[i] = Y[off];                                                            \
+      pm[i] = lam[(kc) + (e >> 6)];                                              \
+    }                                                                            \
+  } while (0)
+#define HS_LSTORE(b)                                                                \
+  do {                                                                              \
+    _Pragma("unroll") for (int i = 0; i < 8; ++i) {                                 \
+      const int e = tid + NTHR * i;                                                 \
+      sL[b][e >> 7][e & 127] = pl[i];                                               \
+    }                                                                               \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                 \
+      const int e = tid + NTHR * i;                                                 \
+      sR[b][e >> 6][e & 63] = pm[i] * pr[i];                                         \
+      sY[b][e >> 6][e & 63] = py[i];                                                \
+    }                                                                               \
+  } while (0)
+
+  d4 hr[4][2], hi[4][2], sr[4][2], si[4][2];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      hr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      hi[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      sr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+      si[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+    }
+
+  const int nchunks = K_pad / BK;
+  HS_GLOAD(0);
+  HS_LSTORE(0);
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int b = c & 1;
+    if (c + 1 < nchunks) HS_GLOAD((c + 1) * BK);
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      double ar[4], ai[4], an[4], yre[2], yim[2], wre[2], wim[2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const d2 a = sL[b][kk][wr * 64 + i * 16 + (lane & 15)];
+        ar[i] = a.x; ai[i] = a.y; an[i] = -a.y;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const d2 yv = sY[b][kk][wc * 32 + j * 16 + (lane & 15)];
+        const d2 wv = sR[b][kk][wc * 32 + j * 16 + (lane & 15)];
+        yre[j] = yv.x; yim[j] = yv.y; wre[j] = wv.x; wim[j] = wv.y;
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) hr[i][j] = MFMA(ar[i], yre[j], hr[i][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) hi[i][j] = MFMA(ar[i], yim[j], hi[i][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) sr[i][j] = MFMA(ar[i], wre[j], sr[i][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) si[i][j] = MFMA(ar[i], wim[j], si[i][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) hr[i][j] = MFMA(ai[i], yim[j], hr[i][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) hi[i][j] = MFMA(an[i], yre[j], hi[i][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) sr[i][j] = MFMA(ai[i], wim[j], sr[i][j]);
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) si[i][j] = MFMA(an[i], wre[j], si[i][j]);
+    }
+    if (c + 1 < nchunks) HS_LSTORE(b ^ 1);
+    __syncthreads();
+  }
+
+  // D layout of the 16x16 f64 MFMA: lane l, element q -> row l/16 + 4q, column l%16
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = row0 + wr * 64 + i * 16 + (lane >> 4) + 4 * q;
+        const int col = col0 + wc * 32 + j * 16 + (lane & 15);
+        if (row < n && col < n && col >= row) {
+          const int64_t o = (int64_t)row * ldh + col;
+          H[o] = make_double2(hr[i][j][q], hi[i][j][q]);
+          S[o] = make_double2(sr[i][j][q], si[i][j][q]);
+        }
+      }
+}
+
+}  // namespace
+
+hipError_t launch_hs_fp64(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
+                          double2* H, double2* S, int64_t ldh, hipStream_t s) {
+  const int nbr = n_pad / BM;
+  const int num_wg = nbr * (nbr + 1);  // two 128 x 64 tiles per upper-triangle 128 x 128 super-tile
+  hipLaunchKernelGGL(k_hs_fp64, dim3(num_wg), dim3(NTHR), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad, n, n_pad,
+                     nbr, num_wg, H, S, ldh);
+  return hipGetLastError();
+}
+
+}  // namespace hsb

@@ -1,0 +1,175 @@
+"""PyTorch-facing wrapper of the hsbuild C-ABI.
+
+Only marshalling happens here: tensors are checked for dtype, device and
+contiguity, the workspace is a uint8 CUDA tensor, and the library is called
+on torch's current stream.  Every step of the computation runs in the HIP
+library.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _native as N
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t: torch.Tensor, dtype, name: str, shape=None) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("%s must be a torch tensor" % name)
+    if t.device.type != "cuda":
+        raise ValueError("%s must be a CUDA (HIP) tensor" % name)
+    if t.dtype != dtype:
+        raise TypeError("%s must be %s (got %s)" % (name, dtype, t.dtype))
+    if shape is not None and tuple(t.shape) != tuple(shape):
+        raise ValueError("%s must have shape %s (got %s)" % (name, tuple(shape), tuple(t.shape)))
+    return t.contiguous()
+
+
+class HSBuilder:
+    """One cell (lattice, atom types, radii, radial boundary values) bound to
+    the current HIP device.  Inputs per call: k (fractional), the G list,
+    atom positions tau and the per-type T blocks."""
+
+    def __init__(self, lattice, atom_type, r_mt, radial, udot_norm2, l_max: int, max_ng: int,
+                 precision: int = N.HSB_FP64, n_slices: int = 0):
+        self._atom_type = np.ascontiguousarray(atom_type, dtype=np.int32)
+        self._r_mt = np.ascontiguousarray(r_mt, dtype=np.float64)
+        self._radial = np.ascontiguousarray(radial, dtype=np.float64)
+        self._udot = np.ascontiguousarray(udot_norm2, dtype=np.float64)
+        lat = np.ascontiguousarray(lattice, dtype=np.float64).reshape(9)
+        self.n_types = int(self._r_mt.shape[0])
+        self.n_atoms = int(self._atom_type.shape[0])
+        self.l_max = int(l_max)
+        self.n_l = (self.l_max + 1) ** 2
+        self.max_ng = int(max_ng)
+        cfg = N.HsbConfig()
+        cfg.n_types = self.n_types
+        cfg.n_atoms = self.n_atoms
+        cfg.l_max = self.l_max
+        cfg.max_ng = self.max_ng
+        for i in range(9):
+            cfg.lattice[i] = float(lat[i])
+        cfg.atom_type = self._atom_type.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        cfg.r_mt = self._r_mt.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        cfg.radial = self._radial.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        cfg.udot_norm2 = self._udot.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+        cfg.precision = int(precision)
+        cfg.n_slices = int(n_slices)
+        handle = ctypes.c_void_p()
+        code = N.lib().hsbuild_create(ctypes.byref(cfg), ctypes.byref(handle))
+        if code != N.HSB_OK:
+            raise N.HSBuildError(code, N.last_error(None))
+        self._h = handle
+        self._ws: Optional[torch.Tensor] = None
+
+    @classmethod
+    def from_case(cls, case: dict, max_ng: Optional[int] = None, precision: int = N.HSB_FP64,
+                  n_slices: int = 0) -> "HSBuilder":
+        if max_ng is None:
+            ng = case["n_g"]
+            max_ng = int(np.max(ng))
+        return cls(case["lattice"], case["atom_type"], case["r_mt"], case["radial"], case["udot_norm2"],
+                   case["l_max"], max_ng, precision, n_slices)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            N.lib().hsbuild_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # -- workspace -------------------------------------------------------------------
+    def workspace_bytes(self, mode: int, ng: Sequence[int]) -> int:
+        arr = (ctypes.c_int32 * len(ng))(*[int(x) for x in ng])
+        nbytes = N.lib().hsbuild_workspace_bytes(self._h, int(mode), len(ng), arr)
+        if nbytes == 0:
+            raise N.HSBuildError(N.HSB_ERR_ARG, N.last_error(self._h))
+        return int(nbytes)
+
+    def workspace(self, mode: int, ng: Sequence[int]) -> torch.Tensor:
+        need = self.workspace_bytes(mode, ng)
+        if self._ws is None or self._ws.numel() < need:
+            self._ws = None
+            self._ws = torch.empty(need, dtype=torch.uint8, device="cuda")
+        return self._ws
+
+    # -- entry points ------------------------------------------------------------------
+    def coefficients(self, k_frac, g: torch.Tensor, tau: torch.Tensor, out: Optional[torch.Tensor] = None):
+        ng = int(g.shape[0])
+        g = _dev(g, torch.int32, "g", (ng, 3))
+        tau = _dev(tau, torch.float64, "tau", (self.n_atoms, 3))
+        shape = (self.n_atoms, 2, self.n_l, ng)
+        if out is None:
+            out = torch.empty(shape, dtype=torch.complex128, device="cuda")
+        out = _dev(out, torch.complex128, "out", shape)
+        ws = self.workspace(N.HSB_MODE_COEFFICIENTS, [ng])
+        kf = (ctypes.c_double * 3)(*[float(x) for x in k_frac])
+        N.check(N.lib().hsbuild_coefficients(self._h, kf, ng, _ptr(g), _ptr(tau), _ptr(out), _ptr(ws),
+                                             ws.numel(), _stream()), self._h)
+        return out
+
+    def forward(self, k_frac, g: torch.Tensor, tau: torch.Tensor, T: torch.Tensor,
+                H: Optional[torch.Tensor] = None, S: Optional[torch.Tensor] = None, ws: Optional[torch.Tensor] = None):
+        """Upper triangles of H and S (column >= row); the strict lower
+        triangle of caller-supplied H, S is left as it was."""
+        ng = int(g.shape[0])
+        g = _dev(g, torch.int32, "g", (ng, 3))
+        tau = _dev(tau, torch.float64, "tau", (self.n_atoms, 3))
+        T = _dev(T, torch.complex128, "T", (self.n_types, 2 * self.n_l, 2 * self.n_l))
+        if H is None:
+            H = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+        if S is None:
+            S = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+        H = _dev(H, torch.complex128, "H", (ng, ng))
+        S = _dev(S, torch.complex128, "S", (ng, ng))
+        if ws is None:
+            ws = self.workspace(N.HSB_MODE_FORWARD, [ng])
+        kf = (ctypes.c_double * 3)(*[float(x) for x in k_frac])
+        N.check(N.lib().hsbuild_forward(self._h, kf, ng, _ptr(g), _ptr(tau), _ptr(T), _ptr(H), _ptr(S),
+                                        _ptr(ws), ws.numel(), _stream()), self._h)
+        return H, S
+
+    def set_timing(self, enable: bool) -> None:
+        N.check(N.lib().hsbuild_set_timing(self._h, 1 if enable else 0), self._h)
+
+    def stage_times(self):
+        """(average ms of [coefficients, T products, contraction], recorded calls)."""
+        ms = (ctypes.c_double * 3)()
+        n = ctypes.c_int32()
+        N.check(N.lib().hsbuild_stage_times(self._h, ms, ctypes.byref(n)), self._h)
+        return [ms[0], ms[1], ms[2]], int(n.value)
+
+    def forward_raw(self, k_frac, ng: int, g, tau, T, H, S, ws, ws_bytes: int) -> int:
+        """Direct call with pointers already validated by the caller (timing loops)."""
+        kf = (ctypes.c_double * 3)(*[float(x) for x in k_frac])
+        return N.lib().hsbuild_forward(self._h, kf, ng, _ptr(g), _ptr(tau), _ptr(T), _ptr(H), _ptr(S),
+                                       _ptr(ws), ws_bytes, _stream())
+
+
+def hermitian_full(upper: torch.Tensor) -> torch.Tensor:
+    """Full Hermitian matrix from its upper triangle (test and reporting helper)."""
+    up = torch.triu(upper)
+    return up + torch.triu(upper, 1).conj().transpose(-2, -1)
+
+
+def case_tensors(case: dict, device="cuda"):
+    """Device tensors of a generator case: g, tau, T."""
+    g = torch.as_tensor(np.ascontiguousarray(case["g"], dtype=np.int32), device=device)
+    tau = torch.as_tensor(np.ascontiguousarray(case["tau"]), device=device)
+    T = torch.as_tensor(np.ascontiguousarray(case["T"]), device=device)
+    return g, tau, T

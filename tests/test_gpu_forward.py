@@ -1,0 +1,164 @@
+"""GPU parity of the FP64 path against the oracle, through the C-ABI.
+
+Tolerances: relative Frobenius error <= 1e-12 for H and for S separately
+(over the full matrices rebuilt from the written upper triangles), and
+<= 1e-13 (max-abs relative) for the matching coefficients.
+"""
+import numpy as np
+import pytest
+import torch
+
+from flapw_cells import make_case
+from oracle import hs_oracle as o
+
+pytestmark = pytest.mark.gpu
+
+TOL_HS = 1e-12
+TOL_COEF = 1e-13
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    from paper_1712_07206_amd import _native
+    _native.lib()
+    yield
+
+
+def _hs_gpu(case, poison=True, max_ng=None):
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    n = case["n_g"]
+    b = HSBuilder.from_case(case, max_ng=max_ng)
+    g, tau, T = case_tensors(case)
+    fill = complex(float("nan"), float("nan")) if poison else 0.0
+    H = torch.full((n, n), fill, dtype=torch.complex128, device="cuda")
+    S = H.clone()
+    b.forward(case["k_frac"], g, tau, T, H, S)
+    torch.cuda.synchronize()
+    return H.cpu().numpy(), S.cpu().numpy()
+
+
+def _check_triangle(M):
+    n = M.shape[0]
+    iu = np.triu_indices(n)
+    il = np.tril_indices(n, -1)
+    assert np.all(np.isfinite(M[iu])), "upper triangle not fully written"
+    assert np.all(np.isnan(M[il])), "strict lower triangle was written"
+
+
+def _full(M):
+    up = np.triu(M)
+    return up + np.triu(M, 1).conj().T
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+_oracle_cache = {}
+
+
+def oracle_hs(idx, n_g=None):
+    key = (idx, n_g)
+    if key not in _oracle_cache:
+        case = make_case(idx, n_g=n_g)
+        _oracle_cache[key] = (case, o.hs(case))
+    return _oracle_cache[key]
+
+
+@pytest.mark.parametrize("idx,n_g", [(0, None), (1, 1000), (2, 300)])
+def test_coefficients_match_oracle(idx, n_g):
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    case = make_case(idx, n_g=n_g)
+    b = HSBuilder.from_case(case)
+    g, tau, T = case_tensors(case)
+    got = b.coefficients(case["k_frac"], g, tau).cpu().numpy()
+    ref = o.coefficients(case)
+    err = np.abs(got - ref).max() / np.abs(ref).max()
+    print("coef rel max err", idx, n_g, err)
+    assert err <= TOL_COEF
+
+
+@pytest.mark.parametrize("idx,n_g", [(0, None), (1, None), (1, 1), (1, 7), (1, 129), (1, 1000), (2, 3000), (4, 800)])
+def test_forward_matches_oracle(idx, n_g):
+    case, (Hr, Sr) = oracle_hs(idx, n_g)
+    H, S = _hs_gpu(case)
+    _check_triangle(H)
+    _check_triangle(S)
+    eh, es = rel(_full(H), Hr), rel(_full(S), Sr)
+    print("forward rel err", idx, case["n_g"], eh, es)
+    assert eh <= TOL_HS and es <= TOL_HS
+
+
+def test_forward_deterministic():
+    case = make_case(1, n_g=700)
+    H1, S1 = _hs_gpu(case)
+    H2, S2 = _hs_gpu(case)
+    iu = np.triu_indices(700)
+    assert np.array_equal(H1[iu], H2[iu]) and np.array_equal(S1[iu], S2[iu])
+
+
+def test_full_size_sampled_entries():
+    """The full-size workload (128 atoms, N_L = 121, N_G = 12000) in the launch
+    configuration the benchmark times, checked on sampled entries."""
+    case = make_case(2)
+    n = case["n_g"]
+    H, S = _hs_gpu(case, poison=False)
+    rng = np.random.default_rng(12)
+    rows = rng.integers(0, n, 160)
+    cols = rng.integers(0, n, 160)
+    rows, cols = np.minimum(rows, cols), np.maximum(rows, cols)
+    extra_r = np.array([0, 0, n - 1, n - 128, n - 129, 5000, 127, 128])
+    extra_c = np.array([0, n - 1, n - 1, n - 1, n - 120, 5000, 128, 128])
+    rows = np.concatenate([rows, extra_r])
+    cols = np.concatenate([cols, extra_c])
+    h_ref, s_ref = o.hs_entries(case, rows, cols)
+    scale_h = np.abs(h_ref).max()
+    scale_s = np.abs(s_ref).max()
+    eh = np.abs(H[rows, cols] - h_ref).max() / scale_h
+    es = np.abs(S[rows, cols] - s_ref).max() / scale_s
+    print("full-size sampled max err (rel to max |entry|)", eh, es)
+    assert eh <= TOL_HS and es <= TOL_HS
+    # Hermitian diagonal: real, and S's positive
+    d = np.arange(0, n, 37)
+    assert np.abs(H[d, d].imag).max() <= 1e-12 * np.abs(H[d, d]).max()
+    assert S[d, d].real.min() > 0
+    il = (rows > cols)
+    assert not np.any(il)
+
+
+def test_device_error_paths_leave_outputs_untouched():
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    case = make_case(0)
+    n = case["n_g"]
+    b = HSBuilder.from_case(case, max_ng=n)
+    g, tau, T = case_tensors(case)
+    H = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+    S = torch.zeros((n, n), dtype=torch.complex128, device="cuda")
+    need = b.workspace_bytes(N.HSB_MODE_FORWARD, [n])
+    ws = torch.empty(need + 512, dtype=torch.uint8, device="cuda")
+    code = b.forward_raw(case["k_frac"], n, g, tau, T, H, S, ws, need - 1)
+    assert code == N.HSB_ERR_WORKSPACE
+    code = b.forward_raw(case["k_frac"], n + 1, g, tau, T, H, S, ws, need)
+    assert code == N.HSB_ERR_SHAPE
+    code = b.forward_raw(case["k_frac"], n, g, tau, T, H, S, ws[8:], need)
+    assert code == N.HSB_ERR_ARG
+    code = b.forward_raw(case["k_frac"], n, g, tau, T, H, H, ws, need)
+    assert code == N.HSB_ERR_ARG
+    torch.cuda.synchronize()
+    assert torch.count_nonzero(H).item() == 0 and torch.count_nonzero(S).item() == 0
+
+
+def test_stage_timing_records_calls():
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    case = make_case(1, n_g=500)
+    b = HSBuilder.from_case(case)
+    g, tau, T = case_tensors(case)
+    b.set_timing(True)
+    for _ in range(3):
+        b.forward(case["k_frac"], g, tau, T)
+    ms, calls = b.stage_times()
+    assert calls == 3 and all(m > 0 for m in ms)
+    b.set_timing(False)
