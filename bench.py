@@ -52,7 +52,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2, help="workload index (default: the full-size cell)")
     ap.add_argument("--ng", type=int, default=None, help="override the basis size")
-    ap.add_argument("--cpu-ng", type=int, default=3000, help="basis size of the oracle sample")
+    ap.add_argument("--cpu-ng", type=int, default=5400, help="basis size of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
