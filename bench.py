@@ -45,6 +45,21 @@ def cpu_baseline(index: int, n_g: int) -> dict:
                       "(F=%.3g TFLOP, %.1f s)" % (n_g, flops / 1e12, dt)}
 
 
+def recorded_traffic(workload: str):
+    """HBM bytes per launch of the contraction kernel from the committed
+    rocprofv3 PMC record, only if the kernel source is the one profiled."""
+    import hashlib
+    root = os.path.dirname(os.path.abspath(__file__))
+    try:
+        rec = json.load(open(os.path.join(root, "profiles", "k_hs_fp64_traffic.json")))
+        src = open(os.path.join(root, rec["source"]), "rb").read()
+    except (OSError, ValueError, KeyError):
+        return None
+    if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16") or rec.get("workload") != workload:
+        return None
+    return rec["traffic_bytes"]
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,6 +69,8 @@ def main() -> int:
     ap.add_argument("--ng", type=int, default=None, help="override the basis size")
     ap.add_argument("--cpu-ng", type=int, default=5400, help="basis size of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="first run one plain device-to-device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (the H/S tiles would be "
@@ -69,6 +86,15 @@ def main() -> int:
     if not torch.cuda.is_available():
         log("no HIP device")
         return 1
+    if args.copy_probe_mib > 0:
+        nbytes = args.copy_probe_mib << 20
+        src = torch.ones(nbytes, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy probe: %d MiB device-to-device" % args.copy_probe_mib)
+        del src, dst
     case = make_case(args.config, n_g=args.ng)
     n, n_at, n_l = case["n_g"], case["n_atoms"], case["n_l"]
     k_c = n_at * n_l
@@ -134,7 +160,8 @@ def main() -> int:
                       "hs_contraction": round(stage_ms[2], 4)},
         "roofline": {"kernel": "k_hs_fp64", "bound": "mfma", "achieved": round(hs_tflops, 4),
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
-                     "frac": round(hs_tflops / FP64_MFMA_PEAK_TFLOPS, 4), "traffic": None,
+                     "frac": round(hs_tflops / FP64_MFMA_PEAK_TFLOPS, 4),
+                     "traffic": recorded_traffic(case["name"]),
                      "algorithmic_flops_per_launch": flops_hs},
         "split_speedup": None,
     }

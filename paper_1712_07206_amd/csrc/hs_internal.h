@@ -40,7 +40,15 @@ struct TypeConsts {
 //   lam : S weight of row k (1 for A rows, ||udot_l||^2 for B rows, 0 for pad)
 struct Layout {
   int n = 0, n_pad = 0, K = 0, K_pad = 0;
-  size_t W = 0, Y = 0, ang = 0, ab = 0, kv = 0, lam = 0, consts = 0, extra = 0, end = 0;
+  size_t W = 0, Y = 0, ang = 0, ab = 0, kv = 0, lam = 0, consts = 0, end = 0;
+  size_t PH = 0, PS = 0, partT = 0, partTau = 0;  // backward only
+};
+
+// Per-k-point entry of the batched contraction's tile list (device copy in the workspace).
+struct BatchMeta {
+  int64_t w_off, y_off;  // W_k and Y_k, in complex elements from the workspace base
+  int64_t out_off;       // H_k, S_k, in complex elements from the output bases (ld = n)
+  int n, n_pad, nbr, tile_start;
 };
 
 // ---- kernel launchers (each returns hipGetLastError() after enqueue) ----
@@ -61,5 +69,24 @@ hipError_t launch_tprod(const CellArgs& c, const double2* T, const double2* W, d
 // Upper triangles of H = W^H Y and S = W^H diag(lam) W over K_pad rows.
 hipError_t launch_hs_fp64(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
                           double2* H, double2* S, int64_t ldh, hipStream_t s);
+
+// Number of 128 x 64 tiles the contraction covers for a padded basis size.
+int hs_tiles(int n_pad);
+// Persistent contraction over the tiles of every k-point in meta (grid: a multiple of 8).
+hipError_t launch_hs_fp64_batch(const double2* ws, const double* lam, int K_pad, const BatchMeta* meta, int n_k,
+                                int total, int grid, double2* H, double2* S, hipStream_t s);
+
+// ---- adjoint ----
+int gradtau_blocks(int n);
+// P_H = W gH and P_S = W gS ([K_pad][n_pad]); gH, gS are [n][n].
+hipError_t launch_pgemm(const double2* W, const double2* gH, const double2* gS, int K_pad, int n, int n_pad,
+                        double2* PH, double2* PS, hipStream_t s);
+// gT[t] = sum over atoms of type t of P_H,a W_a^H (part: [n_atoms][2N_L][2N_L] scratch).
+hipError_t launch_gradT(const CellArgs& c, const double2* PH, const double2* W, int n_pad, double2* part,
+                        double2* gT, hipStream_t s);
+// gtau[a] = -2 sum_G K_G Im c_a(G) (part: [n_atoms][gradtau_blocks(n)][3] scratch).
+hipError_t launch_gradtau(const CellArgs& c, const double2* PH, const double2* PS, const double2* Y,
+                          const double2* W, const double* lam, const double* kv, int n, int n_pad, double* part,
+                          double* gtau, hipStream_t s);
 
 }  // namespace hsb

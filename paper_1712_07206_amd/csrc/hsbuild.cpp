@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <algorithm>
 #include <cstring>
 #include <new>
 #include <string>
@@ -28,6 +29,16 @@ struct hsbuild_s {
   // stage timing (hsbuild_set_timing)
   std::vector<hipEvent_t> events;  // 4 per recorded call
   int n_timed = 0;
+  bool capturing = false;  // no timing events inside a graph capture
+  // batch: persistent-kernel grid, captured graph and the arguments it was captured for
+  int num_cus = 0;
+  hipStream_t cap_stream = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
+  hipEvent_t graph_done = nullptr;
+  BatchMeta* meta_host = nullptr;  // pinned, source of the graph's metadata upload
+  int meta_cap = 0;
+  std::vector<double> key_f;
+  std::vector<int64_t> key_i;
 };
 
 namespace {
@@ -70,6 +81,13 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
     L.W = take((size_t)L.K_pad * np * sizeof(double2));
     L.Y = take((size_t)L.K_pad * np * sizeof(double2));
   }
+  if (mode == HSB_MODE_BACKWARD) {
+    const size_t M = 2 * (size_t)h.n_l;
+    L.PH = take((size_t)L.K_pad * np * sizeof(double2));
+    L.PS = take((size_t)L.K_pad * np * sizeof(double2));
+    L.partT = take((size_t)h.n_atoms * M * M * sizeof(double2));
+    L.partTau = take((size_t)h.n_atoms * gradtau_blocks(ng) * 3 * sizeof(double));
+  }
   L.end = off;
   return L;
 }
@@ -103,7 +121,7 @@ int launched(hsbuild_t h, hipError_t e, const char* what) {
 
 // Records stage boundary `idx` (0..3) of the current call when timing is on.
 void mark(hsbuild_t h, int idx, hipStream_t s) {
-  if (h->events.empty() || h->n_timed >= HSB_TIMING_CAPACITY) return;
+  if (h->capturing || h->events.empty() || h->n_timed >= HSB_TIMING_CAPACITY) return;
   (void)hipEventRecord(h->events[4 * h->n_timed + idx], s);
   if (idx == 3) ++h->n_timed;
 }
@@ -150,6 +168,52 @@ int enqueue_operands(hsbuild_t h, const Layout& L, const double k_frac[3], const
   rc = launched(h, launch_tprod(c, (const double2*)T, W, Y, L.n_pad, s), "k_tprod");
   mark(h, 2, s);
   return rc;
+}
+
+struct BatchLayout {
+  int K = 0, K_pad = 0, max_n_pad = 0;
+  size_t consts = 0, lam = 0, kv = 0, ang = 0, ab = 0, meta = 0, end = 0;
+  std::vector<size_t> W, Y;
+  std::vector<int> n_pad;
+};
+
+BatchLayout make_batch_layout(const hsbuild_s& h, int n_k, const int32_t* ng) {
+  BatchLayout B;
+  B.K = 2 * h.n_atoms * h.n_l;
+  B.K_pad = (int)round_up(B.K, kTileK);
+  for (int k = 0; k < n_k; ++k) {
+    B.n_pad.push_back((int)round_up(ng[k], kTileN));
+    B.max_n_pad = std::max(B.max_n_pad, B.n_pad.back());
+  }
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + bytes);
+    return o;
+  };
+  const size_t np = (size_t)B.max_n_pad;
+  B.consts = take(sizeof(TypeConsts));
+  B.lam = take((size_t)B.K_pad * sizeof(double));
+  B.kv = take(np * 4 * sizeof(double));
+  B.ang = take((size_t)h.n_l * np * sizeof(double2));
+  B.ab = take((size_t)h.n_types * (h.l_max + 1) * np * sizeof(double2));
+  B.meta = take((size_t)n_k * sizeof(BatchMeta));
+  for (int k = 0; k < n_k; ++k) {
+    B.W.push_back(take((size_t)B.K_pad * B.n_pad[k] * sizeof(double2)));
+    B.Y.push_back(take((size_t)B.K_pad * B.n_pad[k] * sizeof(double2)));
+  }
+  B.end = off;
+  return B;
+}
+
+void drop_graph(hsbuild_t h) {
+  if (h->graph_exec) {
+    if (h->graph_done) (void)hipEventSynchronize(h->graph_done);
+    (void)hipGraphExecDestroy(h->graph_exec);
+    h->graph_exec = nullptr;
+  }
+  h->key_f.clear();
+  h->key_i.clear();
 }
 
 }  // namespace
@@ -228,6 +292,7 @@ int hsbuild_create(const hsb_config* cfg, hsbuild_t* out) {
   }
   std::memset(h->consts, 0, sizeof(TypeConsts));
   h->device = dev;
+  h->num_cus = prop.multiProcessorCount;
   h->n_types = cfg->n_types;
   h->n_atoms = cfg->n_atoms;
   h->l_max = cfg->l_max;
@@ -266,6 +331,10 @@ int hsbuild_create(const hsb_config* cfg, hsbuild_t* out) {
 void hsbuild_destroy(hsbuild_t h) {
   if (!h) return;
   destroy_events(h);
+  drop_graph(h);
+  if (h->graph_done) (void)hipEventDestroy(h->graph_done);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  if (h->meta_host) (void)hipHostFree(h->meta_host);
   if (h->consts) (void)hipHostFree(h->consts);
   delete h;
 }
@@ -276,11 +345,16 @@ size_t hsbuild_workspace_bytes(hsbuild_t h, int32_t mode, int32_t n_k, const int
     fail(h, HSB_ERR_ARG, "ng must point to n_k >= 1 sizes");
     return 0;
   }
-  if (mode == HSB_MODE_FORWARD || mode == HSB_MODE_COEFFICIENTS) {
+  if (mode == HSB_MODE_FORWARD || mode == HSB_MODE_COEFFICIENTS || mode == HSB_MODE_BACKWARD) {
     if (n_k != 1 || check_ng(h, ng[0])) return 0;
     return make_layout(*h, ng[0], mode).end;
   }
-  fail(h, HSB_ERR_UNSUPPORTED, "workspace mode %d is not available in this build", mode);
+  if (mode == HSB_MODE_BATCH) {
+    for (int k = 0; k < n_k; ++k)
+      if (check_ng(h, ng[k])) return 0;
+    return make_batch_layout(*h, n_k, ng).end;
+  }
+  fail(h, HSB_ERR_ARG, "unknown workspace mode %d", mode);
   return 0;
 }
 
@@ -327,16 +401,154 @@ int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32
   return rc;
 }
 
-int hsbuild_backward(hsbuild_t h, const double*, int32_t, const int32_t*, const double*, const void*, const void*,
-                     const void*, void*, double*, void*, size_t, void*) {
+int hsbuild_backward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
+                     const void* T, const void* gH, const void* gS, void* gT, double* gtau, void* ws,
+                     size_t ws_bytes, void* stream) {
   if (!h) return HSB_ERR_ARG;
-  return fail(h, HSB_ERR_UNSUPPORTED, "backward is not available in this build");
+  h->err.clear();
+  if (!k_frac || !g || !tau || !T || !gH || !gS || !gT || !gtau)
+    return fail(h, HSB_ERR_ARG, "null k_frac, g, tau, T, gH, gS, gT or gtau");
+  int rc = check_ng(h, ng);
+  if (rc) return rc;
+  const Layout L = make_layout(*h, ng, HSB_MODE_BACKWARD);
+  if ((rc = check_ws(h, L, ws, ws_bytes))) return rc;
+  if ((rc = check_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  if ((rc = enqueue_operands(h, L, k_frac, g, tau, T, w, s))) return rc;
+  CellArgs c = h->cell;
+  const double2* W = (const double2*)(w + L.W);
+  double2* PH = (double2*)(w + L.PH);
+  double2* PS = (double2*)(w + L.PS);
+  rc = launched(h, launch_pgemm(W, (const double2*)gH, (const double2*)gS, L.K_pad, ng, L.n_pad, PH, PS, s),
+                "k_pgemm");
+  if (rc) return rc;
+  rc = launched(h, launch_gradT(c, PH, W, L.n_pad, (double2*)(w + L.partT), (double2*)gT, s), "k_gradT");
+  if (rc) return rc;
+  return launched(h, launch_gradtau(c, PH, PS, (const double2*)(w + L.Y), W, (const double*)(w + L.lam),
+                                    (const double*)(w + L.kv), ng, L.n_pad, (double*)(w + L.partTau), gtau, s),
+                  "k_gradtau");
 }
 
-int hsbuild_batch(hsbuild_t h, int32_t, const double*, const int32_t*, const int32_t*, const int64_t*,
-                  const double*, const void*, void*, void*, void*, size_t, void*) {
+int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t* ng, const int32_t* g,
+                  const int64_t* out_off, const double* tau, const void* T, void* H, void* S, void* ws,
+                  size_t ws_bytes, void* stream) {
   if (!h) return HSB_ERR_ARG;
-  return fail(h, HSB_ERR_UNSUPPORTED, "batch is not available in this build");
+  h->err.clear();
+  if (n_k < 1) return fail(h, HSB_ERR_ARG, "n_k must be >= 1 (got %d)", n_k);
+  if (!k_frac || !ng || !g || !out_off || !tau || !T || !H || !S)
+    return fail(h, HSB_ERR_ARG, "null k_frac, ng, g, out_off, tau, T, H or S");
+  if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
+  if (h->precision != HSB_FP64)
+    return fail(h, HSB_ERR_UNSUPPORTED, "batch runs the FP64 contraction only");
+  int rc;
+  for (int k = 0; k < n_k; ++k)
+    if ((rc = check_ng(h, ng[k]))) return rc;
+  {  // output blocks must not overlap
+    std::vector<std::pair<int64_t, int64_t>> blocks;
+    for (int k = 0; k < n_k; ++k) {
+      if (out_off[k] < 0) return fail(h, HSB_ERR_ARG, "out_off[%d] is negative", k);
+      blocks.push_back({out_off[k], out_off[k] + (int64_t)ng[k] * ng[k]});
+    }
+    std::sort(blocks.begin(), blocks.end());
+    for (size_t i = 1; i < blocks.size(); ++i)
+      if (blocks[i].first < blocks[i - 1].second) return fail(h, HSB_ERR_SHAPE, "output blocks overlap");
+  }
+  const BatchLayout B = make_batch_layout(*h, n_k, ng);
+  if (!ws) return fail(h, HSB_ERR_ARG, "workspace pointer is null");
+  if (((uintptr_t)ws) & 255) return fail(h, HSB_ERR_ARG, "workspace must be 256-byte aligned");
+  if (ws_bytes < B.end)
+    return fail(h, HSB_ERR_WORKSPACE, "workspace has %zu bytes, this call needs %zu", ws_bytes, B.end);
+  if ((rc = check_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+
+  // the graph is reused when every argument matches the call it was captured for
+  std::vector<double> kf(k_frac, k_frac + 3 * (size_t)n_k);
+  std::vector<int64_t> ki = {n_k, (int64_t)(uintptr_t)g, (int64_t)(uintptr_t)tau, (int64_t)(uintptr_t)T,
+                             (int64_t)(uintptr_t)H, (int64_t)(uintptr_t)S, (int64_t)(uintptr_t)ws,
+                             (int64_t)ws_bytes};
+  for (int k = 0; k < n_k; ++k) {
+    ki.push_back(ng[k]);
+    ki.push_back(out_off[k]);
+  }
+  if (!(h->graph_exec && kf == h->key_f && ki == h->key_i)) {
+    drop_graph(h);
+    if (!h->cap_stream && hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking) != hipSuccess)
+      return fail(h, HSB_ERR_DEVICE, "hipStreamCreateWithFlags failed");
+    if (!h->graph_done && hipEventCreateWithFlags(&h->graph_done, hipEventDisableTiming) != hipSuccess)
+      return fail(h, HSB_ERR_DEVICE, "hipEventCreate failed");
+    if (n_k > h->meta_cap) {
+      if (h->meta_host) (void)hipHostFree(h->meta_host);
+      h->meta_host = nullptr;
+      h->meta_cap = 0;
+      if (hipHostMalloc((void**)&h->meta_host, sizeof(BatchMeta) * n_k, hipHostMallocDefault) != hipSuccess)
+        return fail(h, HSB_ERR_DEVICE, "pinned host allocation failed");
+      h->meta_cap = n_k;
+    }
+    int total = 0;
+    int64_t g_row = 0;
+    for (int k = 0; k < n_k; ++k) {
+      BatchMeta& m = h->meta_host[k];
+      m.w_off = (int64_t)(B.W[k] / sizeof(double2));
+      m.y_off = (int64_t)(B.Y[k] / sizeof(double2));
+      m.out_off = out_off[k];
+      m.n = ng[k];
+      m.n_pad = B.n_pad[k];
+      m.nbr = B.n_pad[k] / kTileN;
+      m.tile_start = total;
+      total += hs_tiles(B.n_pad[k]);
+    }
+    hipStream_t cs = h->cap_stream;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess)
+      return fail(h, HSB_ERR_DEVICE, "hipStreamBeginCapture failed");
+    char* w = (char*)ws;
+    rc = HSB_OK;
+    h->capturing = true;
+    for (int k = 0; k < n_k && rc == HSB_OK; ++k) {
+      Layout L;
+      L.n = ng[k];
+      L.n_pad = B.n_pad[k];
+      L.K = B.K;
+      L.K_pad = B.K_pad;
+      L.consts = B.consts;
+      L.lam = B.lam;
+      L.kv = B.kv;
+      L.ang = B.ang;
+      L.ab = B.ab;
+      L.W = B.W[k];
+      L.Y = B.Y[k];
+      rc = enqueue_operands(h, L, k_frac + 3 * k, g + 3 * g_row, tau, T, w, cs);
+      g_row += ng[k];
+    }
+    if (rc == HSB_OK) {
+      hipError_t e = hipMemcpyAsync(w + B.meta, h->meta_host, sizeof(BatchMeta) * n_k, hipMemcpyHostToDevice, cs);
+      if (e == hipSuccess) {
+        const int grid = std::max(8, (h->num_cus / 8) * 8);  // one workgroup per CU, a multiple of 8
+        e = launch_hs_fp64_batch((const double2*)w, (const double*)(w + B.lam), B.K_pad,
+                                 (const BatchMeta*)(w + B.meta), n_k, total, grid, (double2*)H, (double2*)S, cs);
+      }
+      if (e != hipSuccess) rc = launched(h, e, "batched contraction");
+    }
+    hipGraph_t graph = nullptr;
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    h->capturing = false;
+    if (rc != HSB_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (ec != hipSuccess || !graph) return fail(h, HSB_ERR_DEVICE, "hipStreamEndCapture failed");
+    const hipError_t ei = hipGraphInstantiate(&h->graph_exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) {
+      h->graph_exec = nullptr;
+      return fail(h, HSB_ERR_DEVICE, "hipGraphInstantiate: %s", hipGetErrorString(ei));
+    }
+    h->key_f = kf;
+    h->key_i = ki;
+  }
+  hipError_t e = hipGraphLaunch(h->graph_exec, s);
+  if (e != hipSuccess) return launched(h, e, "hipGraphLaunch");
+  return launched(h, hipEventRecord(h->graph_done, s), "hipEventRecord");
 }
 
 int hsbuild_set_timing(hsbuild_t h, int32_t enable) {

@@ -15,9 +15,16 @@
 // and S; each wave owns 64 x 32 of each (4 x 2 MFMA blocks, 16 accumulators
 // of 4 doubles per matrix).  K is staged 16 rows at a time through
 // double-buffered LDS with a register prefetch of the next chunk.  Only tiles
-// that touch the upper triangle are launched; they are numbered row-major
+// that touch the upper triangle are computed; they are numbered row-major
 // over 128 x 128 super-tiles and the numbering is dealt to the eight XCDs in
 // contiguous ranges so tiles sharing a row strip share an L2.
+//
+// k_hs_fp64 computes one k-point, one workgroup per tile.  k_hs_fp64_batch is
+// the persistent form for many k-points: a fixed grid (one workgroup per CU)
+// walks a tile list spanning every k-point, each XCD taking one contiguous
+// range of it; every tile costs the same (same stacked width), so a static
+// walk balances.  Both run the same tile body, so a batched H(k) is bitwise
+// equal to the single-k one.
 #include "hs_internal.h"
 
 namespace hsb {
@@ -30,12 +37,11 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 constexpr int BM = 128, BN = 64, BK = 16, NTHR = 256;
 constexpr int kXcds = 8;
 
-// Workgroup id -> position in a numbering where each XCD (dispatch is
-// round-robin over XCDs) owns one contiguous range.
-__device__ inline int xcd_remap(int w, int num) {
-  const int xcd = w % kXcds, local = w / kXcds;
+// Start and length of XCD x's contiguous share of `num` items.
+__device__ inline void xcd_range(int x, int num, int& start, int& len) {
   const int per = num / kXcds, rem = num % kXcds;
-  return xcd < rem ? xcd * (per + 1) + local : rem * (per + 1) + (xcd - rem) * per + local;
+  start = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+  len = per + (x < rem ? 1 : 0);
 }
 
 // s -> (bi, bj), bj >= bi, row-major over the upper triangle of an nb x nb grid.
@@ -53,21 +59,18 @@ __device__ inline void tri_decode(int s, int nb, int& bi, int& bj) {
 
 #define MFMA(a, b, c) __builtin_amdgcn_mfma_f64_16x16x4f64((a), (b), (c), 0, 0, 0)
 
-__global__ void __launch_bounds__(NTHR, 1) k_hs_fp64(const d2* __restrict__ W, const d2* __restrict__ Y,
-                                                     const double* __restrict__ lam, int K_pad, int n, int n_pad,
-                                                     int nbr, int num_wg, double2* __restrict__ H,
-                                                     double2* __restrict__ S, int64_t ldh) {
-  __shared__ d2 sL[2][BK][BM];
-  __shared__ d2 sR[2][BK][BN];
-  __shared__ d2 sY[2][BK][BN];
+struct Smem {
+  d2 L[2][BK][BM];
+  d2 R[2][BK][BN];
+  d2 Y[2][BK][BN];
+};
 
+// One 128 x 64 tile (rows row0.., columns col0..) of H and S, upper triangle stored.
+__device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, const d2* __restrict__ Y,
+                                        const double* __restrict__ lam, int K_pad, int n, int n_pad, int row0,
+                                        int col0, d2* __restrict__ H, d2* __restrict__ S, int64_t ldh) {
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
-  const int w = xcd_remap(blockIdx.x, num_wg);
-  int bi, sj;
-  tri_decode(w >> 1, nbr, bi, sj);
-  const int row0 = bi * BM, col0 = sj * BM + (w & 1) * BN;
-  if (col0 >= n) return;
 
   // staging map: left chunk 16 x 128 (8 per thread), right chunks 16 x 64 (4 per thread)
   d2 pl[8], pr[4], py[4];
@@ -86,17 +89,17 @@ __global__ void __launch_bounds__(NTHR, 1) k_hs_fp64(const d2* __restrict__ W, c
       pm[i] = lam[(kc) + (e >> 6)];                                              \
     }                                                                            \
   } while (0)
-#define HS_LSTORE(b)                                                                \
-  do {                                                                              \
-    _Pragma("unroll") for (int i = 0; i < 8; ++i) {                                 \
-      const int e = tid + NTHR * i;                                                 \
-      sL[b][e >> 7][e & 127] = pl[i];                                               \
-    }                                                                               \
-    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                 \
-      const int e = tid + NTHR * i;                                                 \
-      sR[b][e >> 6][e & 63] = pm[i] * pr[i];                                         \
-      sY[b][e >> 6][e & 63] = py[i];                                                \
-    }                                                                               \
+#define HS_LSTORE(b)                                 \
+  do {                                               \
+    _Pragma("unroll") for (int i = 0; i < 8; ++i) {  \
+      const int e = tid + NTHR * i;                  \
+      sm.L[b][e >> 7][e & 127] = pl[i];              \
+    }                                                \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {  \
+      const int e = tid + NTHR * i;                  \
+      sm.R[b][e >> 6][e & 63] = pm[i] * pr[i];       \
+      sm.Y[b][e >> 6][e & 63] = py[i];               \
+    }                                                \
   } while (0)
 
   d4 hr[4][2], hi[4][2], sr[4][2], si[4][2];
@@ -123,13 +126,13 @@ __global__ void __launch_bounds__(NTHR, 1) k_hs_fp64(const d2* __restrict__ W, c
       double ar[4], ai[4], an[4], yre[2], yim[2], wre[2], wim[2];
 #pragma unroll
       for (int i = 0; i < 4; ++i) {
-        const d2 a = sL[b][kk][wr * 64 + i * 16 + (lane & 15)];
+        const d2 a = sm.L[b][kk][wr * 64 + i * 16 + (lane & 15)];
         ar[i] = a.x; ai[i] = a.y; an[i] = -a.y;
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const d2 yv = sY[b][kk][wc * 32 + j * 16 + (lane & 15)];
-        const d2 wv = sR[b][kk][wc * 32 + j * 16 + (lane & 15)];
+        const d2 yv = sm.Y[b][kk][wc * 32 + j * 16 + (lane & 15)];
+        const d2 wv = sm.R[b][kk][wc * 32 + j * 16 + (lane & 15)];
         yre[j] = yv.x; yim[j] = yv.y; wre[j] = wv.x; wim[j] = wv.y;
       }
 #pragma unroll
@@ -168,6 +171,8 @@ __global__ void __launch_bounds__(NTHR, 1) k_hs_fp64(const d2* __restrict__ W, c
     if (c + 1 < nchunks) HS_LSTORE(b ^ 1);
     __syncthreads();
   }
+#undef HS_GLOAD
+#undef HS_LSTORE
 
   // D layout of the 16x16 f64 MFMA: lane l, element q -> row l/16 + 4q, column l%16
 #pragma unroll
@@ -180,20 +185,81 @@ __global__ void __launch_bounds__(NTHR, 1) k_hs_fp64(const d2* __restrict__ W, c
         const int col = col0 + wc * 32 + j * 16 + (lane & 15);
         if (row < n && col < n && col >= row) {
           const int64_t o = (int64_t)row * ldh + col;
-          H[o] = make_double2(hr[i][j][q], hi[i][j][q]);
-          S[o] = make_double2(sr[i][j][q], si[i][j][q]);
+          H[o] = d2{hr[i][j][q], hi[i][j][q]};
+          S[o] = d2{sr[i][j][q], si[i][j][q]};
         }
       }
 }
 
+// Tile w of a k-point with nbr row blocks -> (row0, col0); two 128 x 64 tiles per super-tile.
+__device__ inline void tile_origin(int w, int nbr, int& row0, int& col0) {
+  int bi, sj;
+  tri_decode(w >> 1, nbr, bi, sj);
+  row0 = bi * BM;
+  col0 = sj * BM + (w & 1) * BN;
+}
+
+__global__ void __launch_bounds__(NTHR, 1) k_hs_fp64(const d2* __restrict__ W, const d2* __restrict__ Y,
+                                                     const double* __restrict__ lam, int K_pad, int n, int n_pad,
+                                                     int nbr, int num_wg, d2* __restrict__ H, d2* __restrict__ S,
+                                                     int64_t ldh) {
+  __shared__ Smem sm;
+  // dispatch is round-robin over XCDs: give XCD x the contiguous range of tile numbers
+  const int x = blockIdx.x % kXcds;
+  int start, len;
+  xcd_range(x, num_wg, start, len);
+  const int w = start + blockIdx.x / kXcds;
+  int row0, col0;
+  tile_origin(w, nbr, row0, col0);
+  if (col0 >= n) return;
+  hs_tile(sm, W, Y, lam, K_pad, n, n_pad, row0, col0, H, S, ldh);
+}
+
+__global__ void __launch_bounds__(NTHR, 1) k_hs_fp64_batch(const d2* __restrict__ ws, const double* __restrict__ lam,
+                                                           int K_pad, const BatchMeta* __restrict__ meta, int n_k,
+                                                           int total, d2* __restrict__ H, d2* __restrict__ S) {
+  __shared__ Smem sm;
+  const int x = blockIdx.x % kXcds;
+  const int per_xcd = gridDim.x / kXcds;  // the grid is a multiple of the XCD count
+  int start, len;
+  xcd_range(x, total, start, len);
+  for (int i = blockIdx.x / kXcds; i < len; i += per_xcd) {
+    const int t = start + i;
+    int lo = 0, hi = n_k - 1;  // last k with tile_start <= t
+    while (lo < hi) {
+      const int mid = (lo + hi + 1) >> 1;
+      if (meta[mid].tile_start <= t) lo = mid;
+      else hi = mid - 1;
+    }
+    const BatchMeta m = meta[lo];
+    int row0, col0;
+    tile_origin(t - m.tile_start, m.nbr, row0, col0);
+    if (col0 >= m.n) continue;  // uniform across the workgroup
+    hs_tile(sm, ws + m.w_off, ws + m.y_off, lam, K_pad, m.n, m.n_pad, row0, col0, H + m.out_off, S + m.out_off,
+            m.n);
+  }
+}
+
 }  // namespace
+
+int hs_tiles(int n_pad) {
+  const int nbr = n_pad / BM;
+  return nbr * (nbr + 1);
+}
 
 hipError_t launch_hs_fp64(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
                           double2* H, double2* S, int64_t ldh, hipStream_t s) {
   const int nbr = n_pad / BM;
-  const int num_wg = nbr * (nbr + 1);  // two 128 x 64 tiles per upper-triangle 128 x 128 super-tile
+  const int num_wg = hs_tiles(n_pad);  // two 128 x 64 tiles per upper-triangle 128 x 128 super-tile
   hipLaunchKernelGGL(k_hs_fp64, dim3(num_wg), dim3(NTHR), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad, n, n_pad,
-                     nbr, num_wg, H, S, ldh);
+                     nbr, num_wg, (d2*)H, (d2*)S, ldh);
+  return hipGetLastError();
+}
+
+hipError_t launch_hs_fp64_batch(const double2* ws, const double* lam, int K_pad, const BatchMeta* meta, int n_k,
+                                int total, int grid, double2* H, double2* S, hipStream_t s) {
+  hipLaunchKernelGGL(k_hs_fp64_batch, dim3(grid), dim3(NTHR), 0, s, (const d2*)ws, lam, K_pad, meta, n_k, total,
+                     (d2*)H, (d2*)S);
   return hipGetLastError();
 }
 

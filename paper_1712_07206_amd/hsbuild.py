@@ -144,6 +144,69 @@ class HSBuilder:
                                         _ptr(ws), ws.numel(), _stream()), self._h)
         return H, S
 
+    def backward(self, k_frac, g: torch.Tensor, tau: torch.Tensor, T: torch.Tensor, gH: torch.Tensor,
+                 gS: torch.Tensor, gT: Optional[torch.Tensor] = None, gtau: Optional[torch.Tensor] = None):
+        """Gradients of a real loss with Hermitian dL/dH = gH and dL/dS = gS
+        (torch convention dL/dRe + i dL/dIm): returns (dL/dT, dL/dtau)."""
+        ng = int(g.shape[0])
+        g = _dev(g, torch.int32, "g", (ng, 3))
+        tau = _dev(tau, torch.float64, "tau", (self.n_atoms, 3))
+        m = 2 * self.n_l
+        T = _dev(T, torch.complex128, "T", (self.n_types, m, m))
+        gH = _dev(gH, torch.complex128, "gH", (ng, ng))
+        gS = _dev(gS, torch.complex128, "gS", (ng, ng))
+        if gT is None:
+            gT = torch.empty((self.n_types, m, m), dtype=torch.complex128, device="cuda")
+        if gtau is None:
+            gtau = torch.empty((self.n_atoms, 3), dtype=torch.float64, device="cuda")
+        gT = _dev(gT, torch.complex128, "gT", (self.n_types, m, m))
+        gtau = _dev(gtau, torch.float64, "gtau", (self.n_atoms, 3))
+        ws = self.workspace(N.HSB_MODE_BACKWARD, [ng])
+        kf = (ctypes.c_double * 3)(*[float(x) for x in k_frac])
+        N.check(N.lib().hsbuild_backward(self._h, kf, ng, _ptr(g), _ptr(tau), _ptr(T), _ptr(gH), _ptr(gS),
+                                         _ptr(gT), _ptr(gtau), _ptr(ws), ws.numel(), _stream()), self._h)
+        return gT, gtau
+
+    def batch(self, k_frac, g_list: Sequence[torch.Tensor], tau: torch.Tensor, T: torch.Tensor,
+              H: Optional[torch.Tensor] = None, S: Optional[torch.Tensor] = None, out_off=None,
+              ws: Optional[torch.Tensor] = None):
+        """H and S of many k-points in one captured graph (one persistent
+        contraction).  Returns flat complex128 buffers H, S and the element
+        offsets of each k's N_G x N_G block (upper triangles written)."""
+        kf = np.ascontiguousarray(k_frac, dtype=np.float64).reshape(-1, 3)
+        n_k = kf.shape[0]
+        if len(g_list) != n_k:
+            raise ValueError("one G list per k-point")
+        ng = np.array([int(x.shape[0]) for x in g_list], dtype=np.int32)
+        gkey = tuple((int(x.data_ptr()), int(x.shape[0])) for x in g_list)
+        if getattr(self, "_gcat_key", None) == gkey:
+            g_cat = self._batch_keep  # same G lists: keep the buffer the captured graph refers to
+        else:
+            g_cat = _dev(torch.cat([_dev(x, torch.int32, "g") for x in g_list]), torch.int32, "g")
+        tau = _dev(tau, torch.float64, "tau", (self.n_atoms, 3))
+        T = _dev(T, torch.complex128, "T", (self.n_types, 2 * self.n_l, 2 * self.n_l))
+        if out_off is None:
+            out_off = np.concatenate([[0], np.cumsum(ng.astype(np.int64) ** 2)[:-1]])
+        out_off = np.ascontiguousarray(out_off, dtype=np.int64)
+        total = int(max(out_off[k] + int(ng[k]) ** 2 for k in range(n_k)))
+        if H is None:
+            H = torch.empty(total, dtype=torch.complex128, device="cuda")
+        if S is None:
+            S = torch.empty(total, dtype=torch.complex128, device="cuda")
+        H = _dev(H, torch.complex128, "H")
+        S = _dev(S, torch.complex128, "S")
+        if H.numel() < total or S.numel() < total:
+            raise ValueError("H and S need %d elements" % total)
+        if ws is None:
+            ws = self.workspace(N.HSB_MODE_BATCH, list(ng))
+        self._batch_keep = g_cat  # the captured graph refers to this buffer
+        self._gcat_key = gkey
+        N.check(N.lib().hsbuild_batch(self._h, n_k, kf.ctypes.data_as(ctypes.POINTER(ctypes.c_double)),
+                                      ng.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)), _ptr(g_cat),
+                                      out_off.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), _ptr(tau), _ptr(T),
+                                      _ptr(H), _ptr(S), _ptr(ws), ws.numel(), _stream()), self._h)
+        return H, S, out_off
+
     def set_timing(self, enable: bool) -> None:
         N.check(N.lib().hsbuild_set_timing(self._h, 1 if enable else 0), self._h)
 

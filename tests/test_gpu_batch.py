@@ -1,0 +1,105 @@
+"""Batched k-points (one captured graph, one persistent contraction) against
+sequential single-k forwards (bitwise) and against the oracle."""
+import numpy as np
+import pytest
+import torch
+
+from flapw_cells import make_batch_case, sub_case
+from oracle import hs_oracle as o
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    yield
+
+
+def _full(M):
+    return np.triu(M) + np.triu(M, 1).conj().T
+
+
+def _setup(case):
+    from paper_1712_07206_amd.hsbuild import HSBuilder
+    b = HSBuilder.from_case(case)
+    tau = torch.as_tensor(case["tau"], device="cuda")
+    T = torch.as_tensor(case["T"], device="cuda")
+    gl = [torch.as_tensor(g, device="cuda") for g in case["g"]]
+    return b, tau, T, gl
+
+
+def _block(M, off, n):
+    return M[int(off): int(off) + n * n].reshape(n, n)
+
+
+def test_batch_equals_sequential_bitwise():
+    case = make_batch_case(3, n_k=5)
+    b, tau, T, gl = _setup(case)
+    H, S, off = b.batch(case["k_frac"], gl, tau, T)
+    torch.cuda.synchronize()
+    Hc, Sc = H.cpu().numpy(), S.cpu().numpy()
+    for k in range(5):
+        n = int(case["n_g"][k])
+        h1, s1 = b.forward(case["k_frac"][k], gl[k], tau, T)
+        iu = np.triu_indices(n)
+        assert np.array_equal(_block(Hc, off[k], n)[iu], h1.cpu().numpy()[iu]), k
+        assert np.array_equal(_block(Sc, off[k], n)[iu], s1.cpu().numpy()[iu]), k
+
+
+def test_batch_graph_reuse_and_recapture():
+    case = make_batch_case(3, n_k=3)
+    b, tau, T, gl = _setup(case)
+    n_tot = int(sum(int(n) ** 2 for n in case["n_g"]))
+    H = torch.zeros(n_tot, dtype=torch.complex128, device="cuda")
+    S = torch.zeros(n_tot, dtype=torch.complex128, device="cuda")
+    b.batch(case["k_frac"], gl, tau, T, H, S)
+    first = H.clone()
+    H.zero_()
+    b.batch(case["k_frac"], gl, tau, T, H, S)  # same arguments: the captured graph is replayed
+    torch.cuda.synchronize()
+    assert torch.equal(first, H)
+    # different k-points: captured again
+    k2 = case["k_frac"].copy()
+    k2[0] = -k2[0]
+    b.batch(k2, gl, tau, T, H, S)
+    h0, _ = b.forward(k2[0], gl[0], tau, T)
+    torch.cuda.synchronize()
+    n0 = int(case["n_g"][0])
+    iu = np.triu_indices(n0)
+    assert np.array_equal(H[:n0 * n0].reshape(n0, n0).cpu().numpy()[iu], h0.cpu().numpy()[iu])
+
+
+def test_batch_full_64k_against_oracle():
+    """The full multi-k workload (64 k-points, N_G 2800-3400, 32 atoms, l_max = 8):
+    the k-points with the smallest and largest N_G and two others vs the oracle."""
+    case = make_batch_case(3)
+    b, tau, T, gl = _setup(case)
+    H, S, off = b.batch(case["k_frac"], gl, tau, T)
+    torch.cuda.synchronize()
+    ng = case["n_g"]
+    picks = sorted({int(np.argmin(ng)), int(np.argmax(ng)), 17, 40})
+    for k in picks:
+        n = int(ng[k])
+        sub = sub_case(case, k)
+        Hr, Sr = o.hs(sub)
+        Hk = _block(H, off[k], n).cpu().numpy()
+        Sk = _block(S, off[k], n).cpu().numpy()
+        eh = np.linalg.norm(_full(Hk) - Hr) / np.linalg.norm(Hr)
+        es = np.linalg.norm(_full(Sk) - Sr) / np.linalg.norm(Sr)
+        print("batch k=%d N_G=%d rel err H %.3e S %.3e" % (k, n, eh, es))
+        assert eh <= 1e-12 and es <= 1e-12
+
+
+def test_batch_error_paths():
+    from paper_1712_07206_amd import _native as N
+    case = make_batch_case(3, n_k=2)
+    b, tau, T, gl = _setup(case)
+    n0, n1 = int(case["n_g"][0]), int(case["n_g"][1])
+    with pytest.raises(N.HSBuildError) as e:
+        b.batch(case["k_frac"], gl, tau, T, out_off=[0, n0 * n0 - 1])
+    assert e.value.code == N.HSB_ERR_SHAPE
+    with pytest.raises(N.HSBuildError) as e:
+        b.batch(case["k_frac"], gl, tau, T, out_off=[0, -5])
+    assert e.value.code == N.HSB_ERR_ARG
