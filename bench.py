@@ -45,6 +45,108 @@ def cpu_baseline(index: int, n_g: int) -> dict:
                       "(F=%.3g TFLOP, %.1f s)" % (n_g, flops / 1e12, dt)}
 
 
+def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
+    """The BF16 split-precision forward on the same workload: time per step,
+    speedup over the FP64 path and the relative Frobenius error against it."""
+    import torch
+
+    from paper_1712_07206_amd import HSB_SPLIT_BF16
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import HSBuilder, hermitian_full
+    n = case["n_g"]
+    H64, S64 = hermitian_full(H), hermitian_full(S)
+    b64.close()
+    del ws
+    torch.cuda.empty_cache()
+    bs = HSBuilder.from_case(case, precision=HSB_SPLIT_BF16, n_slices=args.split_slices)
+    wsb = bs.workspace_bytes(N.HSB_MODE_FORWARD, [n])
+    wss = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    log("split path: workspace %.2f GB" % (wsb / 1e9))
+
+    def step():
+        code = bs.forward_raw(case["k_frac"], n, g, tau, T, H, S, wss, wsb)
+        if code != N.HSB_OK:
+            raise N.HSBuildError(code, N.last_error(bs._h))
+
+    for _ in range(max(1, args.warmup)):
+        step()
+    torch.cuda.synchronize()
+    bs.set_timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(args.steps):
+        step()
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / args.steps
+    stage_ms, _ = bs.stage_times()
+    eh = (torch.linalg.norm(hermitian_full(H) - H64) / torch.linalg.norm(H64)).item()
+    es = (torch.linalg.norm(hermitian_full(S) - S64) / torch.linalg.norm(S64)).item()
+    log("split bf16 x%d: %.3f ms/step (contraction stage %.3f ms), speedup %.3f, rel err vs FP64 H %.2e S %.2e"
+        % (args.split_slices, ms, stage_ms[2], ms_fp64 / ms, eh, es))
+    del wss, H64, S64
+    bs.close()
+    torch.cuda.empty_cache()
+    return {"precision": "bf16", "slices": args.split_slices, "slice_bits": 8, "ms_per_step": round(ms, 4),
+            "fp64_equiv_tflops": round(flops / (ms * 1e-3) / 1e12, 4), "speedup": round(ms_fp64 / ms, 4),
+            "stages_ms": {"coefficients": round(stage_ms[0], 4), "t_products": round(stage_ms[1], 4),
+                          "split_contraction": round(stage_ms[2], 4)},
+            "rel_err_vs_fp64": {"H": eh, "S": es}, "meets_1e-10": bool(eh <= 1e-10 and es <= 1e-10)}
+
+
+def batch_leg(args) -> dict:
+    """The multi-k workload (64 k-points, N_G 2800-3400, T shared): one captured
+    graph with a persistent contraction, against 64 sequential forward calls."""
+    import torch
+
+    from flapw_cells import make_batch_case
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import HSBuilder
+
+    case = make_batch_case(3)
+    n_k = len(case["g"])
+    b = HSBuilder.from_case(case)
+    tau = torch.as_tensor(case["tau"], device="cuda")
+    T = torch.as_tensor(case["T"], device="cuda")
+    gl = [torch.as_tensor(g, device="cuda") for g in case["g"]]
+    ng = [int(x) for x in case["n_g"]]
+    k_c = case["n_atoms"] * case["n_l"]
+    flops = sum(16.0 * k_c * n * (n + 1) + 32.0 * case["n_atoms"] * case["n_l"] ** 2 * n for n in ng)
+    H, S, off = b.batch(case["k_frac"], gl, tau, T)  # captures the graph
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(1, args.steps)
+    e0.record()
+    for _ in range(reps):
+        b.batch(case["k_frac"], gl, tau, T, H, S)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_graph = e0.elapsed_time(e1) / reps
+    # sequential: one forward per k on the same stream, outputs written in place
+    wsb = b.workspace_bytes(N.HSB_MODE_FORWARD, [max(ng)])
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    outs = [(H[int(off[k]): int(off[k]) + ng[k] ** 2].view(ng[k], ng[k]),
+             S[int(off[k]): int(off[k]) + ng[k] ** 2].view(ng[k], ng[k])) for k in range(n_k)]
+    for k in range(n_k):
+        b.forward_raw(case["k_frac"][k], ng[k], gl[k], tau, T, outs[k][0], outs[k][1], ws, wsb)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(reps):
+        for k in range(n_k):
+            b.forward_raw(case["k_frac"][k], ng[k], gl[k], tau, T, outs[k][0], outs[k][1], ws, wsb)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_seq = e0.elapsed_time(e1) / reps
+    log("batch %d k-points: graph %.3f ms, sequential %.3f ms, speedup %.3f, %.2f TFLOP/s"
+        % (n_k, ms_graph, ms_seq, ms_seq / ms_graph, flops / (ms_graph * 1e-3) / 1e12))
+    del H, S, ws, outs
+    b.close()
+    torch.cuda.empty_cache()
+    return {"workload": case["name"], "n_k": n_k, "n_g_min": min(ng), "n_g_max": max(ng),
+            "ms_graph": round(ms_graph, 4), "ms_sequential": round(ms_seq, 4),
+            "speedup": round(ms_seq / ms_graph, 4), "fp64_equiv_tflops": round(flops / (ms_graph * 1e-3) / 1e12, 4)}
+
+
 def recorded_traffic(workload: str):
     """HBM bytes per launch of the contraction kernel from the committed
     rocprofv3 PMC record, only if the kernel source is the one profiled."""
@@ -69,6 +171,9 @@ def main() -> int:
     ap.add_argument("--ng", type=int, default=None, help="override the basis size")
     ap.add_argument("--cpu-ng", type=int, default=5400, help="basis size of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-k-point batch leg")
+    ap.add_argument("--split-slices", type=int, default=5,
+                    help="also time the BF16 split-precision path with this many slices (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -165,8 +270,14 @@ def main() -> int:
                      "algorithmic_flops_per_launch": flops_hs},
         "split_speedup": None,
     }
+    if args.split_slices > 0:
+        result["split"] = split_leg(args, case, b, g, tau, T, H, S, ws, ms_step, flops)
+        result["split_speedup"] = result["split"]["speedup"]
     del H, S, ws
     torch.cuda.empty_cache()
+    if not args.no_batch:
+        result["batch"] = batch_leg(args)
+        result["batch_speedup"] = result["batch"]["speedup"]
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host (N_G=%d)" % args.cpu_ng)
         result["cpu_baseline"] = cpu_baseline(args.config, args.cpu_ng)

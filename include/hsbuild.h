@@ -81,7 +81,7 @@ typedef struct {
   const double* radial;       /* [n_types][l_max+1][4]: u, u', udot, udot' at R_MT */
   const double* udot_norm2;   /* [n_types][l_max+1]: ||udot_l||^2 >= 0 */
   int32_t precision;          /* HSB_FP64, HSB_SPLIT_FP16 or HSB_SPLIT_BF16 */
-  int32_t n_slices;           /* split path only: slices per operand, 3..8 */
+  int32_t n_slices;           /* split path only: 8-bit slices per operand, 3..6 */
 } hsb_config;
 
 /* Create a handle.  Returns HSB_ERR_NUMERIC if some radial Wronskian
@@ -141,6 +141,15 @@ int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t*
 #define HSB_TIMING_CAPACITY 256
 int hsbuild_set_timing(hsbuild_t h, int32_t enable);
 int hsbuild_stage_times(hsbuild_t h, double* ms_avg, int32_t* n_calls);
+
+/* Tuning options (performance only: results are bitwise independent of them).
+ * HSB_OPT_TILE_GROUP: order in which the upper-triangle tiles of the FP64
+ * contraction are dealt to the compute units: 0 = row-major, g > 0 = 128-row
+ * super-rows taken g at a time, column by column (0..64; default 0).  Setting
+ * an option drops a captured batch graph. */
+enum { HSB_OPT_TILE_GROUP = 1 };
+int hsbuild_set_option(hsbuild_t h, int32_t option, int32_t value);
+int hsbuild_get_option(hsbuild_t h, int32_t option, int32_t* value);
 
 /* Message of the last error on h (h = NULL: the last hsbuild_create error of
  * this thread).  Valid until the next call on the handle. */

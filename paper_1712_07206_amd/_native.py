@@ -32,7 +32,10 @@ HSB_MODE_COEFFICIENTS = 3
 
 EXPORTS = ("hsbuild_create", "hsbuild_destroy", "hsbuild_workspace_bytes", "hsbuild_coefficients",
            "hsbuild_forward", "hsbuild_backward", "hsbuild_batch", "hsbuild_last_error",
-           "hsbuild_host_bessel", "hsbuild_host_angular", "hsbuild_set_timing", "hsbuild_stage_times")
+           "hsbuild_host_bessel", "hsbuild_host_angular", "hsbuild_set_timing", "hsbuild_stage_times",
+           "hsbuild_set_option", "hsbuild_get_option")
+
+HSB_OPT_TILE_GROUP = 1
 
 
 class HsbConfig(ctypes.Structure):
@@ -92,6 +95,10 @@ def lib():
     L.hsbuild_set_timing.restype = c_int
     L.hsbuild_stage_times.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int32)]
     L.hsbuild_stage_times.restype = c_int
+    L.hsbuild_set_option.argtypes = [c_void_p, c_int32, c_int32]
+    L.hsbuild_set_option.restype = c_int
+    L.hsbuild_get_option.argtypes = [c_void_p, c_int32, POINTER(c_int32)]
+    L.hsbuild_get_option.restype = c_int
     _lib = L
     return L
 

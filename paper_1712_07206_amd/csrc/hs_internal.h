@@ -42,6 +42,8 @@ struct Layout {
   int n = 0, n_pad = 0, K = 0, K_pad = 0;
   size_t W = 0, Y = 0, ang = 0, ab = 0, kv = 0, lam = 0, consts = 0, end = 0;
   size_t PH = 0, PS = 0, partT = 0, partTau = 0;  // backward only
+  int K_pad2 = 0;                                  // split only: stacked rows padded to 32
+  size_t mx = 0, scale = 0, slL = 0, slS = 0, slY = 0;  // split only
 };
 
 // Per-k-point entry of the batched contraction's tile list (device copy in the workspace).
@@ -67,14 +69,26 @@ hipError_t launch_zero_rows(double2* a, int64_t ld, int row0, int row1, hipStrea
 hipError_t launch_tprod(const CellArgs& c, const double2* T, const double2* W, double2* Y, int n_pad,
                         hipStream_t s);
 // Upper triangles of H = W^H Y and S = W^H diag(lam) W over K_pad rows.
+// gr: tile order (0 row-major, > 0 super-rows taken in groups of gr).
 hipError_t launch_hs_fp64(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
-                          double2* H, double2* S, int64_t ldh, hipStream_t s);
+                          int gr, double2* H, double2* S, int64_t ldh, hipStream_t s);
 
 // Number of 128 x 64 tiles the contraction covers for a padded basis size.
 int hs_tiles(int n_pad);
 // Persistent contraction over the tiles of every k-point in meta (grid: a multiple of 8).
 hipError_t launch_hs_fp64_batch(const double2* ws, const double* lam, int K_pad, const BatchMeta* meta, int n_k,
-                                int total, int grid, double2* H, double2* S, hipStream_t s);
+                                int total, int grid, int gr, double2* H, double2* S, hipStream_t s);
+
+// ---- split precision ----
+// Column scales 2^e (max_k |Re|, |Im| < 2^e) of W, lam W and Y: scale[0..3 n_pad); mx: 3 n_pad scratch.
+hipError_t launch_split_scales(const double2* W, const double2* Y, const double* lam, int K, int n_pad,
+                               unsigned long long* mx, double* scale, hipStream_t s);
+// S 8-bit slices (BF16 or FP16 values) of X (times lam if use_lam) in the blocked layout, QK = K_pad2 / 8.
+hipError_t launch_split_slices(int precision, int S, const double2* X, const double* lam, int use_lam, int K,
+                               int n_pad, int QK, const double* scale, void* out, hipStream_t s);
+// Upper triangle of C = conj(L)^T R from the slices (C: [n][n]).
+hipError_t launch_hs_split(int precision, int S, const void* L, const void* R, const double* scL, const double* scR,
+                           int QK, int n, int n_pad, double2* C, hipStream_t s);
 
 // ---- adjoint ----
 int gradtau_blocks(int n);

@@ -22,6 +22,7 @@ struct hsbuild_s {
   int device = 0;
   int n_types = 0, n_atoms = 0, l_max = 0, n_l = 0, max_ng = 0;
   int precision = HSB_FP64, n_slices = 0;
+  int tile_group = 0;  // HSB_OPT_TILE_GROUP
   double lattice[9];
   CellArgs cell;              // kfrac filled per call
   TypeConsts* consts = nullptr;  // pinned host copy, source of the per-call upload
@@ -80,6 +81,15 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
     L.lam = take((size_t)L.K_pad * sizeof(double));
     L.W = take((size_t)L.K_pad * np * sizeof(double2));
     L.Y = take((size_t)L.K_pad * np * sizeof(double2));
+  }
+  if (mode == HSB_MODE_FORWARD && h.precision != HSB_FP64) {
+    L.K_pad2 = (int)round_up(L.K, 32);
+    const size_t planes = (size_t)2 * h.n_slices * np * L.K_pad2 * 2;  // bytes per sliced operand
+    L.mx = take(3 * np * sizeof(unsigned long long));
+    L.scale = take(3 * np * sizeof(double));
+    L.slL = take(planes);
+    L.slS = take(planes);
+    L.slY = take(planes);
   }
   if (mode == HSB_MODE_BACKWARD) {
     const size_t M = 2 * (size_t)h.n_l;
@@ -170,6 +180,36 @@ int enqueue_operands(hsbuild_t h, const Layout& L, const double k_frac[3], const
   return rc;
 }
 
+// Split-precision contraction: column scales, slices of W, lam W and Y, then S and H.
+int enqueue_split(hsbuild_t h, const Layout& L, char* w, double2* H, double2* S, hipStream_t s) {
+  const double2* W = (const double2*)(w + L.W);
+  const double2* Y = (const double2*)(w + L.Y);
+  const double* lam = (const double*)(w + L.lam);
+  const double* sc = (const double*)(w + L.scale);
+  const int QK = L.K_pad2 / 8;
+  int rc = launched(h, launch_split_scales(W, Y, lam, L.K, L.n_pad, (unsigned long long*)(w + L.mx), (double*)sc, s),
+                    "split scales");
+  if (rc) return rc;
+  rc = launched(h, launch_split_slices(h->precision, h->n_slices, W, lam, 0, L.K, L.n_pad, QK, sc, w + L.slL, s),
+                "split slices");
+  if (rc) return rc;
+  rc = launched(h, launch_split_slices(h->precision, h->n_slices, W, lam, 1, L.K, L.n_pad, QK, sc + L.n_pad,
+                                       w + L.slS, s),
+                "split slices");
+  if (rc) return rc;
+  rc = launched(h, launch_split_slices(h->precision, h->n_slices, Y, lam, 0, L.K, L.n_pad, QK, sc + 2 * L.n_pad,
+                                       w + L.slY, s),
+                "split slices");
+  if (rc) return rc;
+  rc = launched(h, launch_hs_split(h->precision, h->n_slices, w + L.slL, w + L.slS, sc, sc + L.n_pad, QK, L.n,
+                                   L.n_pad, S, s),
+                "split contraction (S)");
+  if (rc) return rc;
+  return launched(h, launch_hs_split(h->precision, h->n_slices, w + L.slL, w + L.slY, sc, sc + 2 * L.n_pad, QK, L.n,
+                                     L.n_pad, H, s),
+                  "split contraction (H)");
+}
+
 struct BatchLayout {
   int K = 0, K_pad = 0, max_n_pad = 0;
   size_t consts = 0, lam = 0, kv = 0, ang = 0, ab = 0, meta = 0, end = 0;
@@ -233,8 +273,8 @@ int hsbuild_create(const hsb_config* cfg, hsbuild_t* out) {
     return fail(nullptr, HSB_ERR_ARG, "null atom_type, r_mt, radial or udot_norm2");
   if (cfg->precision != HSB_FP64 && cfg->precision != HSB_SPLIT_FP16 && cfg->precision != HSB_SPLIT_BF16)
     return fail(nullptr, HSB_ERR_ARG, "unknown precision %d", cfg->precision);
-  if (cfg->precision != HSB_FP64 && (cfg->n_slices < 3 || cfg->n_slices > 8))
-    return fail(nullptr, HSB_ERR_ARG, "n_slices=%d outside [3, 8]", cfg->n_slices);
+  if (cfg->precision != HSB_FP64 && (cfg->n_slices < 3 || cfg->n_slices > 6))
+    return fail(nullptr, HSB_ERR_ARG, "n_slices=%d outside [3, 6]", cfg->n_slices);
   const int n_l = (cfg->l_max + 1) * (cfg->l_max + 1);
   const int64_t K = 2LL * cfg->n_atoms * n_l;
   if (K > (1LL << 30) || (int64_t)cfg->max_ng * (int64_t)round_up(cfg->max_ng, kTileN) > (1LL << 40))
@@ -385,8 +425,6 @@ int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32
   if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
   int rc = check_ng(h, ng);
   if (rc) return rc;
-  if (h->precision != HSB_FP64)
-    return fail(h, HSB_ERR_UNSUPPORTED, "split-precision contraction is not available in this build");
   const Layout L = make_layout(*h, ng, HSB_MODE_FORWARD);
   if ((rc = check_ws(h, L, ws, ws_bytes))) return rc;
   if ((rc = check_device(h))) return rc;
@@ -394,9 +432,13 @@ int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32
   char* w = (char*)ws;
   mark(h, 0, s);
   if ((rc = enqueue_operands(h, L, k_frac, g, tau, T, w, s))) return rc;
-  rc = launched(h, launch_hs_fp64((const double2*)(w + L.W), (const double2*)(w + L.Y),
-                                  (const double*)(w + L.lam), L.K_pad, ng, L.n_pad, (double2*)H, (double2*)S, ng, s),
-                "k_hs_fp64");
+  if (h->precision == HSB_FP64) {
+    rc = launched(h, launch_hs_fp64((const double2*)(w + L.W), (const double2*)(w + L.Y), (const double*)(w + L.lam),
+                                    L.K_pad, ng, L.n_pad, h->tile_group, (double2*)H, (double2*)S, ng, s),
+                  "k_hs_fp64");
+  } else {
+    rc = enqueue_split(h, L, w, (double2*)H, (double2*)S, s);
+  }
   mark(h, 3, s);
   return rc;
 }
@@ -525,7 +567,8 @@ int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t*
       if (e == hipSuccess) {
         const int grid = std::max(8, (h->num_cus / 8) * 8);  // one workgroup per CU, a multiple of 8
         e = launch_hs_fp64_batch((const double2*)w, (const double*)(w + B.lam), B.K_pad,
-                                 (const BatchMeta*)(w + B.meta), n_k, total, grid, (double2*)H, (double2*)S, cs);
+                                 (const BatchMeta*)(w + B.meta), n_k, total, grid, h->tile_group, (double2*)H,
+                                 (double2*)S, cs);
       }
       if (e != hipSuccess) rc = launched(h, e, "batched contraction");
     }
@@ -583,6 +626,31 @@ int hsbuild_stage_times(hsbuild_t h, double* ms_avg, int32_t* n_calls) {
   for (int k = 0; k < 3; ++k) ms_avg[k] = h->n_timed ? acc[k] / h->n_timed : 0.0;
   *n_calls = h->n_timed;
   return HSB_OK;
+}
+
+int hsbuild_set_option(hsbuild_t h, int32_t option, int32_t value) {
+  if (!h) return HSB_ERR_ARG;
+  h->err.clear();
+  switch (option) {
+    case HSB_OPT_TILE_GROUP:
+      if (value < 0 || value > 64) return fail(h, HSB_ERR_ARG, "tile group %d outside [0, 64]", value);
+      if (value != h->tile_group) drop_graph(h);
+      h->tile_group = value;
+      return HSB_OK;
+    default:
+      return fail(h, HSB_ERR_ARG, "unknown option %d", option);
+  }
+}
+
+int hsbuild_get_option(hsbuild_t h, int32_t option, int32_t* value) {
+  if (!h || !value) return HSB_ERR_ARG;
+  switch (option) {
+    case HSB_OPT_TILE_GROUP:
+      *value = h->tile_group;
+      return HSB_OK;
+    default:
+      return fail(h, HSB_ERR_ARG, "unknown option %d", option);
+  }
 }
 
 const char* hsbuild_last_error(hsbuild_t h) { return h ? h->err.c_str() : g_create_error.c_str(); }

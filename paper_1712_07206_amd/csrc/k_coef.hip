@@ -6,8 +6,9 @@
 //                radial matching pair (a_l, b_l).  Small and compute-light.
 //   k_assemble : the HBM-write-bound product
 //                W[atom][A|B][L][G] = e^{iK_G.tau_atom} * ang[L][G] * (a|b)_{t,l}(G),
-//                one thread per G (coalesced 16-byte stores along G), one
-//                workgroup row per atom so every atom re-reads ang from L2.
+//                one thread per G (coalesced 16-byte stores along G) and a
+//                group of eight atoms, so each angular factor is read once
+//                per eight atoms.
 //   k_lambda   : the overlap weight of each stacked row.
 #include "hs_internal.h"
 #include "special.h"
@@ -96,32 +97,50 @@ __global__ void __launch_bounds__(256) k_lambda(CellArgs c, const TypeConsts* __
   lam[k] = v;
 }
 
-// One thread per G, blockIdx.y = atom.  Stores are 16 B per lane, contiguous along G.
+// One thread per G and a group of kAtomGroup atoms (blockIdx.y): each angular
+// factor is read once and written out for every atom of the group.  Stores are
+// 16 B per lane, contiguous along G.
+constexpr int kAtomGroup = 8;
+
 __global__ void __launch_bounds__(256) k_assemble(CellArgs c, int n_pad, const double2* __restrict__ ang,
                                                   const double2* __restrict__ ab, const double* __restrict__ kv,
                                                   const double* __restrict__ tau, double2* __restrict__ out,
                                                   int64_t ld, int n_store) {
   const int G = blockIdx.x * blockDim.x + threadIdx.x;
-  const int atom = blockIdx.y;
+  const int a0 = blockIdx.y * kAtomGroup;
+  const int na = min(kAtomGroup, c.n_atoms - a0);
   if (G >= n_store) return;
-  const int t = atom_type_of(c, atom);
   const double kx = kv[4 * (int64_t)G + 0], ky = kv[4 * (int64_t)G + 1], kz = kv[4 * (int64_t)G + 2];
-  const double arg = kx * tau[3 * atom + 0] + ky * tau[3 * atom + 1] + kz * tau[3 * atom + 2];
-  double ps, pc;
-  sincos(arg, &ps, &pc);
-  const int64_t rowA = (int64_t)atom * 2 * c.n_l;
-  const int64_t rowB = rowA + c.n_l;
-  const double2* abt = ab + (int64_t)t * (c.l_max + 1) * n_pad + G;
+  double pc[kAtomGroup], ps[kAtomGroup];
+  const double2* abt[kAtomGroup];
+#pragma unroll
+  for (int q = 0; q < kAtomGroup; ++q) {
+    const int atom = a0 + (q < na ? q : 0);
+    const double arg = kx * tau[3 * atom + 0] + ky * tau[3 * atom + 1] + kz * tau[3 * atom + 2];
+    sincos(arg, &ps[q], &pc[q]);
+    abt[q] = ab + (int64_t)atom_type_of(c, atom) * (c.l_max + 1) * n_pad + G;
+  }
+  const int rows = 2 * c.n_l;
   int L = 0;
   for (int l = 0; l <= c.l_max; ++l) {
-    const double2 m = abt[(int64_t)l * n_pad];
-    // phase * (a|b): complex times real
-    const double par = pc * m.x, pai = ps * m.x;
-    const double pbr = pc * m.y, pbi = ps * m.y;
+    double par[kAtomGroup], pai[kAtomGroup], pbr[kAtomGroup], pbi[kAtomGroup];
+#pragma unroll
+    for (int q = 0; q < kAtomGroup; ++q) {
+      const double2 m = abt[q][(int64_t)l * n_pad];
+      // phase * (a|b): complex times real
+      par[q] = pc[q] * m.x; pai[q] = ps[q] * m.x;
+      pbr[q] = pc[q] * m.y; pbi[q] = ps[q] * m.y;
+    }
     for (int mm = 0; mm < 2 * l + 1; ++mm, ++L) {
       const double2 y = ang[(int64_t)L * n_pad + G];
-      out[(rowA + L) * ld + G] = make_double2(par * y.x - pai * y.y, par * y.y + pai * y.x);
-      out[(rowB + L) * ld + G] = make_double2(pbr * y.x - pbi * y.y, pbr * y.y + pbi * y.x);
+#pragma unroll
+      for (int q = 0; q < kAtomGroup; ++q) {
+        if (q < na) {
+          const int64_t rowA = (int64_t)(a0 + q) * rows + L;
+          out[rowA * ld + G] = make_double2(par[q] * y.x - pai[q] * y.y, par[q] * y.y + pai[q] * y.x);
+          out[(rowA + c.n_l) * ld + G] = make_double2(pbr[q] * y.x - pbi[q] * y.y, pbr[q] * y.y + pbi[q] * y.x);
+        }
+      }
     }
   }
 }
@@ -148,7 +167,7 @@ hipError_t launch_lambda(const CellArgs& c, const TypeConsts* consts, int K_pad,
 
 hipError_t launch_assemble(const CellArgs& c, int n_pad, const double2* ang, const double2* ab, const double* kv,
                            const double* tau, double2* out, int64_t ld, int n_store, hipStream_t s) {
-  dim3 grid((n_store + 255) / 256, c.n_atoms);
+  dim3 grid((n_store + 255) / 256, (c.n_atoms + kAtomGroup - 1) / kAtomGroup);
   hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, c, n_pad, ang, ab, kv, tau, out, ld, n_store);
   return hipGetLastError();
 }

@@ -191,18 +191,46 @@ __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, cons
       }
 }
 
-// Tile w of a k-point with nbr row blocks -> (row0, col0); two 128 x 64 tiles per super-tile.
-__device__ inline void tile_origin(int w, int nbr, int& row0, int& col0) {
+// Super-tile s -> (bi, sj) when the super-rows are taken in groups of gr: group by
+// group, and inside a group super-column by super-column, the group's rows with
+// bi <= sj.  Consecutive numbers then cover a compact gr-row patch, so the tiles an
+// XCD runs at one time share row strips and column strips.
+__device__ inline void grouped_decode(int s, int nb, int gr, int& bi, int& sj) {
+  int g0 = 0;
+  int rows = min(gr, nb);
+  for (;;) {
+    rows = min(gr, nb - g0);
+    const int ncol = nb - g0;
+    const int cnt = rows * (rows + 1) / 2 + (ncol - rows) * rows;
+    if (s < cnt || g0 + rows >= nb) break;
+    s -= cnt;
+    g0 += rows;
+  }
+  int c = 0;
+  for (;;) {
+    const int k = min(rows, c + 1);
+    if (s < k || g0 + c + 1 >= nb) break;
+    s -= k;
+    ++c;
+  }
+  sj = g0 + c;
+  bi = g0 + s;
+}
+
+// Tile w of a k-point with nbr row blocks -> (row0, col0); two 128 x 64 tiles per
+// super-tile.  gr = 0: row-major over the upper triangle; gr > 0: grouped order.
+__device__ inline void tile_origin(int w, int nbr, int gr, int& row0, int& col0) {
   int bi, sj;
-  tri_decode(w >> 1, nbr, bi, sj);
+  if (gr > 0) grouped_decode(w >> 1, nbr, gr, bi, sj);
+  else tri_decode(w >> 1, nbr, bi, sj);
   row0 = bi * BM;
   col0 = sj * BM + (w & 1) * BN;
 }
 
 __global__ void __launch_bounds__(NTHR, 1) k_hs_fp64(const d2* __restrict__ W, const d2* __restrict__ Y,
                                                      const double* __restrict__ lam, int K_pad, int n, int n_pad,
-                                                     int nbr, int num_wg, d2* __restrict__ H, d2* __restrict__ S,
-                                                     int64_t ldh) {
+                                                     int nbr, int num_wg, int gr, d2* __restrict__ H,
+                                                     d2* __restrict__ S, int64_t ldh) {
   __shared__ Smem sm;
   // dispatch is round-robin over XCDs: give XCD x the contiguous range of tile numbers
   const int x = blockIdx.x % kXcds;
@@ -210,14 +238,15 @@ __global__ void __launch_bounds__(NTHR, 1) k_hs_fp64(const d2* __restrict__ W, c
   xcd_range(x, num_wg, start, len);
   const int w = start + blockIdx.x / kXcds;
   int row0, col0;
-  tile_origin(w, nbr, row0, col0);
+  tile_origin(w, nbr, gr, row0, col0);
   if (col0 >= n) return;
   hs_tile(sm, W, Y, lam, K_pad, n, n_pad, row0, col0, H, S, ldh);
 }
 
 __global__ void __launch_bounds__(NTHR, 1) k_hs_fp64_batch(const d2* __restrict__ ws, const double* __restrict__ lam,
                                                            int K_pad, const BatchMeta* __restrict__ meta, int n_k,
-                                                           int total, d2* __restrict__ H, d2* __restrict__ S) {
+                                                           int total, int gr, d2* __restrict__ H,
+                                                           d2* __restrict__ S) {
   __shared__ Smem sm;
   const int x = blockIdx.x % kXcds;
   const int per_xcd = gridDim.x / kXcds;  // the grid is a multiple of the XCD count
@@ -233,7 +262,7 @@ __global__ void __launch_bounds__(NTHR, 1) k_hs_fp64_batch(const d2* __restrict_
     }
     const BatchMeta m = meta[lo];
     int row0, col0;
-    tile_origin(t - m.tile_start, m.nbr, row0, col0);
+    tile_origin(t - m.tile_start, m.nbr, gr, row0, col0);
     if (col0 >= m.n) continue;  // uniform across the workgroup
     hs_tile(sm, ws + m.w_off, ws + m.y_off, lam, K_pad, m.n, m.n_pad, row0, col0, H + m.out_off, S + m.out_off,
             m.n);
@@ -248,17 +277,17 @@ int hs_tiles(int n_pad) {
 }
 
 hipError_t launch_hs_fp64(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
-                          double2* H, double2* S, int64_t ldh, hipStream_t s) {
+                          int gr, double2* H, double2* S, int64_t ldh, hipStream_t s) {
   const int nbr = n_pad / BM;
   const int num_wg = hs_tiles(n_pad);  // two 128 x 64 tiles per upper-triangle 128 x 128 super-tile
   hipLaunchKernelGGL(k_hs_fp64, dim3(num_wg), dim3(NTHR), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad, n, n_pad,
-                     nbr, num_wg, (d2*)H, (d2*)S, ldh);
+                     nbr, num_wg, gr, (d2*)H, (d2*)S, ldh);
   return hipGetLastError();
 }
 
 hipError_t launch_hs_fp64_batch(const double2* ws, const double* lam, int K_pad, const BatchMeta* meta, int n_k,
-                                int total, int grid, double2* H, double2* S, hipStream_t s) {
-  hipLaunchKernelGGL(k_hs_fp64_batch, dim3(grid), dim3(NTHR), 0, s, (const d2*)ws, lam, K_pad, meta, n_k, total,
+                                int total, int grid, int gr, double2* H, double2* S, hipStream_t s) {
+  hipLaunchKernelGGL(k_hs_fp64_batch, dim3(grid), dim3(NTHR), 0, s, (const d2*)ws, lam, K_pad, meta, n_k, total, gr,
                      (d2*)H, (d2*)S);
   return hipGetLastError();
 }

@@ -1,0 +1,363 @@
+// Split-precision (Ozaki-style) form of the H/S contraction.
+//
+// Every operand column (one G: the vector over the stacked index k) is scaled
+// by a power of two 2^e_G with max_k |Re|, |Im| < 2^e_G, then cut into S
+// integer slices of 8 bits each:
+//     x / 2^e = sum_{s=0}^{S-1} q_s 2^{-8(s+1)} + r,   |q_0| <= 256, |q_s| <= 128, |r| <= 2^{-8S-1}
+// (round-to-nearest at each step, every step exact in FP64).  The slices are
+// integers of at most 8 significant bits, hence exact in BF16 and FP16.  The
+// product conj(L)^T R is then
+//     2^{e_L(G') + e_R(G)} sum_d 2^{-8(d+2)} sum_{s+t=d} conj(L_s)^T R_t,   d < S,
+// the pairs with s + t >= S being dropped (they are below the truncation).
+// Slice products run on v_mfma_f32_16x16x32_{bf16,f16}; each level d has its
+// own FP32 accumulator, which stays an exact integer while it sums at most 64
+// stacked rows (|Re| <= 64 * 2 * 2^16.8 < 2^24); it is converted and added into
+// the FP64 accumulator every 32 rows.  The level sums and the final scaling are
+// FP64.
+//
+// Slice layout (16-byte units of 8 consecutive k): unit ((p * NB + b) * QK + q) * 64 + g
+// holds plane p (= 2 s + {0: Re, 1: Im}), G = 64 b + g, k = 8 q .. 8 q + 7, so one
+// 32-row chunk of a 64-column block is 4 KB contiguous.
+#include "hs_internal.h"
+
+namespace hsb {
+
+namespace {
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef float f4 __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
+typedef _Float16 h8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+
+// ---- column scales -------------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_colmax(const d2* __restrict__ W, const d2* __restrict__ Y,
+                                                const double* __restrict__ lam, int K, int n_pad,
+                                                unsigned long long* __restrict__ mx) {
+  const int G = blockIdx.x * 256 + threadIdx.x;
+  if (G >= n_pad) return;
+  const int k0 = blockIdx.y * 512;
+  const int k1 = min(k0 + 512, K);
+  double mw = 0.0, ms = 0.0, my = 0.0;
+  for (int k = k0; k < k1; ++k) {
+    const d2 w = W[(int64_t)k * n_pad + G];
+    const d2 y = Y[(int64_t)k * n_pad + G];
+    const double aw = fmax(fabs(w.x), fabs(w.y));
+    mw = fmax(mw, aw);
+    ms = fmax(ms, lam[k] * aw);
+    my = fmax(my, fmax(fabs(y.x), fabs(y.y)));
+  }
+  // non-negative doubles order like their bit patterns
+  atomicMax(&mx[G], (unsigned long long)__double_as_longlong(mw));
+  atomicMax(&mx[n_pad + G], (unsigned long long)__double_as_longlong(ms));
+  atomicMax(&mx[2 * n_pad + G], (unsigned long long)__double_as_longlong(my));
+}
+
+__global__ void __launch_bounds__(256) k_zero_u64(unsigned long long* __restrict__ a, int count) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i < count) a[i] = 0ull;
+}
+
+// scale[i] = 2^e with max < 2^e (frexp), 1 for an all-zero column
+__global__ void __launch_bounds__(256) k_colscale(const unsigned long long* __restrict__ mx, int count,
+                                                  double* __restrict__ scale) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= count) return;
+  const double m = __longlong_as_double((long long)mx[i]);
+  int e = 0;
+  if (m > 0.0) (void)frexp(m, &e);
+  scale[i] = ldexp(1.0, e);
+}
+
+// ---- slicing ---------------------------------------------------------------------------
+template <typename T>
+__device__ inline unsigned short to_bits(double q);
+template <>
+__device__ inline unsigned short to_bits<__bf16>(double q) {
+  const __bf16 v = (__bf16)(float)q;  // q is an integer with |q| <= 256: exact
+  return __builtin_bit_cast(unsigned short, v);
+}
+template <>
+__device__ inline unsigned short to_bits<_Float16>(double q) {
+  const _Float16 v = (_Float16)(float)q;
+  return __builtin_bit_cast(unsigned short, v);
+}
+
+// One thread per (column G, 8-row group q); op 0: W, 1: lam W, 2: Y.
+template <typename T, int S>
+__global__ void __launch_bounds__(256) k_slice(const d2* __restrict__ X, const double* __restrict__ lam, int use_lam,
+                                               int K, int n_pad, int QK, const double* __restrict__ scale,
+                                               u4* __restrict__ out) {
+  const int g = threadIdx.x & 63;
+  const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int b = blockIdx.x;
+  const int G = b * 64 + g;
+  if (q >= QK) return;
+  const double inv = 1.0 / scale[G];  // a power of two: exact
+  double re[8], im[8];
+#pragma unroll
+  for (int j = 0; j < 8; ++j) {
+    const int k = q * 8 + j;
+    d2 v = d2{0.0, 0.0};
+    if (k < K) {
+      v = X[(int64_t)k * n_pad + G];
+      if (use_lam) v *= lam[k];
+    }
+    re[j] = v.x * inv;
+    im[j] = v.y * inv;
+  }
+  const int NB = n_pad / 64;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    unsigned short hr[8], hi[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) {
+      const double tr = re[j] * 256.0, ti = im[j] * 256.0;
+      const double qr = rint(tr), qi = rint(ti);
+      re[j] = tr - qr;
+      im[j] = ti - qi;
+      hr[j] = to_bits<T>(qr);
+      hi[j] = to_bits<T>(qi);
+    }
+    u4 ur, ui;
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      ur[w] = (unsigned)hr[2 * w] | ((unsigned)hr[2 * w + 1] << 16);
+      ui[w] = (unsigned)hi[2 * w] | ((unsigned)hi[2 * w + 1] << 16);
+    }
+    out[((int64_t)((2 * s) * NB + b) * QK + q) * 64 + g] = ur;
+    out[((int64_t)((2 * s + 1) * NB + b) * QK + q) * 64 + g] = ui;
+  }
+}
+
+// ---- slice contraction -----------------------------------------------------------------
+constexpr int SBM = 128, SBN = 64, SNT = 256;
+constexpr int kXcds = 8;
+
+__device__ inline void xcd_range(int x, int num, int& start, int& len) {
+  const int per = num / kXcds, rem = num % kXcds;
+  start = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
+  len = per + (x < rem ? 1 : 0);
+}
+
+__device__ inline void tri_decode(int s, int nb, int& bi, int& bj) {
+  const double bb = 2.0 * nb + 1.0;
+  int i = (int)((bb - sqrt(bb * bb - 8.0 * s)) * 0.5);
+  if (i < 0) i = 0;
+  if (i > nb - 1) i = nb - 1;
+  auto start = [nb](int r) { return r * nb - r * (r - 1) / 2; };
+  while (i > 0 && start(i) > s) --i;
+  while (i + 1 < nb && start(i + 1) <= s) ++i;
+  bi = i;
+  bj = i + (s - start(i));
+}
+
+template <typename T>
+__device__ inline f4 slice_mfma(u4 a, u4 b, f4 c);
+template <>
+__device__ inline f4 slice_mfma<__bf16>(u4 a, u4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf8, a), __builtin_bit_cast(bf8, b), c, 0, 0, 0);
+}
+template <>
+__device__ inline f4 slice_mfma<_Float16>(u4 a, u4 b, f4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_f16(__builtin_bit_cast(h8, a), __builtin_bit_cast(h8, b), c, 0, 0, 0);
+}
+
+// Output tile 128 (G') x 64 (G); 4 waves, each 64 x 32 (4 x 2 MFMA blocks).  Per
+// 32-row chunk the slices of both operand tiles sit in LDS (single buffer, the
+// next chunk prefetched into registers); the levels are taken one at a time,
+// each with its FP32 accumulators, which are added into the FP64 ones at the
+// end of the level (32 rows: exact).
+template <typename T, int S>
+__global__ void __launch_bounds__(SNT, 1) k_hs_split(const u4* __restrict__ Ls, const u4* __restrict__ Rs,
+                                                     const double* __restrict__ scL, const double* __restrict__ scR,
+                                                     int QK, int n, int n_pad, int nbr, int num_wg,
+                                                     d2* __restrict__ C) {
+  constexpr int P = 2 * S;                   // planes per operand
+  constexpr int LU = P * 2 * 4 * 64;         // left units per 32-row chunk
+  constexpr int RU = P * 4 * 64;             // right units per chunk
+  constexpr int PER = (LU + RU) / SNT;       // units staged per thread
+  static_assert((LU + RU) % SNT == 0, "staging map");
+  __shared__ u4 lds[LU + RU];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;   // rows wr*64, columns wc*32
+  const int x = blockIdx.x % kXcds;
+  int start, len;
+  xcd_range(x, num_wg, start, len);
+  const int w = start + blockIdx.x / kXcds;
+  int bi, sj;
+  tri_decode(w >> 1, nbr, bi, sj);
+  const int row0 = bi * SBM, col0 = sj * SBM + (w & 1) * SBN;
+  if (col0 >= n) return;
+  const int NB = n_pad / 64;
+  const int bL = row0 / 64, bR = col0 / 64;
+
+  d2 a64[4][2][4];  // [i][j][element] (re, im)
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) a64[i][j][e] = d2{0.0, 0.0};
+
+  u4 pf[PER];
+  const int nchunks = QK / 4;
+#define SP_GLOAD(q0)                                                                    \
+  do {                                                                                  \
+    _Pragma("unroll") for (int r = 0; r < PER; ++r) {                                   \
+      const int u = tid + SNT * r;                                                      \
+      if (u < LU) {                                                                     \
+        const int p = u >> 9, rem = u & 511;                                            \
+        pf[r] = Ls[((int64_t)(p * NB + bL + (rem >> 8)) * QK + (q0) + ((rem >> 6) & 3)) * 64 + (rem & 63)]; \
+      } else {                                                                          \
+        const int v = u - LU;                                                           \
+        const int p = v >> 8;                                                           \
+        pf[r] = Rs[((int64_t)(p * NB + bR) * QK + (q0) + ((v >> 6) & 3)) * 64 + (v & 63)]; \
+      }                                                                                 \
+    }                                                                                   \
+  } while (0)
+
+  SP_GLOAD(0);
+  const int qq = lane >> 4;
+  for (int c = 0; c < nchunks; ++c) {
+    __syncthreads();  // the previous chunk's reads are done
+#pragma unroll
+    for (int r = 0; r < PER; ++r) lds[tid + SNT * r] = pf[r];
+    __syncthreads();
+    if (c + 1 < nchunks) SP_GLOAD((c + 1) * 4);
+#pragma unroll 1
+    for (int d = 0; d < S; ++d) {
+      f4 are[4][2], aim[4][2];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          are[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+          aim[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+        }
+#pragma unroll 1
+      for (int s = 0; s <= d; ++s) {
+        const int t = d - s;
+        u4 lr[4], li[4], rr[2], ri[2];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          // row g' = wr*64 + i*16 + lane%16 of the tile: 64-block wr, column within it
+          const int gg = i * 16 + (lane & 15);
+          lr[i] = lds[(((2 * s) * 2 + wr) * 4 + qq) * 64 + gg];
+          li[i] = lds[(((2 * s + 1) * 2 + wr) * 4 + qq) * 64 + gg];
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          const int g = wc * 32 + j * 16 + (lane & 15);
+          rr[j] = lds[LU + ((2 * t) * 4 + qq) * 64 + g];
+          ri[j] = lds[LU + ((2 * t + 1) * 4 + qq) * 64 + g];
+        }
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) are[i][j] = slice_mfma<T>(lr[i], rr[j], are[i][j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) aim[i][j] = slice_mfma<T>(lr[i], ri[j], aim[i][j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+          for (int j = 0; j < 2; ++j) are[i][j] = slice_mfma<T>(li[i], ri[j], are[i][j]);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          const u4 ln = li[i] ^ u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+#pragma unroll
+          for (int j = 0; j < 2; ++j) aim[i][j] = slice_mfma<T>(ln, rr[j], aim[i][j]);
+        }
+      }
+      const double sc = __builtin_ldexp(1.0, -8 * (d + 2));
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j)
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            a64[i][j][e].x += sc * (double)are[i][j][e];
+            a64[i][j][e].y += sc * (double)aim[i][j][e];
+          }
+    }
+  }
+#undef SP_GLOAD
+  // D layout of the 16x16 f32 MFMA: lane l, element e -> row 4 (l/16) + e, column l%16
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int row = row0 + wr * 64 + i * 16 + 4 * (lane >> 4) + e;
+        const int col = col0 + wc * 32 + j * 16 + (lane & 15);
+        if (row < n && col < n && col >= row) {
+          const double sc = scL[row] * scR[col];
+          C[(int64_t)row * n + col] = a64[i][j][e] * sc;
+        }
+      }
+}
+
+template <typename T>
+hipError_t launch_slices_t(int S, const double2* X, const double* lam, int use_lam, int K, int n_pad, int QK,
+                           const double* scale, void* out, hipStream_t s) {
+  dim3 grid(n_pad / 64, (QK + 3) / 4);
+  switch (S) {
+    case 3: hipLaunchKernelGGL((k_slice<T, 3>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, (u4*)out); break;
+    case 4: hipLaunchKernelGGL((k_slice<T, 4>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, (u4*)out); break;
+    case 5: hipLaunchKernelGGL((k_slice<T, 5>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, (u4*)out); break;
+    case 6: hipLaunchKernelGGL((k_slice<T, 6>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, (u4*)out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_hs_split_t(int S, const void* L, const void* R, const double* scL, const double* scR, int QK,
+                             int n, int n_pad, double2* C, hipStream_t s) {
+  const int nbr = n_pad / SBM;
+  const int num_wg = nbr * (nbr + 1);
+  dim3 grid(num_wg), block(SNT);
+  switch (S) {
+    case 3: hipLaunchKernelGGL((k_hs_split<T, 3>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, (d2*)C); break;
+    case 4: hipLaunchKernelGGL((k_hs_split<T, 4>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, (d2*)C); break;
+    case 5: hipLaunchKernelGGL((k_hs_split<T, 5>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, (d2*)C); break;
+    case 6: hipLaunchKernelGGL((k_hs_split<T, 6>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, (d2*)C); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_split_scales(const double2* W, const double2* Y, const double* lam, int K, int n_pad,
+                               unsigned long long* mx, double* scale, hipStream_t s) {
+  const int count = 3 * n_pad;
+  hipLaunchKernelGGL(k_zero_u64, dim3((count + 255) / 256), dim3(256), 0, s, mx, count);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colmax, dim3(n_pad / 256 + (n_pad % 256 ? 1 : 0), (K + 511) / 512), dim3(256), 0, s,
+                     (const d2*)W, (const d2*)Y, lam, K, n_pad, mx);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_colscale, dim3((count + 255) / 256), dim3(256), 0, s, (const unsigned long long*)mx, count,
+                     scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_split_slices(int precision, int S, const double2* X, const double* lam, int use_lam, int K,
+                               int n_pad, int QK, const double* scale, void* out, hipStream_t s) {
+  if (precision == HSB_SPLIT_BF16) return launch_slices_t<__bf16>(S, X, lam, use_lam, K, n_pad, QK, scale, out, s);
+  return launch_slices_t<_Float16>(S, X, lam, use_lam, K, n_pad, QK, scale, out, s);
+}
+
+hipError_t launch_hs_split(int precision, int S, const void* L, const void* R, const double* scL, const double* scR,
+                           int QK, int n, int n_pad, double2* C, hipStream_t s) {
+  if (precision == HSB_SPLIT_BF16) return launch_hs_split_t<__bf16>(S, L, R, scL, scR, QK, n, n_pad, C, s);
+  return launch_hs_split_t<_Float16>(S, L, R, scL, scR, QK, n, n_pad, C, s);
+}
+
+}  // namespace hsb

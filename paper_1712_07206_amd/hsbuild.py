@@ -207,6 +207,14 @@ class HSBuilder:
                                       _ptr(H), _ptr(S), _ptr(ws), ws.numel(), _stream()), self._h)
         return H, S, out_off
 
+    def set_option(self, option: int, value: int) -> None:
+        N.check(N.lib().hsbuild_set_option(self._h, int(option), int(value)), self._h)
+
+    def get_option(self, option: int) -> int:
+        v = ctypes.c_int32()
+        N.check(N.lib().hsbuild_get_option(self._h, int(option), ctypes.byref(v)), self._h)
+        return int(v.value)
+
     def set_timing(self, enable: bool) -> None:
         N.check(N.lib().hsbuild_set_timing(self._h, 1 if enable else 0), self._h)
 

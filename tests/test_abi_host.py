@@ -190,3 +190,14 @@ def test_host_angular_matches_scipy_harmonics():
             for m in range(-l, l + 1):
                 ref = 1.7 * (1j ** l) * np.conj(special.sph_harm_y(l, m, theta, phi))
                 assert abs(got[l * l + l + m] - ref) <= 1e-14 * 1.7 * np.sqrt((2 * l + 1) / (4 * np.pi)), (v, l, m)
+
+
+def test_options_null_handle():
+    L = N.lib()
+    v = ctypes.c_int32()
+    assert L.hsbuild_set_option(None, N.HSB_OPT_TILE_GROUP, 4) == N.HSB_ERR_ARG
+    assert L.hsbuild_get_option(None, N.HSB_OPT_TILE_GROUP, ctypes.byref(v)) == N.HSB_ERR_ARG
+    assert L.hsbuild_set_timing(None, 1) == N.HSB_ERR_ARG
+    ms = (ctypes.c_double * 3)()
+    n = ctypes.c_int32()
+    assert L.hsbuild_stage_times(None, ms, ctypes.byref(n)) == N.HSB_ERR_ARG

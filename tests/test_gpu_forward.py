@@ -162,3 +162,38 @@ def test_stage_timing_records_calls():
     ms, calls = b.stage_times()
     assert calls == 3 and all(m > 0 for m in ms)
     b.set_timing(False)
+
+
+def test_tile_order_options_bitwise_identical():
+    """The tile-order option only changes scheduling: H and S are bitwise equal."""
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    case = make_case(1, n_g=1500)
+    b = HSBuilder.from_case(case)
+    g, tau, T = case_tensors(case)
+    ref = None
+    for gr in (0, 1, 3, 4, 64):
+        b.set_option(N.HSB_OPT_TILE_GROUP, gr)
+        assert b.get_option(N.HSB_OPT_TILE_GROUP) == gr
+        H, S = b.forward(case["k_frac"], g, tau, T)
+        torch.cuda.synchronize()
+        iu = np.triu_indices(1500)
+        cur = (H.cpu().numpy()[iu], S.cpu().numpy()[iu])
+        if ref is None:
+            ref = cur
+        else:
+            assert np.array_equal(ref[0], cur[0]) and np.array_equal(ref[1], cur[1]), gr
+    with pytest.raises(N.HSBuildError):
+        b.set_option(N.HSB_OPT_TILE_GROUP, -1)
+
+
+def test_autotuner_picks_and_caches(tmp_path):
+    from paper_1712_07206_amd import autotune
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    case = make_case(1, n_g=1200)
+    b = HSBuilder.from_case(case)
+    g, tau, T = case_tensors(case)
+    path = str(tmp_path / "tune.json")
+    res = autotune.tune(b, case["k_frac"], g, tau, T, groups=(0, 4), reps=1, path=path)
+    assert res["tile_group"] in (0, 4)
+    assert autotune.cached_options(b, 1200, path=path)["tile_group"] == res["tile_group"]

@@ -1,0 +1,100 @@
+"""Split-precision (Ozaki slice) forward: BF16 and FP16 slices on MFMA with
+FP32 accumulation, FP64 recombination.  Bar: relative Frobenius error
+<= 1e-10 for H and for S against the oracle (5 slices of 8 bits)."""
+import numpy as np
+import pytest
+import torch
+
+from flapw_cells import make_case
+from oracle import hs_oracle as o
+
+pytestmark = pytest.mark.gpu
+
+TOL_SPLIT = 1e-10
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a HIP device")
+    yield
+
+
+_cache = {}
+
+
+def oracle(idx, n_g):
+    if (idx, n_g) not in _cache:
+        case = make_case(idx, n_g=n_g)
+        _cache[(idx, n_g)] = (case, o.hs(case))
+    return _cache[(idx, n_g)]
+
+
+def _full(M):
+    return np.triu(M) + np.triu(M, 1).conj().T
+
+
+def _split(case, precision, slices, poison=True):
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    b = HSBuilder.from_case(case, precision=precision, n_slices=slices)
+    g, tau, T = case_tensors(case)
+    n = case["n_g"]
+    fill = complex(float("nan"), float("nan")) if poison else 0.0
+    H = torch.full((n, n), fill, dtype=torch.complex128, device="cuda")
+    S = H.clone()
+    b.forward(case["k_frac"], g, tau, T, H, S)
+    torch.cuda.synchronize()
+    return H.cpu().numpy(), S.cpu().numpy()
+
+
+def rel(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("prec_name", ["bf16", "fp16"])
+@pytest.mark.parametrize("idx,n_g", [(0, None), (1, 1000), (2, 3000)])
+def test_split_matches_oracle(prec_name, idx, n_g):
+    from paper_1712_07206_amd import HSB_SPLIT_BF16, HSB_SPLIT_FP16
+    prec = HSB_SPLIT_BF16 if prec_name == "bf16" else HSB_SPLIT_FP16
+    case, (Hr, Sr) = oracle(idx, n_g)
+    H, S = _split(case, prec, 5)
+    n = case["n_g"]
+    il = np.tril_indices(n, -1)
+    assert np.all(np.isnan(H[il])) and np.all(np.isnan(S[il])), "strict lower triangle was written"
+    eh, es = rel(_full(H), Hr), rel(_full(S), Sr)
+    print("split %s idx %d N_G %d: rel err H %.3e S %.3e" % (prec_name, idx, n, eh, es))
+    assert eh <= TOL_SPLIT and es <= TOL_SPLIT
+
+
+def test_split_error_falls_with_slices():
+    from paper_1712_07206_amd import HSB_SPLIT_BF16
+    case, (Hr, Sr) = oracle(1, 1000)
+    errs = []
+    for s in (3, 4, 5, 6):
+        H, S = _split(case, HSB_SPLIT_BF16, s, poison=False)
+        errs.append(max(rel(_full(H), Hr), rel(_full(S), Sr)))
+    print("bf16 error by slice count 3..6:", errs)
+    assert errs[0] > errs[1] > errs[2] > errs[3]
+    assert errs[0] < 1e-4 and errs[3] < 1e-12
+
+
+def test_split_full_size_against_fp64_path():
+    """Full-size workload (N_G = 12000, stacked width 30976) in the benchmark's
+    launch configuration: BF16, 5 slices, against the FP64 MFMA path."""
+    from paper_1712_07206_amd import HSB_SPLIT_BF16
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors, hermitian_full
+    case = make_case(2)
+    g, tau, T = case_tensors(case)
+    b64 = HSBuilder.from_case(case)
+    H64, S64 = b64.forward(case["k_frac"], g, tau, T)
+    H64, S64 = hermitian_full(H64), hermitian_full(S64)
+    b64.close()
+    del b64
+    torch.cuda.empty_cache()
+    bs = HSBuilder.from_case(case, precision=HSB_SPLIT_BF16, n_slices=5)
+    Hs, Ss = bs.forward(case["k_frac"], g, tau, T)
+    Hs, Ss = hermitian_full(Hs), hermitian_full(Ss)
+    eh = (torch.linalg.norm(Hs - H64) / torch.linalg.norm(H64)).item()
+    es = (torch.linalg.norm(Ss - S64) / torch.linalg.norm(S64)).item()
+    print("full-size split bf16 vs fp64: H %.3e S %.3e" % (eh, es))
+    assert eh <= TOL_SPLIT and es <= TOL_SPLIT
