@@ -147,9 +147,10 @@ def batch_leg(args) -> dict:
             "speedup": round(ms_seq / ms_graph, 4), "fp64_equiv_tflops": round(flops / (ms_graph * 1e-3) / 1e12, 4)}
 
 
-def recorded_traffic(workload: str):
+def recorded_traffic(workload: str, options: dict):
     """HBM bytes per launch of the contraction kernel from the committed
-    rocprofv3 PMC record, only if the kernel source is the one profiled."""
+    rocprofv3 PMC record, only if the kernel source and its options are the
+    ones profiled."""
     import hashlib
     root = os.path.dirname(os.path.abspath(__file__))
     try:
@@ -158,6 +159,8 @@ def recorded_traffic(workload: str):
     except (OSError, ValueError, KeyError):
         return None
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16") or rec.get("workload") != workload:
+        return None
+    if rec.get("options", {"waves": 4, "tile_group": 0}) != options:
         return None
     return rec["traffic_bytes"]
 
@@ -172,6 +175,7 @@ def main() -> int:
     ap.add_argument("--cpu-ng", type=int, default=5400, help="basis size of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-k-point batch leg")
+    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default contraction options)")
     ap.add_argument("--split-slices", type=int, default=5,
                     help="also time the BF16 split-precision path with this many slices (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -221,6 +225,16 @@ def main() -> int:
         if code != N.HSB_OK:
             raise N.HSBuildError(code, N.last_error(b._h))
 
+    tuned = None
+    if not args.no_tune:
+        from paper_1712_07206_amd import autotune
+        del ws
+        tuned = autotune.tune(b, case["k_frac"], g, tau, T, reps=1, path=None)
+        ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
+        log("autotuned contraction: waves %d, tile group %d (%s)"
+            % (tuned["waves"], tuned["tile_group"], ", ".join("%s %.1f ms" % kv for kv in tuned["candidates_ms"].items())))
+    options = {"waves": b.get_option(N.HSB_OPT_HS_WAVES), "tile_group": b.get_option(N.HSB_OPT_TILE_GROUP)}
+
     for i in range(args.warmup):
         step()
         torch.cuda.synchronize()
@@ -261,12 +275,13 @@ def main() -> int:
         "config": {"workload": case["name"], "n_atoms": n_at, "n_types": case["n_types"], "l_max": case["l_max"],
                    "n_l": n_l, "n_g": n, "k_c": k_c, "precision": "fp64", "flops_per_step": flops},
         "pct_fp64_mfma_peak": round(100.0 * tflops / FP64_MFMA_PEAK_TFLOPS, 2),
+        "contraction_options": options,
         "stages_ms": {"coefficients": round(stage_ms[0], 4), "t_products": round(stage_ms[1], 4),
                       "hs_contraction": round(stage_ms[2], 4)},
         "roofline": {"kernel": "k_hs_fp64", "bound": "mfma", "achieved": round(hs_tflops, 4),
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(hs_tflops / FP64_MFMA_PEAK_TFLOPS, 4),
-                     "traffic": recorded_traffic(case["name"]),
+                     "traffic": recorded_traffic(case["name"], options),
                      "algorithmic_flops_per_launch": flops_hs},
         "split_speedup": None,
     }

@@ -36,6 +36,7 @@ EXPORTS = ("hsbuild_create", "hsbuild_destroy", "hsbuild_workspace_bytes", "hsbu
            "hsbuild_set_option", "hsbuild_get_option")
 
 HSB_OPT_TILE_GROUP = 1
+HSB_OPT_HS_WAVES = 2
 
 
 class HsbConfig(ctypes.Structure):

@@ -17,7 +17,8 @@ import torch
 from . import _native as N
 
 DEFAULT_CACHE = os.environ.get("HSB_TUNE_CACHE", os.path.join(os.path.expanduser("~"), ".cache", "hsbuild_tune.json"))
-TILE_GROUPS = (0, 2, 4, 8, 16)
+TILE_GROUPS = (0, 4, 8)
+WAVES = (4, 8)
 
 
 def _key(builder, n_g: int, precision: int) -> str:
@@ -44,33 +45,39 @@ def cached_options(builder, n_g: int, precision: int = N.HSB_FP64, path: str = D
 def apply(builder, options: dict) -> None:
     if "tile_group" in options:
         builder.set_option(N.HSB_OPT_TILE_GROUP, int(options["tile_group"]))
+    if "waves" in options:
+        builder.set_option(N.HSB_OPT_HS_WAVES, int(options["waves"]))
 
 
 def tune(builder, k_frac, g, tau, T, precision: int = N.HSB_FP64, groups: Iterable[int] = TILE_GROUPS,
-         reps: int = 2, path: Optional[str] = DEFAULT_CACHE) -> dict:
-    """Times hsbuild_forward for each tile order and keeps the fastest (and
-    stores it in the cache when `path` is given)."""
+         waves: Iterable[int] = WAVES, reps: int = 2, path: Optional[str] = DEFAULT_CACHE) -> dict:
+    """Times hsbuild_forward for each (waves, tile order) and keeps the fastest
+    (and stores it in the cache when `path` is given)."""
     n = int(g.shape[0])
     H = torch.empty((n, n), dtype=torch.complex128, device="cuda")
     S = torch.empty((n, n), dtype=torch.complex128, device="cuda")
     wsb = builder.workspace_bytes(N.HSB_MODE_FORWARD, [n])
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     times = {}
-    for gr in groups:
-        builder.set_option(N.HSB_OPT_TILE_GROUP, gr)
-        builder.forward_raw(k_frac, n, g, tau, T, H, S, ws, wsb)  # warm
-        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-        e0.record()
-        for _ in range(reps):
-            code = builder.forward_raw(k_frac, n, g, tau, T, H, S, ws, wsb)
-            if code != N.HSB_OK:
-                raise N.HSBuildError(code, N.last_error(builder._h))
-        e1.record()
-        torch.cuda.synchronize()
-        times[gr] = e0.elapsed_time(e1) / reps
+    for wv in waves:
+        for gr in groups:
+            builder.set_option(N.HSB_OPT_HS_WAVES, wv)
+            builder.set_option(N.HSB_OPT_TILE_GROUP, gr)
+            builder.forward_raw(k_frac, n, g, tau, T, H, S, ws, wsb)  # warm
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                code = builder.forward_raw(k_frac, n, g, tau, T, H, S, ws, wsb)
+                if code != N.HSB_OK:
+                    raise N.HSBuildError(code, N.last_error(builder._h))
+            e1.record()
+            torch.cuda.synchronize()
+            times[(wv, gr)] = e0.elapsed_time(e1) / reps
     best = min(times, key=times.get)
-    builder.set_option(N.HSB_OPT_TILE_GROUP, best)
-    result = {"tile_group": best, "ms": times[best], "candidates_ms": {str(k): v for k, v in times.items()}}
+    builder.set_option(N.HSB_OPT_HS_WAVES, best[0])
+    builder.set_option(N.HSB_OPT_TILE_GROUP, best[1])
+    result = {"waves": best[0], "tile_group": best[1], "ms": times[best],
+              "candidates_ms": {"w%d_g%d" % k: v for k, v in times.items()}}
     if path:
         cache = _load(path)
         cache[_key(builder, n, precision)] = result

@@ -70,14 +70,15 @@ hipError_t launch_tprod(const CellArgs& c, const double2* T, const double2* W, d
                         hipStream_t s);
 // Upper triangles of H = W^H Y and S = W^H diag(lam) W over K_pad rows.
 // gr: tile order (0 row-major, > 0 super-rows taken in groups of gr).
+// waves: 4 (64 x 32 per wave) or 8 (32 x 32 per wave).
 hipError_t launch_hs_fp64(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
-                          int gr, double2* H, double2* S, int64_t ldh, hipStream_t s);
+                          int gr, int waves, double2* H, double2* S, int64_t ldh, hipStream_t s);
 
 // Number of 128 x 64 tiles the contraction covers for a padded basis size.
 int hs_tiles(int n_pad);
 // Persistent contraction over the tiles of every k-point in meta (grid: a multiple of 8).
 hipError_t launch_hs_fp64_batch(const double2* ws, const double* lam, int K_pad, const BatchMeta* meta, int n_k,
-                                int total, int grid, int gr, double2* H, double2* S, hipStream_t s);
+                                int total, int grid, int gr, int waves, double2* H, double2* S, hipStream_t s);
 
 // ---- split precision ----
 // Column scales 2^e (max_k |Re|, |Im| < 2^e) of W, lam W and Y: scale[0..3 n_pad); mx: 3 n_pad scratch.

@@ -23,6 +23,7 @@ struct hsbuild_s {
   int n_types = 0, n_atoms = 0, l_max = 0, n_l = 0, max_ng = 0;
   int precision = HSB_FP64, n_slices = 0;
   int tile_group = 0;  // HSB_OPT_TILE_GROUP
+  int hs_waves = 4;    // HSB_OPT_HS_WAVES
   double lattice[9];
   CellArgs cell;              // kfrac filled per call
   TypeConsts* consts = nullptr;  // pinned host copy, source of the per-call upload
@@ -434,7 +435,7 @@ int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32
   if ((rc = enqueue_operands(h, L, k_frac, g, tau, T, w, s))) return rc;
   if (h->precision == HSB_FP64) {
     rc = launched(h, launch_hs_fp64((const double2*)(w + L.W), (const double2*)(w + L.Y), (const double*)(w + L.lam),
-                                    L.K_pad, ng, L.n_pad, h->tile_group, (double2*)H, (double2*)S, ng, s),
+                                    L.K_pad, ng, L.n_pad, h->tile_group, h->hs_waves, (double2*)H, (double2*)S, ng, s),
                   "k_hs_fp64");
   } else {
     rc = enqueue_split(h, L, w, (double2*)H, (double2*)S, s);
@@ -567,8 +568,8 @@ int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t*
       if (e == hipSuccess) {
         const int grid = std::max(8, (h->num_cus / 8) * 8);  // one workgroup per CU, a multiple of 8
         e = launch_hs_fp64_batch((const double2*)w, (const double*)(w + B.lam), B.K_pad,
-                                 (const BatchMeta*)(w + B.meta), n_k, total, grid, h->tile_group, (double2*)H,
-                                 (double2*)S, cs);
+                                 (const BatchMeta*)(w + B.meta), n_k, total, grid, h->tile_group, h->hs_waves,
+                                 (double2*)H, (double2*)S, cs);
       }
       if (e != hipSuccess) rc = launched(h, e, "batched contraction");
     }
@@ -637,6 +638,11 @@ int hsbuild_set_option(hsbuild_t h, int32_t option, int32_t value) {
       if (value != h->tile_group) drop_graph(h);
       h->tile_group = value;
       return HSB_OK;
+    case HSB_OPT_HS_WAVES:
+      if (value != 4 && value != 8) return fail(h, HSB_ERR_ARG, "contraction waves must be 4 or 8 (got %d)", value);
+      if (value != h->hs_waves) drop_graph(h);
+      h->hs_waves = value;
+      return HSB_OK;
     default:
       return fail(h, HSB_ERR_ARG, "unknown option %d", option);
   }
@@ -647,6 +653,9 @@ int hsbuild_get_option(hsbuild_t h, int32_t option, int32_t* value) {
   switch (option) {
     case HSB_OPT_TILE_GROUP:
       *value = h->tile_group;
+      return HSB_OK;
+    case HSB_OPT_HS_WAVES:
+      *value = h->hs_waves;
       return HSB_OK;
     default:
       return fail(h, HSB_ERR_ARG, "unknown option %d", option);

@@ -11,9 +11,11 @@
 //
 // Complex FP64 on v_mfma_f64_16x16x4f64 (four real MFMAs per complex MAC):
 //   Re += Wr^T Yr + Wi^T Yi,  Im += Wr^T Yi - Wi^T Yr.
-// Workgroup: 256 threads = 4 waves, output tile 128 (G') x 64 (G) for both H
-// and S; each wave owns 64 x 32 of each (4 x 2 MFMA blocks, 16 accumulators
-// of 4 doubles per matrix).  K is staged 16 rows at a time through
+// Workgroup: output tile 128 (G') x 64 (G) for both H and S, either 4 waves
+// of 64 x 32 (4 x 2 MFMA blocks per matrix, accumulators in AGPRs, one wave per
+// SIMD) or 8 waves of 32 x 32 (two waves per SIMD, which hides the chunk
+// barriers); both issue the same MFMA sequence per output block, so they give
+// bitwise the same result.  K is staged 16 rows at a time through
 // double-buffered LDS with a register prefetch of the next chunk.  Only tiles
 // that touch the upper triangle are computed; they are numbered row-major
 // over 128 x 128 super-tiles and the numbering is dealt to the eight XCDs in
@@ -34,7 +36,7 @@ namespace {
 typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
-constexpr int BM = 128, BN = 64, BK = 16, NTHR = 256;
+constexpr int BM = 128, BN = 64, BK = 16;
 constexpr int kXcds = 8;
 
 // Start and length of XCD x's contiguous share of `num` items.
@@ -66,23 +68,28 @@ struct Smem {
 };
 
 // One 128 x 64 tile (rows row0.., columns col0..) of H and S, upper triangle stored.
+// WR x 2 waves; each wave owns (128/WR) x 32 of both outputs: MI x 2 MFMA blocks.
+template <int WR>
 __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, const d2* __restrict__ Y,
                                         const double* __restrict__ lam, int K_pad, int n, int n_pad, int row0,
                                         int col0, d2* __restrict__ H, d2* __restrict__ S, int64_t ldh) {
+  constexpr int NT = 64 * WR * 2;   // threads
+  constexpr int MI = BM / WR / 16;  // row blocks per wave
+  constexpr int PL = BK * BM / NT, PR = BK * BN / NT;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int wr = wave >> 1, wc = wave & 1;
 
-  // staging map: left chunk 16 x 128 (8 per thread), right chunks 16 x 64 (4 per thread)
-  d2 pl[8], pr[4], py[4];
-  double pm[4];
+  // staging map: left chunk 16 x 128 (PL per thread), right chunks 16 x 64 (PR per thread)
+  d2 pl[PL], pr[PR], py[PR];
+  double pm[PR];
 #define HS_GLOAD(kc)                                                             \
   do {                                                                           \
-    _Pragma("unroll") for (int i = 0; i < 8; ++i) {                              \
-      const int e = tid + NTHR * i;                                              \
+    _Pragma("unroll") for (int i = 0; i < PL; ++i) {                             \
+      const int e = tid + NT * i;                                                \
       pl[i] = W[(int64_t)((kc) + (e >> 7)) * n_pad + row0 + (e & 127)];          \
     }                                                                            \
-    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                              \
-      const int e = tid + NTHR * i;                                              \
+    _Pragma("unroll") for (int i = 0; i < PR; ++i) {                             \
+      const int e = tid + NT * i;                                                \
       const int64_t off = (int64_t)((kc) + (e >> 6)) * n_pad + col0 + (e & 63);  \
       pr[i] = W[off];                                                            \
       py[i] = Y[off];                                                            \
@@ -91,20 +98,20 @@ __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, cons
   } while (0)
 #define HS_LSTORE(b)                                 \
   do {                                               \
-    _Pragma("unroll") for (int i = 0; i < 8; ++i) {  \
-      const int e = tid + NTHR * i;                  \
+    _Pragma("unroll") for (int i = 0; i < PL; ++i) { \
+      const int e = tid + NT * i;                    \
       sm.L[b][e >> 7][e & 127] = pl[i];              \
     }                                                \
-    _Pragma("unroll") for (int i = 0; i < 4; ++i) {  \
-      const int e = tid + NTHR * i;                  \
+    _Pragma("unroll") for (int i = 0; i < PR; ++i) { \
+      const int e = tid + NT * i;                    \
       sm.R[b][e >> 6][e & 63] = pm[i] * pr[i];       \
       sm.Y[b][e >> 6][e & 63] = py[i];               \
     }                                                \
   } while (0)
 
-  d4 hr[4][2], hi[4][2], sr[4][2], si[4][2];
+  d4 hr[MI][2], hi[MI][2], sr[MI][2], si[MI][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       hr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
@@ -123,10 +130,10 @@ __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, cons
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
-      double ar[4], ai[4], an[4], yre[2], yim[2], wre[2], wim[2];
+      double ar[MI], ai[MI], an[MI], yre[2], yim[2], wre[2], wim[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const d2 a = sm.L[b][kk][wr * 64 + i * 16 + (lane & 15)];
+      for (int i = 0; i < MI; ++i) {
+        const d2 a = sm.L[b][kk][wr * (BM / WR) + i * 16 + (lane & 15)];
         ar[i] = a.x; ai[i] = a.y; an[i] = -a.y;
       }
 #pragma unroll
@@ -136,35 +143,35 @@ __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, cons
         yre[j] = yv.x; yim[j] = yv.y; wre[j] = wv.x; wim[j] = wv.y;
       }
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) hr[i][j] = MFMA(ar[i], yre[j], hr[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) hi[i][j] = MFMA(ar[i], yim[j], hi[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) sr[i][j] = MFMA(ar[i], wre[j], sr[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) si[i][j] = MFMA(ar[i], wim[j], si[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) hr[i][j] = MFMA(ai[i], yim[j], hr[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) hi[i][j] = MFMA(an[i], yre[j], hi[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) sr[i][j] = MFMA(ai[i], wim[j], sr[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) si[i][j] = MFMA(an[i], wre[j], si[i][j]);
     }
@@ -176,12 +183,12 @@ __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, cons
 
   // D layout of the 16x16 f64 MFMA: lane l, element q -> row l/16 + 4q, column l%16
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < MI; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = row0 + wr * 64 + i * 16 + (lane >> 4) + 4 * q;
+        const int row = row0 + wr * (BM / WR) + i * 16 + (lane >> 4) + 4 * q;
         const int col = col0 + wc * 32 + j * 16 + (lane & 15);
         if (row < n && col < n && col >= row) {
           const int64_t o = (int64_t)row * ldh + col;
@@ -227,7 +234,8 @@ __device__ inline void tile_origin(int w, int nbr, int gr, int& row0, int& col0)
   col0 = sj * BM + (w & 1) * BN;
 }
 
-__global__ void __launch_bounds__(NTHR, 1) k_hs_fp64(const d2* __restrict__ W, const d2* __restrict__ Y,
+template <int WR>
+__global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64(const d2* __restrict__ W, const d2* __restrict__ Y,
                                                      const double* __restrict__ lam, int K_pad, int n, int n_pad,
                                                      int nbr, int num_wg, int gr, d2* __restrict__ H,
                                                      d2* __restrict__ S, int64_t ldh) {
@@ -240,10 +248,11 @@ __global__ void __launch_bounds__(NTHR, 1) k_hs_fp64(const d2* __restrict__ W, c
   int row0, col0;
   tile_origin(w, nbr, gr, row0, col0);
   if (col0 >= n) return;
-  hs_tile(sm, W, Y, lam, K_pad, n, n_pad, row0, col0, H, S, ldh);
+  hs_tile<WR>(sm, W, Y, lam, K_pad, n, n_pad, row0, col0, H, S, ldh);
 }
 
-__global__ void __launch_bounds__(NTHR, 1) k_hs_fp64_batch(const d2* __restrict__ ws, const double* __restrict__ lam,
+template <int WR>
+__global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64_batch(const d2* __restrict__ ws, const double* __restrict__ lam,
                                                            int K_pad, const BatchMeta* __restrict__ meta, int n_k,
                                                            int total, int gr, d2* __restrict__ H,
                                                            d2* __restrict__ S) {
@@ -264,8 +273,8 @@ __global__ void __launch_bounds__(NTHR, 1) k_hs_fp64_batch(const d2* __restrict_
     int row0, col0;
     tile_origin(t - m.tile_start, m.nbr, gr, row0, col0);
     if (col0 >= m.n) continue;  // uniform across the workgroup
-    hs_tile(sm, ws + m.w_off, ws + m.y_off, lam, K_pad, m.n, m.n_pad, row0, col0, H + m.out_off, S + m.out_off,
-            m.n);
+    hs_tile<WR>(sm, ws + m.w_off, ws + m.y_off, lam, K_pad, m.n, m.n_pad, row0, col0, H + m.out_off,
+                S + m.out_off, m.n);
   }
 }
 
@@ -277,18 +286,26 @@ int hs_tiles(int n_pad) {
 }
 
 hipError_t launch_hs_fp64(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
-                          int gr, double2* H, double2* S, int64_t ldh, hipStream_t s) {
+                          int gr, int waves, double2* H, double2* S, int64_t ldh, hipStream_t s) {
   const int nbr = n_pad / BM;
   const int num_wg = hs_tiles(n_pad);  // two 128 x 64 tiles per upper-triangle 128 x 128 super-tile
-  hipLaunchKernelGGL(k_hs_fp64, dim3(num_wg), dim3(NTHR), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad, n, n_pad,
-                     nbr, num_wg, gr, (d2*)H, (d2*)S, ldh);
+  if (waves == 8)
+    hipLaunchKernelGGL(k_hs_fp64<4>, dim3(num_wg), dim3(512), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad, n, n_pad,
+                       nbr, num_wg, gr, (d2*)H, (d2*)S, ldh);
+  else
+    hipLaunchKernelGGL(k_hs_fp64<2>, dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad, n, n_pad,
+                       nbr, num_wg, gr, (d2*)H, (d2*)S, ldh);
   return hipGetLastError();
 }
 
 hipError_t launch_hs_fp64_batch(const double2* ws, const double* lam, int K_pad, const BatchMeta* meta, int n_k,
-                                int total, int grid, int gr, double2* H, double2* S, hipStream_t s) {
-  hipLaunchKernelGGL(k_hs_fp64_batch, dim3(grid), dim3(NTHR), 0, s, (const d2*)ws, lam, K_pad, meta, n_k, total, gr,
-                     (d2*)H, (d2*)S);
+                                int total, int grid, int gr, int waves, double2* H, double2* S, hipStream_t s) {
+  if (waves == 8)
+    hipLaunchKernelGGL(k_hs_fp64_batch<4>, dim3(grid), dim3(512), 0, s, (const d2*)ws, lam, K_pad, meta, n_k, total,
+                       gr, (d2*)H, (d2*)S);
+  else
+    hipLaunchKernelGGL(k_hs_fp64_batch<2>, dim3(grid), dim3(256), 0, s, (const d2*)ws, lam, K_pad, meta, n_k, total,
+                       gr, (d2*)H, (d2*)S);
   return hipGetLastError();
 }
 

@@ -48,6 +48,23 @@ def test_batch_equals_sequential_bitwise():
         assert np.array_equal(_block(Sc, off[k], n)[iu], s1.cpu().numpy()[iu]), k
 
 
+def test_batch_eight_wave_variant_bitwise():
+    from paper_1712_07206_amd import _native as N
+    case = make_batch_case(3, n_k=3)
+    b, tau, T, gl = _setup(case)
+    H1, S1, _ = b.batch(case["k_frac"], gl, tau, T)
+    H1, S1 = H1.clone(), S1.clone()
+    b.set_option(N.HSB_OPT_HS_WAVES, 8)
+    b.set_option(N.HSB_OPT_TILE_GROUP, 4)
+    H2, S2, off = b.batch(case["k_frac"], gl, tau, T)
+    torch.cuda.synchronize()
+    for k in range(3):
+        n = int(case["n_g"][k])
+        iu = np.triu_indices(n)
+        assert np.array_equal(_block(H1.cpu().numpy(), off[k], n)[iu], _block(H2.cpu().numpy(), off[k], n)[iu])
+        assert np.array_equal(_block(S1.cpu().numpy(), off[k], n)[iu], _block(S2.cpu().numpy(), off[k], n)[iu])
+
+
 def test_batch_graph_reuse_and_recapture():
     case = make_batch_case(3, n_k=3)
     b, tau, T, gl = _setup(case)

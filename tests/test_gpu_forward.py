@@ -172,9 +172,10 @@ def test_tile_order_options_bitwise_identical():
     b = HSBuilder.from_case(case)
     g, tau, T = case_tensors(case)
     ref = None
-    for gr in (0, 1, 3, 4, 64):
+    for wv, gr in ((4, 0), (4, 1), (4, 3), (8, 0), (8, 4), (4, 64)):
         b.set_option(N.HSB_OPT_TILE_GROUP, gr)
-        assert b.get_option(N.HSB_OPT_TILE_GROUP) == gr
+        b.set_option(N.HSB_OPT_HS_WAVES, wv)
+        assert b.get_option(N.HSB_OPT_TILE_GROUP) == gr and b.get_option(N.HSB_OPT_HS_WAVES) == wv
         H, S = b.forward(case["k_frac"], g, tau, T)
         torch.cuda.synchronize()
         iu = np.triu_indices(1500)
@@ -185,6 +186,8 @@ def test_tile_order_options_bitwise_identical():
             assert np.array_equal(ref[0], cur[0]) and np.array_equal(ref[1], cur[1]), gr
     with pytest.raises(N.HSBuildError):
         b.set_option(N.HSB_OPT_TILE_GROUP, -1)
+    with pytest.raises(N.HSBuildError):
+        b.set_option(N.HSB_OPT_HS_WAVES, 6)
 
 
 def test_autotuner_picks_and_caches(tmp_path):
@@ -194,6 +197,6 @@ def test_autotuner_picks_and_caches(tmp_path):
     b = HSBuilder.from_case(case)
     g, tau, T = case_tensors(case)
     path = str(tmp_path / "tune.json")
-    res = autotune.tune(b, case["k_frac"], g, tau, T, groups=(0, 4), reps=1, path=path)
-    assert res["tile_group"] in (0, 4)
+    res = autotune.tune(b, case["k_frac"], g, tau, T, groups=(0, 4), waves=(4, 8), reps=1, path=path)
+    assert res["tile_group"] in (0, 4) and res["waves"] in (4, 8)
     assert autotune.cached_options(b, 1200, path=path)["tile_group"] == res["tile_group"]
