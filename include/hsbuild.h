@@ -113,6 +113,14 @@ int hsbuild_coefficients(hsbuild_t h, const double k_frac[3], int32_t ng, const 
 int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
                     const void* T, void* H, void* S, void* ws, size_t ws_bytes, void* stream);
 
+/* H and S from caller-given matching coefficients, the input the paper's
+ * HSDLA algorithm starts from (Alg. 1, Alg. 3): coef is device complex128
+ * [n_atoms][2][N_L][ng] (index 0: A, 1: B, as hsbuild_coefficients writes
+ * it); T, H, S, workspace (HSB_MODE_FORWARD size) and precision as for
+ * hsbuild_forward. */
+int hsbuild_forward_coefficients(hsbuild_t h, int32_t ng, const void* coef, const void* T, void* H, void* S,
+                                 void* ws, size_t ws_bytes, void* stream);
+
 /* Adjoint of hsbuild_forward for a real loss L(H, S).  gH, gS: device
  * complex128 [ng][ng], the full Hermitian gradients dL/dRe H + i dL/dIm H
  * (likewise S).  Outputs: gT device complex128 [n_types][2N_L][2N_L] =

@@ -63,6 +63,8 @@ hipError_t launch_lambda(const CellArgs& c, const TypeConsts* consts, int K_pad,
 // out[(atom*2N_L + (A|B)*N_L + L) * ld + G] for G < n_store.
 hipError_t launch_assemble(const CellArgs& c, int n_pad, const double2* ang, const double2* ab, const double* kv,
                            const double* tau, double2* out, int64_t ld, int n_store, hipStream_t s);
+// dst[r][G] = src[r][G] for G < ng, 0 up to n_pad (rows r < rows; rows <= 65535).
+hipError_t launch_pack_rows(const double2* src, int ng, int rows, double2* dst, int n_pad, hipStream_t s);
 // rows [row0, row1) of a [*][ld] complex array set to zero.
 hipError_t launch_zero_rows(double2* a, int64_t ld, int row0, int row1, hipStream_t s);
 // Y_atom = T_type(atom) W_atom for every atom (rows of W/Y per atom: 2N_L).

@@ -444,6 +444,45 @@ int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32
   return rc;
 }
 
+int hsbuild_forward_coefficients(hsbuild_t h, int32_t ng, const void* coef, const void* T, void* H, void* S,
+                                 void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return HSB_ERR_ARG;
+  h->err.clear();
+  if (!coef || !T || !H || !S) return fail(h, HSB_ERR_ARG, "null coef, T, H or S");
+  if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
+  int rc = check_ng(h, ng);
+  if (rc) return rc;
+  const Layout L = make_layout(*h, ng, HSB_MODE_FORWARD);
+  if ((rc = check_ws(h, L, ws, ws_bytes))) return rc;
+  if ((rc = check_device(h))) return rc;
+  if (L.K > 65535 * 64) return fail(h, HSB_ERR_SHAPE, "stacked width too large for this entry point");
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  CellArgs c = h->cell;
+  double2* W = (double2*)(w + L.W);
+  double2* Y = (double2*)(w + L.Y);
+  hipError_t e = hipMemcpyAsync(w + L.consts, h->consts, sizeof(TypeConsts), hipMemcpyHostToDevice, s);
+  if ((rc = launched(h, e, "upload of type constants"))) return rc;
+  if ((rc = launched(h, launch_lambda(c, (const TypeConsts*)(w + L.consts), L.K_pad, (double*)(w + L.lam), s),
+                     "k_lambda")))
+    return rc;
+  for (int r0 = 0; r0 < L.K; r0 += 65535) {  // grid.y limit
+    const int rows = std::min(65535, L.K - r0);
+    if ((rc = launched(h, launch_pack_rows((const double2*)coef + (int64_t)r0 * ng, ng, rows,
+                                           W + (int64_t)r0 * L.n_pad, L.n_pad, s),
+                       "k_pack_rows")))
+      return rc;
+  }
+  if ((rc = launched(h, launch_zero_rows(W, L.n_pad, L.K, L.K_pad, s), "k_zero_rows"))) return rc;
+  if ((rc = launched(h, launch_zero_rows(Y, L.n_pad, L.K, L.K_pad, s), "k_zero_rows"))) return rc;
+  if ((rc = launched(h, launch_tprod(c, (const double2*)T, W, Y, L.n_pad, s), "k_tprod"))) return rc;
+  if (h->precision == HSB_FP64)
+    return launched(h, launch_hs_fp64(W, Y, (const double*)(w + L.lam), L.K_pad, ng, L.n_pad, h->tile_group,
+                                      h->hs_waves, (double2*)H, (double2*)S, ng, s),
+                    "k_hs_fp64");
+  return enqueue_split(h, L, w, (double2*)H, (double2*)S, s);
+}
+
 int hsbuild_backward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
                      const void* T, const void* gH, const void* gS, void* gT, double* gtau, void* ws,
                      size_t ws_bytes, void* stream) {

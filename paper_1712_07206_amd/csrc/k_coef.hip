@@ -145,6 +145,15 @@ __global__ void __launch_bounds__(256) k_assemble(CellArgs c, int n_pad, const d
   }
 }
 
+// Caller-given coefficients [rows][ng] into the padded layout [rows][n_pad] (zeros for G >= ng).
+__global__ void __launch_bounds__(256) k_pack_rows(const double2* __restrict__ src, int ng, int rows,
+                                                   double2* __restrict__ dst, int n_pad) {
+  const int G = blockIdx.x * blockDim.x + threadIdx.x;
+  const int r = blockIdx.y;
+  if (G >= n_pad || r >= rows) return;
+  dst[(int64_t)r * n_pad + G] = G < ng ? src[(int64_t)r * ng + G] : make_double2(0.0, 0.0);
+}
+
 __global__ void __launch_bounds__(256) k_zero_rows(double2* __restrict__ a, int64_t ld, int row0, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= count) return;
@@ -169,6 +178,12 @@ hipError_t launch_assemble(const CellArgs& c, int n_pad, const double2* ang, con
                            const double* tau, double2* out, int64_t ld, int n_store, hipStream_t s) {
   dim3 grid((n_store + 255) / 256, (c.n_atoms + kAtomGroup - 1) / kAtomGroup);
   hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, c, n_pad, ang, ab, kv, tau, out, ld, n_store);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_rows(const double2* src, int ng, int rows, double2* dst, int n_pad, hipStream_t s) {
+  hipLaunchKernelGGL(k_pack_rows, dim3(n_pad / 256 + (n_pad % 256 ? 1 : 0), rows), dim3(256), 0, s, src, ng, rows, dst,
+                     n_pad);
   return hipGetLastError();
 }
 

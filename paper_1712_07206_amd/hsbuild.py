@@ -207,6 +207,23 @@ class HSBuilder:
                                       _ptr(H), _ptr(S), _ptr(ws), ws.numel(), _stream()), self._h)
         return H, S, out_off
 
+    def forward_from_coefficients(self, coef: torch.Tensor, T: torch.Tensor, H: Optional[torch.Tensor] = None,
+                                  S: Optional[torch.Tensor] = None):
+        """H and S (upper triangles) from given coefficients [n_atoms][2][N_L][ng]."""
+        ng = int(coef.shape[-1])
+        coef = _dev(coef, torch.complex128, "coef", (self.n_atoms, 2, self.n_l, ng))
+        T = _dev(T, torch.complex128, "T", (self.n_types, 2 * self.n_l, 2 * self.n_l))
+        if H is None:
+            H = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+        if S is None:
+            S = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+        H = _dev(H, torch.complex128, "H", (ng, ng))
+        S = _dev(S, torch.complex128, "S", (ng, ng))
+        ws = self.workspace(N.HSB_MODE_FORWARD, [ng])
+        N.check(N.lib().hsbuild_forward_coefficients(self._h, ng, _ptr(coef), _ptr(T), _ptr(H), _ptr(S), _ptr(ws),
+                                                     ws.numel(), _stream()), self._h)
+        return H, S
+
     def set_option(self, option: int, value: int) -> None:
         N.check(N.lib().hsbuild_set_option(self._h, int(option), int(value)), self._h)
 
