@@ -176,6 +176,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-k-point batch leg")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default contraction options)")
+    ap.add_argument("--waves", type=int, default=0, help="contraction waves per workgroup (4 or 8; skips tuning)")
+    ap.add_argument("--tile-group", type=int, default=None, help="contraction tile order (skips tuning)")
     ap.add_argument("--split-slices", type=int, default=5,
                     help="also time the BF16 split-precision path with this many slices (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -226,7 +228,12 @@ def main() -> int:
             raise N.HSBuildError(code, N.last_error(b._h))
 
     tuned = None
-    if not args.no_tune:
+    if args.waves or args.tile_group is not None:
+        if args.waves:
+            b.set_option(N.HSB_OPT_HS_WAVES, args.waves)
+        if args.tile_group is not None:
+            b.set_option(N.HSB_OPT_TILE_GROUP, args.tile_group)
+    elif not args.no_tune:
         from paper_1712_07206_amd import autotune
         del ws
         tuned = autotune.tune(b, case["k_frac"], g, tau, T, reps=1, path=None)
