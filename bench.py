@@ -147,6 +147,41 @@ def batch_leg(args) -> dict:
             "speedup": round(ms_seq / ms_graph, 4), "fp64_equiv_tflops": round(flops / (ms_graph * 1e-3) / 1e12, 4)}
 
 
+def adjoint_leg(args) -> dict:
+    """hsbuild_backward on the differentiation workload (64 atoms, l_max 10,
+    N_G 6000; Hermitian W, V as dL/dH, dL/dS): time per call and FP64 rate for
+    F_adj = 32 k_c N_G^2 + 64 N_atoms N_L^2 N_G."""
+    import torch
+
+    from flapw_cells import make_case
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+
+    case = make_case(4)
+    n, n_at, n_l = case["n_g"], case["n_atoms"], case["n_l"]
+    b = HSBuilder.from_case(case)
+    g, tau, T = case_tensors(case)
+    gH = torch.as_tensor(case["W"], device="cuda")
+    gS = torch.as_tensor(case["V"], device="cuda")
+    gT, gtau = b.backward(case["k_frac"], g, tau, T, gH, gS)  # warm, allocates the workspace
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(1, args.steps)
+    e0.record()
+    for _ in range(reps):
+        b.backward(case["k_frac"], g, tau, T, gH, gS, gT, gtau)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    flops = 32.0 * n_at * n_l * n * n + 64.0 * n_at * n_l * n_l * n
+    log("adjoint %s: %.3f ms per backward, %.2f TFLOP/s" % (case["name"], ms, flops / (ms * 1e-3) / 1e12))
+    b.close()
+    del gH, gS, gT, gtau
+    torch.cuda.empty_cache()
+    return {"workload": case["name"], "n_g": n, "ms_per_backward": round(ms, 4), "flops": flops,
+            "fp64_tflops": round(flops / (ms * 1e-3) / 1e12, 4)}
+
+
 def recorded_traffic(workload: str, options: dict):
     """HBM bytes per launch of the contraction kernel from the committed
     rocprofv3 PMC record, only if the kernel source and its options are the
@@ -175,6 +210,7 @@ def main() -> int:
     ap.add_argument("--cpu-ng", type=int, default=5400, help="basis size of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-k-point batch leg")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default contraction options)")
     ap.add_argument("--waves", type=int, default=0, help="contraction waves per workgroup (4 or 8; skips tuning)")
     ap.add_argument("--tile-group", type=int, default=None, help="contraction tile order (skips tuning)")
@@ -297,6 +333,8 @@ def main() -> int:
         result["split_speedup"] = result["split"]["speedup"]
     del H, S, ws
     torch.cuda.empty_cache()
+    if not args.no_adjoint:
+        result["adjoint"] = adjoint_leg(args)
     if not args.no_batch:
         result["batch"] = batch_leg(args)
         result["batch_speedup"] = result["batch"]["speedup"]
