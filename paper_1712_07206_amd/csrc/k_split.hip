@@ -74,7 +74,7 @@ template <typename T>
 __device__ inline unsigned short to_bits(double q);
 template <>
 __device__ inline unsigned short to_bits<__bf16>(double q) {
-  const __bf16 v = (__bf16)(float)q;  // q is an integer with |q| <= 256: exact
+  const __bf16 v = (__bf16)(float)q;  // q: an integer |q| <= 256 times a power of two: exact
   return __builtin_bit_cast(unsigned short, v);
 }
 template <>
@@ -87,7 +87,7 @@ __device__ inline unsigned short to_bits<_Float16>(double q) {
 template <typename T, int S>
 __global__ void __launch_bounds__(256) k_slice(const d2* __restrict__ X, const double* __restrict__ lam, int use_lam,
                                                int K, int n_pad, int QK, const double* __restrict__ scale,
-                                               u4* __restrict__ out) {
+                                               int prescale, u4* __restrict__ out) {
   const int g = threadIdx.x & 63;
   const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int b = blockIdx.x;
@@ -116,8 +116,10 @@ __global__ void __launch_bounds__(256) k_slice(const d2* __restrict__ X, const d
       const double qr = rint(tr), qi = rint(ti);
       re[j] = tr - qr;
       im[j] = ti - qi;
-      hr[j] = to_bits<T>(qr);
-      hi[j] = to_bits<T>(qi);
+      // pre-scaled slices carry their level weight 2^{-8s} (exact: a power of two)
+      const double w = prescale ? __builtin_ldexp(1.0, -8 * s) : 1.0;
+      hr[j] = to_bits<T>(qr * w);
+      hi[j] = to_bits<T>(qi * w);
     }
     u4 ur, ui;
 #pragma unroll
@@ -301,15 +303,150 @@ __global__ void __launch_bounds__(SNT, 1) k_hs_split(const u4* __restrict__ Ls, 
       }
 }
 
+// ---- BF16 contraction with folded levels (pre-scaled slices) ------------------------------
+// Slice s is stored as q_s 2^{-8s}, so the product of pair (s, t) already carries
+// its weight 2^{-8(s+t)}.  Four FP32 accumulator sets: levels 0, 1 and 2 each in
+// their own set, where every partial sum over 64 rows is an exact multiple of
+// 2^{-8d} below 2^{24-8d} (|level-2 row term| <= 2 (2^15 + 2^14 + 2^15) 2^-16), and
+// all levels >= 3 in one set whose FP32 rounding is below 2^-40 of the leading
+// term.  The sets are added into FP64 every 64 rows.  MFMA 32x32x16 (lane l: row
+// l%32, k 8(l/32)..+7; output lane l, element r: column l%32, row 8(r/4) + 4(l/32) +
+// r%4).  16-row chunks of the slices are copied straight into double-buffered LDS
+// with global_load_lds_dwordx4 (no staging registers).  8 waves of 32 x 32 (two per
+// SIMD) cover the 128 x 64 tile.
+typedef float f16v __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+template <int S>
+__global__ void __launch_bounds__(512, 1) k_hs_split2(const u4* __restrict__ Ls, const u4* __restrict__ Rs,
+                                                      const double* __restrict__ scL, const double* __restrict__ scR,
+                                                      int QK, int n, int n_pad, int nbr, int num_wg,
+                                                      d2* __restrict__ C) {
+  constexpr int P = 2 * S;        // planes per operand
+  constexpr int CU = 384 * P;     // units per chunk: left P*2*2*64, right P*2*64
+  constexpr int NI = 6 * P;       // 64-unit copies per chunk
+  __shared__ u4 lds[2][CU];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;  // rows wr*32, columns wc*32 (8 waves: 4 x 2)
+  const int x = blockIdx.x % kXcds;
+  int start, len;
+  xcd_range(x, num_wg, start, len);
+  const int w = start + blockIdx.x / kXcds;
+  int bi, sj;
+  tri_decode(w >> 1, nbr, bi, sj);
+  const int row0 = bi * SBM, col0 = sj * SBM + (w & 1) * SBN;
+  if (col0 >= n) return;
+  const int NB = n_pad / 64;
+  const int bL = row0 / 64, bR = col0 / 64;
+  const int nchunks = QK / 2;
+
+  // copy j of chunk c: left (p, b, q) for j < 4P, right (p, q) after; 8 waves share the copies
+  auto issue = [&](int c, int buf) {
+    for (int j = wave; j < NI; j += 8) {
+      const u4* src;
+      int dst;
+      if (j < 4 * P) {
+        const int p = j >> 2, b = (j >> 1) & 1, qq = j & 1;
+        src = Ls + ((int64_t)(p * NB + bL + b) * QK + 2 * c + qq) * 64;
+        dst = ((p * 2 + b) * 2 + qq) * 64;
+      } else {
+        const int jj = j - 4 * P;
+        const int p = jj >> 1, qq = jj & 1;
+        src = Rs + ((int64_t)(p * NB + bR) * QK + 2 * c + qq) * 64;
+        dst = 256 * P + (p * 2 + qq) * 64;
+      }
+      __builtin_amdgcn_global_load_lds((const void*)(src + lane), (lds_ptr)(&lds[buf][dst]), 16, 0, 0);
+    }
+  };
+
+  f16v acc[4][2];  // [set][re, im]
+  double a64[2][16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) a64[0][r] = a64[1][r] = 0.0;
+#pragma unroll
+  for (int st = 0; st < 4; ++st)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[st][0][r] = acc[st][1][r] = 0.f;
+
+  issue(0, 0);
+  const int q = lane >> 5, g32 = lane & 31;
+  // row block of this wave: rows wr*32 .. of the 128-row tile = 64-block (wr >> 1), offset (wr & 1) * 32
+  const int lrow = ((wr >> 1) * 2 + q) * 64 + (wr & 1) * 32 + g32;  // + p * 256 selects the plane
+  const int rcol = 256 * P + q * 64 + wc * 32 + g32;                 // + p * 128 selects the plane
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of chunk c have landed
+    __syncthreads();                // everyone's have, and buffer buf^1 is free
+    if (c + 1 < nchunks) issue(c + 1, buf ^ 1);
+    const u4* B = lds[buf];
+#pragma unroll
+    for (int si = 0; si < S; ++si) {
+      const u4 lr = B[lrow + (2 * si) * 256];
+      const u4 li = B[lrow + (2 * si + 1) * 256];
+      const u4 ln = li ^ u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
+#pragma unroll
+      for (int ti = 0; ti < S - si; ++ti) {
+        const int st = si + ti < 3 ? si + ti : 3;
+        const bf8 brr = __builtin_bit_cast(bf8, B[rcol + (2 * ti) * 128]);
+        const bf8 bri = __builtin_bit_cast(bf8, B[rcol + (2 * ti + 1) * 128]);
+        acc[st][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, lr), brr, acc[st][0], 0, 0, 0);
+        acc[st][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, lr), bri, acc[st][1], 0, 0, 0);
+        acc[st][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, li), bri, acc[st][0], 0, 0, 0);
+        acc[st][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, ln), brr, acc[st][1], 0, 0, 0);
+      }
+    }
+    if ((c & 3) == 3 || c + 1 == nchunks) {  // 64 rows: the exact sets are still exact
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        double sre = 0.0, sim = 0.0;
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+          sre += (double)acc[st][0][r];
+          sim += (double)acc[st][1][r];
+          acc[st][0][r] = 0.f;
+          acc[st][1][r] = 0.f;
+        }
+        a64[0][r] += 0x1p-16 * sre;
+        a64[1][r] += 0x1p-16 * sim;
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int row = row0 + wr * 32 + 8 * (r >> 2) + 4 * q + (r & 3);
+    const int col = col0 + wc * 32 + g32;
+    if (row < n && col < n && col >= row) {
+      const double sc = scL[row] * scR[col];
+      C[(int64_t)row * n + col] = d2{a64[0][r] * sc, a64[1][r] * sc};
+    }
+  }
+}
+
+hipError_t launch_hs_split2(int S, const void* L, const void* R, const double* scL, const double* scR, int QK, int n,
+                            int n_pad, double2* C, hipStream_t s) {
+  const int nbr = n_pad / SBM;
+  const int num_wg = nbr * (nbr + 1);
+  dim3 grid(num_wg), block(512);
+  switch (S) {
+    case 3: hipLaunchKernelGGL((k_hs_split2<3>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, (d2*)C); break;
+    case 4: hipLaunchKernelGGL((k_hs_split2<4>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, (d2*)C); break;
+    case 5: hipLaunchKernelGGL((k_hs_split2<5>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, (d2*)C); break;
+    case 6: hipLaunchKernelGGL((k_hs_split2<6>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, (d2*)C); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 template <typename T>
 hipError_t launch_slices_t(int S, const double2* X, const double* lam, int use_lam, int K, int n_pad, int QK,
-                           const double* scale, void* out, hipStream_t s) {
+                           const double* scale, int prescale, void* out, hipStream_t s) {
   dim3 grid(n_pad / 64, (QK + 3) / 4);
   switch (S) {
-    case 3: hipLaunchKernelGGL((k_slice<T, 3>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, (u4*)out); break;
-    case 4: hipLaunchKernelGGL((k_slice<T, 4>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, (u4*)out); break;
-    case 5: hipLaunchKernelGGL((k_slice<T, 5>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, (u4*)out); break;
-    case 6: hipLaunchKernelGGL((k_slice<T, 6>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, (u4*)out); break;
+    case 3: hipLaunchKernelGGL((k_slice<T, 3>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, prescale, (u4*)out); break;
+    case 4: hipLaunchKernelGGL((k_slice<T, 4>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, prescale, (u4*)out); break;
+    case 5: hipLaunchKernelGGL((k_slice<T, 5>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, prescale, (u4*)out); break;
+    case 6: hipLaunchKernelGGL((k_slice<T, 6>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, prescale, (u4*)out); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -350,13 +487,14 @@ hipError_t launch_split_scales(const double2* W, const double2* Y, const double*
 
 hipError_t launch_split_slices(int precision, int S, const double2* X, const double* lam, int use_lam, int K,
                                int n_pad, int QK, const double* scale, void* out, hipStream_t s) {
-  if (precision == HSB_SPLIT_BF16) return launch_slices_t<__bf16>(S, X, lam, use_lam, K, n_pad, QK, scale, out, s);
-  return launch_slices_t<_Float16>(S, X, lam, use_lam, K, n_pad, QK, scale, out, s);
+  // BF16 slices are stored pre-scaled for the level-folding contraction
+  if (precision == HSB_SPLIT_BF16) return launch_slices_t<__bf16>(S, X, lam, use_lam, K, n_pad, QK, scale, 1, out, s);
+  return launch_slices_t<_Float16>(S, X, lam, use_lam, K, n_pad, QK, scale, 0, out, s);
 }
 
 hipError_t launch_hs_split(int precision, int S, const void* L, const void* R, const double* scL, const double* scR,
                            int QK, int n, int n_pad, double2* C, hipStream_t s) {
-  if (precision == HSB_SPLIT_BF16) return launch_hs_split_t<__bf16>(S, L, R, scL, scR, QK, n, n_pad, C, s);
+  if (precision == HSB_SPLIT_BF16) return launch_hs_split2(S, L, R, scL, scR, QK, n, n_pad, C, s);
   return launch_hs_split_t<_Float16>(S, L, R, scL, scR, QK, n, n_pad, C, s);
 }
 
