@@ -195,7 +195,7 @@ def recorded_traffic(workload: str, options: dict):
         return None
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16") or rec.get("workload") != workload:
         return None
-    if rec.get("options", {"waves": 4, "tile_group": 0}) != options:
+    if rec.get("options") != options:
         return None
     return rec["traffic_bytes"]
 

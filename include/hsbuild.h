@@ -156,7 +156,7 @@ int hsbuild_stage_times(hsbuild_t h, double* ms_avg, int32_t* n_calls);
  * super-rows taken g at a time, column by column (0..64; default 0).
  * HSB_OPT_HS_WAVES: waves per workgroup of the FP64 contraction, 4 (64 x 32
  * outputs per wave, one wave per SIMD) or 8 (32 x 32 per wave, two per SIMD);
- * default 4.  Setting an option drops a captured batch graph. */
+ * default 8.  Setting an option drops a captured batch graph. */
 enum { HSB_OPT_TILE_GROUP = 1, HSB_OPT_HS_WAVES = 2 };
 int hsbuild_set_option(hsbuild_t h, int32_t option, int32_t value);
 int hsbuild_get_option(hsbuild_t h, int32_t option, int32_t* value);

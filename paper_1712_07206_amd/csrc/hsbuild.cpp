@@ -23,7 +23,7 @@ struct hsbuild_s {
   int n_types = 0, n_atoms = 0, l_max = 0, n_l = 0, max_ng = 0;
   int precision = HSB_FP64, n_slices = 0;
   int tile_group = 0;  // HSB_OPT_TILE_GROUP
-  int hs_waves = 4;    // HSB_OPT_HS_WAVES
+  int hs_waves = 8;    // HSB_OPT_HS_WAVES
   double lattice[9];
   CellArgs cell;              // kfrac filled per call
   TypeConsts* consts = nullptr;  // pinned host copy, source of the per-call upload

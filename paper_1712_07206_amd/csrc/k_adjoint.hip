@@ -10,7 +10,8 @@
 // (A and B of Eq. 2) and H, S are the sums of Eqs. 4-5.  Nothing is kept
 // from the forward: W and Y are rebuilt by the same kernels.
 //
-//   k_pgemm        P_H and P_S in one pass (shared left operand W), FP64 MFMA
+//   k_pgemm        P_H and P_S in one pass (shared left operand W), FP64 MFMA,
+//                  8 waves, double-buffered LDS
 //   k_gradT        per-atom partials P_H,a W_a^H (FP64 MFMA), one workgroup per
 //                  (64 x 64 tile, atom); k_gradT_reduce sums the atoms of a type
 //                  in a fixed order (deterministic)
@@ -28,24 +29,25 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 #define MFMA(a, b, c) __builtin_amdgcn_mfma_f64_16x16x4f64((a), (b), (c), 0, 0, 0)
 
 // ---- P_H = W gH, P_S = W gS -------------------------------------------------------------
-// Tile 128 (k) x 64 (G) for both outputs; 4 waves of 64 x 32.  The contraction runs
-// over G' in chunks of 16.  W is staged transposed (sA[G'][k], padded row) so the
-// A fragment (16 k rows at one G') is a contiguous LDS read.
-constexpr int PM = 128, PN = 64, PK = 16;
+// Tile 128 (k) x 64 (G) for both outputs; 8 waves of 32 x 32 (two per SIMD).  The
+// contraction runs over G' in chunks of 16 through double-buffered LDS with a
+// register prefetch of the next chunk.  W is staged transposed (sA[G'][k], padded
+// row) so the A fragment (16 k rows at one G') is a contiguous LDS read.
+constexpr int PM = 128, PN = 64, PK = 16, PT = 512;
 
-__global__ void __launch_bounds__(256, 1) k_pgemm(const d2* __restrict__ W, const d2* __restrict__ gH,
-                                                  const d2* __restrict__ gS, int K_pad, int n, int n_pad,
-                                                  d2* __restrict__ PH, d2* __restrict__ PS) {
-  __shared__ d2 sA[PK][PM + 1];
-  __shared__ d2 sH[PK][PN];
-  __shared__ d2 sS[PK][PN];
+__global__ void __launch_bounds__(PT, 1) k_pgemm(const d2* __restrict__ W, const d2* __restrict__ gH,
+                                                 const d2* __restrict__ gS, int K_pad, int n, int n_pad,
+                                                 d2* __restrict__ PH, d2* __restrict__ PS) {
+  __shared__ d2 sA[2][PK][PM + 1];
+  __shared__ d2 sH[2][PK][PN];
+  __shared__ d2 sS[2][PK][PN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;
+  const int wr = wave >> 1, wc = wave & 1;  // rows wr*32, columns wc*32
   const int col0 = blockIdx.x * PN;
   const int row0 = blockIdx.y * PM;
-  d4 hr[4][2], hi[4][2], sr[4][2], si[4][2];
+  d4 hr[2][2], hi[2][2], sr[2][2], si[2][2];
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) {
       hr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
@@ -53,87 +55,105 @@ __global__ void __launch_bounds__(256, 1) k_pgemm(const d2* __restrict__ W, cons
       sr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
       si[i][j] = d4{0.0, 0.0, 0.0, 0.0};
     }
-  for (int kc = 0; kc < n_pad; kc += PK) {
-#pragma unroll
-    for (int i = 0; i < 8; ++i) {
-      const int e = tid + 256 * i;
-      const int c = e & 15, r = e >> 4;
-      d2 v = d2{0.0, 0.0};
-      if (row0 + r < K_pad) v = W[(int64_t)(row0 + r) * n_pad + kc + c];
-      sA[c][r] = v;
-    }
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      const int e = tid + 256 * i;
-      const int r = e >> 6, c = e & 63;
-      const int gp = kc + r, gc = col0 + c;
-      d2 vh = d2{0.0, 0.0}, vs = d2{0.0, 0.0};
-      if (gp < n && gc < n) {
-        vh = gH[(int64_t)gp * n + gc];
-        vs = gS[(int64_t)gp * n + gc];
-      }
-      sH[r][c] = vh;
-      sS[r][c] = vs;
-    }
-    __syncthreads();
+  // staging: A 16 x 128 (4 per thread, transposed on store), gH and gS 16 x 64 (2 each)
+  d2 pa[4], ph[2], ps[2];
+#define PG_LOAD(kc)                                                                   \
+  do {                                                                                \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                   \
+      const int e = tid + PT * i;                                                     \
+      const int c = e & 15, r = e >> 4;                                               \
+      pa[i] = row0 + r < K_pad ? W[(int64_t)(row0 + r) * n_pad + (kc) + c] : d2{0.0, 0.0}; \
+    }                                                                                 \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                   \
+      const int e = tid + PT * i;                                                     \
+      const int r = e >> 6, c = e & 63;                                               \
+      const int gp = (kc) + r, gc = col0 + c;                                         \
+      const bool ok = gp < n && gc < n;                                               \
+      ph[i] = ok ? gH[(int64_t)gp * n + gc] : d2{0.0, 0.0};                           \
+      ps[i] = ok ? gS[(int64_t)gp * n + gc] : d2{0.0, 0.0};                           \
+    }                                                                                 \
+  } while (0)
+#define PG_STORE(b)                                    \
+  do {                                                 \
+    _Pragma("unroll") for (int i = 0; i < 4; ++i) {    \
+      const int e = tid + PT * i;                      \
+      sA[b][e & 15][e >> 4] = pa[i];                   \
+    }                                                  \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i) {    \
+      const int e = tid + PT * i;                      \
+      sH[b][e >> 6][e & 63] = ph[i];                   \
+      sS[b][e >> 6][e & 63] = ps[i];                   \
+    }                                                  \
+  } while (0)
+
+  const int nchunks = n_pad / PK;
+  PG_LOAD(0);
+  PG_STORE(0);
+  __syncthreads();
+  for (int ch = 0; ch < nchunks; ++ch) {
+    const int b = ch & 1;
+    if (ch + 1 < nchunks) PG_LOAD((ch + 1) * PK);
 #pragma unroll
     for (int ks = 0; ks < PK / 4; ++ks) {
       const int kk = ks * 4 + (lane >> 4);
-      double ar[4], ai[4], an[4], hre[2], him[2], sre[2], sim[2];
+      double ar[2], ai[2], an[2], hre[2], him[2], sre[2], sim[2];
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        const d2 a = sA[kk][wr * 64 + i * 16 + (lane & 15)];
+      for (int i = 0; i < 2; ++i) {
+        const d2 a = sA[b][kk][wr * 32 + i * 16 + (lane & 15)];
         ar[i] = a.x; ai[i] = a.y; an[i] = -a.y;
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
-        const d2 bh = sH[kk][wc * 32 + j * 16 + (lane & 15)];
-        const d2 bs = sS[kk][wc * 32 + j * 16 + (lane & 15)];
+        const d2 bh = sH[b][kk][wc * 32 + j * 16 + (lane & 15)];
+        const d2 bs = sS[b][kk][wc * 32 + j * 16 + (lane & 15)];
         hre[j] = bh.x; him[j] = bh.y; sre[j] = bs.x; sim[j] = bs.y;
       }
       // (ar + i ai)(br + i bi): re = ar br - ai bi, im = ar bi + ai br
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) hr[i][j] = MFMA(ar[i], hre[j], hr[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) hi[i][j] = MFMA(ar[i], him[j], hi[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) sr[i][j] = MFMA(ar[i], sre[j], sr[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) si[i][j] = MFMA(ar[i], sim[j], si[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) hr[i][j] = MFMA(an[i], him[j], hr[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) hi[i][j] = MFMA(ai[i], hre[j], hi[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) sr[i][j] = MFMA(an[i], sim[j], sr[i][j]);
 #pragma unroll
-      for (int i = 0; i < 4; ++i)
+      for (int i = 0; i < 2; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) si[i][j] = MFMA(ai[i], sre[j], si[i][j]);
     }
+    if (ch + 1 < nchunks) PG_STORE(b ^ 1);
     __syncthreads();
   }
+#undef PG_LOAD
+#undef PG_STORE
 #pragma unroll
-  for (int i = 0; i < 4; ++i)
+  for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int row = row0 + wr * 64 + i * 16 + (lane >> 4) + 4 * q;
+        const int row = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * q;
         const int col = col0 + wc * 32 + j * 16 + (lane & 15);
         if (row < K_pad) {
           const int64_t o = (int64_t)row * n_pad + col;
@@ -297,7 +317,7 @@ int gradtau_blocks(int n) { return (n + TB - 1) / TB; }
 hipError_t launch_pgemm(const double2* W, const double2* gH, const double2* gS, int K_pad, int n, int n_pad,
                         double2* PH, double2* PS, hipStream_t s) {
   dim3 grid(n_pad / PN, (K_pad + PM - 1) / PM);
-  hipLaunchKernelGGL(k_pgemm, grid, dim3(256), 0, s, (const d2*)W, (const d2*)gH, (const d2*)gS, K_pad, n, n_pad,
+  hipLaunchKernelGGL(k_pgemm, grid, dim3(PT), 0, s, (const d2*)W, (const d2*)gH, (const d2*)gS, K_pad, n, n_pad,
                      (d2*)PH, (d2*)PS);
   return hipGetLastError();
 }
