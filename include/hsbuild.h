@@ -89,7 +89,8 @@ typedef struct {
  * current device is not gfx950.  *out is set only on success. */
 int hsbuild_create(const hsb_config* cfg, hsbuild_t* out);
 
-/* Destroy a handle (NULL is ignored).  Does not synchronise. */
+/* Destroy a handle (NULL is ignored).  Waits only for a batch graph this
+ * handle launched; other work the caller enqueued is not synchronised. */
 void hsbuild_destroy(hsbuild_t h);
 
 /* Bytes of device workspace a call needs.  mode: HSB_MODE_*; ng: host array
