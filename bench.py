@@ -190,7 +190,8 @@ def recorded_traffic(workload: str, options: dict):
     root = os.path.dirname(os.path.abspath(__file__))
     try:
         rec = json.load(open(os.path.join(root, "profiles", "k_hs_fp64_traffic.json")))
-        src = open(os.path.join(root, rec["source"]), "rb").read()
+        srcs = rec["source"] if isinstance(rec["source"], list) else [rec["source"]]
+        src = b"".join(open(os.path.join(root, f), "rb").read() for f in srcs)
     except (OSError, ValueError, KeyError):
         return None
     if hashlib.sha256(src).hexdigest()[:16] != rec.get("source_sha256_16") or rec.get("workload") != workload:
@@ -211,7 +212,8 @@ def main() -> int:
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-k-point batch leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
-    ap.add_argument("--no-tune", action="store_true", help="skip the autotuner (default contraction options)")
+    ap.add_argument("--tune", action="store_true",
+                    help="run the autotuner before timing (default: the library's default options)")
     ap.add_argument("--waves", type=int, default=0, help="contraction waves per workgroup (4 or 8; skips tuning)")
     ap.add_argument("--tile-group", type=int, default=None, help="contraction tile order (skips tuning)")
     ap.add_argument("--split-slices", type=int, default=5,
@@ -269,7 +271,7 @@ def main() -> int:
             b.set_option(N.HSB_OPT_HS_WAVES, args.waves)
         if args.tile_group is not None:
             b.set_option(N.HSB_OPT_TILE_GROUP, args.tile_group)
-    elif not args.no_tune:
+    elif args.tune:
         from paper_1712_07206_amd import autotune
         del ws
         tuned = autotune.tune(b, case["k_frac"], g, tau, T, reps=1, path=None)

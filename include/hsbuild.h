@@ -154,7 +154,7 @@ int hsbuild_stage_times(hsbuild_t h, double* ms_avg, int32_t* n_calls);
 /* Tuning options (performance only: results are bitwise independent of them).
  * HSB_OPT_TILE_GROUP: order in which the upper-triangle tiles of the FP64
  * contraction are dealt to the compute units: 0 = row-major, g > 0 = 128-row
- * super-rows taken g at a time, column by column (0..64; default 0).
+ * super-rows taken g at a time, column by column (0..64; default 8).
  * HSB_OPT_HS_WAVES: waves per workgroup of the FP64 contraction, 4 (64 x 32
  * outputs per wave, one wave per SIMD) or 8 (32 x 32 per wave, two per SIMD);
  * default 8.  Setting an option drops a captured batch graph. */

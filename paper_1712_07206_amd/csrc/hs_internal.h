@@ -91,7 +91,7 @@ hipError_t launch_split_slices(int precision, int S, const double2* X, const dou
                                int n_pad, int QK, const double* scale, void* out, hipStream_t s);
 // Upper triangle of C = conj(L)^T R from the slices (C: [n][n]).
 hipError_t launch_hs_split(int precision, int S, const void* L, const void* R, const double* scL, const double* scR,
-                           int QK, int n, int n_pad, double2* C, hipStream_t s);
+                           int QK, int n, int n_pad, int gr, double2* C, hipStream_t s);
 
 // ---- adjoint ----
 int gradtau_blocks(int n);

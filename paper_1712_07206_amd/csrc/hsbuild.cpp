@@ -22,7 +22,7 @@ struct hsbuild_s {
   int device = 0;
   int n_types = 0, n_atoms = 0, l_max = 0, n_l = 0, max_ng = 0;
   int precision = HSB_FP64, n_slices = 0;
-  int tile_group = 0;  // HSB_OPT_TILE_GROUP
+  int tile_group = 8;  // HSB_OPT_TILE_GROUP
   int hs_waves = 8;    // HSB_OPT_HS_WAVES
   double lattice[9];
   CellArgs cell;              // kfrac filled per call
@@ -203,11 +203,11 @@ int enqueue_split(hsbuild_t h, const Layout& L, char* w, double2* H, double2* S,
                 "split slices");
   if (rc) return rc;
   rc = launched(h, launch_hs_split(h->precision, h->n_slices, w + L.slL, w + L.slS, sc, sc + L.n_pad, QK, L.n,
-                                   L.n_pad, S, s),
+                                   L.n_pad, h->tile_group, S, s),
                 "split contraction (S)");
   if (rc) return rc;
   return launched(h, launch_hs_split(h->precision, h->n_slices, w + L.slL, w + L.slY, sc, sc + 2 * L.n_pad, QK, L.n,
-                                     L.n_pad, H, s),
+                                     L.n_pad, h->tile_group, H, s),
                   "split contraction (H)");
 }
 

@@ -28,6 +28,7 @@
 // walk balances.  Both run the same tile body, so a batched H(k) is bitwise
 // equal to the single-k one.
 #include "hs_internal.h"
+#include "tiles.h"
 
 namespace hsb {
 
@@ -37,28 +38,6 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
 constexpr int BM = 128, BN = 64, BK = 16;
-constexpr int kXcds = 8;
-
-// Start and length of XCD x's contiguous share of `num` items.
-__device__ inline void xcd_range(int x, int num, int& start, int& len) {
-  const int per = num / kXcds, rem = num % kXcds;
-  start = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
-  len = per + (x < rem ? 1 : 0);
-}
-
-// s -> (bi, bj), bj >= bi, row-major over the upper triangle of an nb x nb grid.
-__device__ inline void tri_decode(int s, int nb, int& bi, int& bj) {
-  const double b = 2.0 * nb + 1.0;
-  int i = (int)((b - sqrt(b * b - 8.0 * s)) * 0.5);
-  if (i < 0) i = 0;
-  if (i > nb - 1) i = nb - 1;
-  auto start = [nb](int r) { return r * nb - r * (r - 1) / 2; };
-  while (i > 0 && start(i) > s) --i;
-  while (i + 1 < nb && start(i + 1) <= s) ++i;
-  bi = i;
-  bj = i + (s - start(i));
-}
-
 #define MFMA(a, b, c) __builtin_amdgcn_mfma_f64_16x16x4f64((a), (b), (c), 0, 0, 0)
 
 struct Smem {
@@ -196,42 +175,6 @@ __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, cons
           S[o] = d2{sr[i][j][q], si[i][j][q]};
         }
       }
-}
-
-// Super-tile s -> (bi, sj) when the super-rows are taken in groups of gr: group by
-// group, and inside a group super-column by super-column, the group's rows with
-// bi <= sj.  Consecutive numbers then cover a compact gr-row patch, so the tiles an
-// XCD runs at one time share row strips and column strips.
-__device__ inline void grouped_decode(int s, int nb, int gr, int& bi, int& sj) {
-  int g0 = 0;
-  int rows = min(gr, nb);
-  for (;;) {
-    rows = min(gr, nb - g0);
-    const int ncol = nb - g0;
-    const int cnt = rows * (rows + 1) / 2 + (ncol - rows) * rows;
-    if (s < cnt || g0 + rows >= nb) break;
-    s -= cnt;
-    g0 += rows;
-  }
-  int c = 0;
-  for (;;) {
-    const int k = min(rows, c + 1);
-    if (s < k || g0 + c + 1 >= nb) break;
-    s -= k;
-    ++c;
-  }
-  sj = g0 + c;
-  bi = g0 + s;
-}
-
-// Tile w of a k-point with nbr row blocks -> (row0, col0); two 128 x 64 tiles per
-// super-tile.  gr = 0: row-major over the upper triangle; gr > 0: grouped order.
-__device__ inline void tile_origin(int w, int nbr, int gr, int& row0, int& col0) {
-  int bi, sj;
-  if (gr > 0) grouped_decode(w >> 1, nbr, gr, bi, sj);
-  else tri_decode(w >> 1, nbr, bi, sj);
-  row0 = bi * BM;
-  col0 = sj * BM + (w & 1) * BN;
 }
 
 template <int WR>

@@ -19,6 +19,7 @@
 // holds plane p (= 2 s + {0: Re, 1: Im}), G = 64 b + g, k = 8 q .. 8 q + 7, so one
 // 32-row chunk of a 64-column block is 4 KB contiguous.
 #include "hs_internal.h"
+#include "tiles.h"
 
 namespace hsb {
 
@@ -134,26 +135,6 @@ __global__ void __launch_bounds__(256) k_slice(const d2* __restrict__ X, const d
 
 // ---- slice contraction -----------------------------------------------------------------
 constexpr int SBM = 128, SBN = 64, SNT = 256;
-constexpr int kXcds = 8;
-
-__device__ inline void xcd_range(int x, int num, int& start, int& len) {
-  const int per = num / kXcds, rem = num % kXcds;
-  start = x < rem ? x * (per + 1) : rem * (per + 1) + (x - rem) * per;
-  len = per + (x < rem ? 1 : 0);
-}
-
-__device__ inline void tri_decode(int s, int nb, int& bi, int& bj) {
-  const double bb = 2.0 * nb + 1.0;
-  int i = (int)((bb - sqrt(bb * bb - 8.0 * s)) * 0.5);
-  if (i < 0) i = 0;
-  if (i > nb - 1) i = nb - 1;
-  auto start = [nb](int r) { return r * nb - r * (r - 1) / 2; };
-  while (i > 0 && start(i) > s) --i;
-  while (i + 1 < nb && start(i + 1) <= s) ++i;
-  bi = i;
-  bj = i + (s - start(i));
-}
-
 template <typename T>
 __device__ inline f4 slice_mfma(u4 a, u4 b, f4 c);
 template <>
@@ -320,7 +301,7 @@ typedef __attribute__((address_space(3))) void* lds_ptr;
 template <int S>
 __global__ void __launch_bounds__(512, 1) k_hs_split2(const u4* __restrict__ Ls, const u4* __restrict__ Rs,
                                                       const double* __restrict__ scL, const double* __restrict__ scR,
-                                                      int QK, int n, int n_pad, int nbr, int num_wg,
+                                                      int QK, int n, int n_pad, int nbr, int num_wg, int gr,
                                                       d2* __restrict__ C) {
   constexpr int P = 2 * S;        // planes per operand
   constexpr int CU = 384 * P;     // units per chunk: left P*2*2*64, right P*2*64
@@ -333,9 +314,8 @@ __global__ void __launch_bounds__(512, 1) k_hs_split2(const u4* __restrict__ Ls,
   int start, len;
   xcd_range(x, num_wg, start, len);
   const int w = start + blockIdx.x / kXcds;
-  int bi, sj;
-  tri_decode(w >> 1, nbr, bi, sj);
-  const int row0 = bi * SBM, col0 = sj * SBM + (w & 1) * SBN;
+  int row0, col0;
+  tile_origin(w, nbr, gr, row0, col0);
   if (col0 >= n) return;
   const int NB = n_pad / 64;
   const int bL = row0 / 64, bR = col0 / 64;
@@ -424,15 +404,15 @@ __global__ void __launch_bounds__(512, 1) k_hs_split2(const u4* __restrict__ Ls,
 }
 
 hipError_t launch_hs_split2(int S, const void* L, const void* R, const double* scL, const double* scR, int QK, int n,
-                            int n_pad, double2* C, hipStream_t s) {
+                            int n_pad, int gr, double2* C, hipStream_t s) {
   const int nbr = n_pad / SBM;
   const int num_wg = nbr * (nbr + 1);
   dim3 grid(num_wg), block(512);
   switch (S) {
-    case 3: hipLaunchKernelGGL((k_hs_split2<3>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, (d2*)C); break;
-    case 4: hipLaunchKernelGGL((k_hs_split2<4>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, (d2*)C); break;
-    case 5: hipLaunchKernelGGL((k_hs_split2<5>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, (d2*)C); break;
-    case 6: hipLaunchKernelGGL((k_hs_split2<6>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, (d2*)C); break;
+    case 3: hipLaunchKernelGGL((k_hs_split2<3>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, (d2*)C); break;
+    case 4: hipLaunchKernelGGL((k_hs_split2<4>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, (d2*)C); break;
+    case 5: hipLaunchKernelGGL((k_hs_split2<5>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, (d2*)C); break;
+    case 6: hipLaunchKernelGGL((k_hs_split2<6>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, (d2*)C); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -493,8 +473,8 @@ hipError_t launch_split_slices(int precision, int S, const double2* X, const dou
 }
 
 hipError_t launch_hs_split(int precision, int S, const void* L, const void* R, const double* scL, const double* scR,
-                           int QK, int n, int n_pad, double2* C, hipStream_t s) {
-  if (precision == HSB_SPLIT_BF16) return launch_hs_split2(S, L, R, scL, scR, QK, n, n_pad, C, s);
+                           int QK, int n, int n_pad, int gr, double2* C, hipStream_t s) {
+  if (precision == HSB_SPLIT_BF16) return launch_hs_split2(S, L, R, scL, scR, QK, n, n_pad, gr, C, s);
   return launch_hs_split_t<_Float16>(S, L, R, scL, scR, QK, n, n_pad, C, s);
 }
 

@@ -20,7 +20,8 @@ def test_traffic_record_requires_matching_source_and_options():
     rec = json.load(open(os.path.join(ROOT, "profiles", "k_hs_fp64_traffic.json")))
     opts = rec.get("options", {"waves": 4, "tile_group": 0})
     import hashlib
-    sha = hashlib.sha256(open(os.path.join(ROOT, rec["source"]), "rb").read()).hexdigest()[:16]
+    srcs = rec["source"] if isinstance(rec["source"], list) else [rec["source"]]
+    sha = hashlib.sha256(b"".join(open(os.path.join(ROOT, f), "rb").read() for f in srcs)).hexdigest()[:16]
     got = bench.recorded_traffic(rec["workload"], opts)
     if sha == rec["source_sha256_16"]:
         assert got == rec["traffic_bytes"]
