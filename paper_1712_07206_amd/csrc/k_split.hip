@@ -298,6 +298,16 @@ __global__ void __launch_bounds__(SNT, 1) k_hs_split(const u4* __restrict__ Ls, 
 typedef float f16v __attribute__((ext_vector_type(16)));
 typedef __attribute__((address_space(3))) void* lds_ptr;
 
+// scheduling groups (DS read = 0x100, MFMA = 0x008): reads of step K + 1, then the 4 (K + 1) MFMAs of step K
+template <int K, int S>
+__device__ __forceinline__ void split2_schedule() {
+  if constexpr (K < S) {
+    if constexpr (K + 1 < S) __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 4 * (K + 1), 0);
+    split2_schedule<K + 1, S>();
+  }
+}
+
 template <int S>
 __global__ void __launch_bounds__(512, 1) k_hs_split2(const u4* __restrict__ Ls, const u4* __restrict__ Rs,
                                                       const double* __restrict__ scL, const double* __restrict__ scR,
@@ -308,7 +318,8 @@ __global__ void __launch_bounds__(512, 1) k_hs_split2(const u4* __restrict__ Ls,
   constexpr int NI = 6 * P;       // 64-unit copies per chunk
   __shared__ u4 lds[2][CU];
 
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform: copy addresses stay scalar
   const int wr = wave >> 1, wc = wave & 1;  // rows wr*32, columns wc*32 (8 waves: 4 x 2)
   const int x = blockIdx.x % kXcds;
   int start, len;
@@ -321,24 +332,38 @@ __global__ void __launch_bounds__(512, 1) k_hs_split2(const u4* __restrict__ Ls,
   const int bL = row0 / 64, bR = col0 / 64;
   const int nchunks = QK / 2;
 
-  // copy j of chunk c: left (p, b, q) for j < 4P, right (p, q) after; 8 waves share the copies
-  auto issue = [&](int c, int buf) {
-    for (int j = wave; j < NI; j += 8) {
-      const u4* src;
-      int dst;
-      if (j < 4 * P) {
-        const int p = j >> 2, b = (j >> 1) & 1, qq = j & 1;
-        src = Ls + ((int64_t)(p * NB + bL + b) * QK + 2 * c + qq) * 64;
-        dst = ((p * 2 + b) * 2 + qq) * 64;
-      } else {
-        const int jj = j - 4 * P;
-        const int p = jj >> 1, qq = jj & 1;
-        src = Rs + ((int64_t)(p * NB + bR) * QK + 2 * c + qq) * 64;
-        dst = 256 * P + (p * 2 + qq) * 64;
-      }
-      __builtin_amdgcn_global_load_lds((const void*)(src + lane), (lds_ptr)(&lds[buf][dst]), 16, 0, 0);
+  // The copies of a chunk (64 units = 1 KB each): left (p, b, q) for j < 4P, right (p, q)
+  // after; wave w takes j = w, w + 8, ...  A copy's source advances by 128 units per chunk.
+  constexpr int NPW = (NI + 7) / 8;
+  const u4* src0[NPW];
+  int dst[NPW];
+#pragma unroll
+  for (int i = 0; i < NPW; ++i) {
+    const int j = wave + 8 * i;
+    src0[i] = Ls;  // unused when j >= NI
+    dst[i] = 0;
+    if (j >= NI) continue;
+    if (j < 4 * P) {
+      const int p = j >> 2, b = (j >> 1) & 1, qq = j & 1;
+      src0[i] = Ls + ((int64_t)(p * NB + bL + b) * QK + qq) * 64;
+      dst[i] = ((p * 2 + b) * 2 + qq) * 64;
+    } else {
+      const int jj = j - 4 * P;
+      const int p = jj >> 1, qq = jj & 1;
+      src0[i] = Rs + ((int64_t)(p * NB + bR) * QK + qq) * 64;
+      dst[i] = 256 * P + (p * 2 + qq) * 64;
     }
+  }
+  auto issue = [&](int c, int buf) {
+#pragma unroll
+    for (int i = 0; i < NPW; ++i)
+      if (wave + 8 * i < NI)
+        __builtin_amdgcn_global_load_lds((const void*)(src0[i] + (int64_t)c * 128 + lane),
+                                         (lds_ptr)(&lds[buf][dst[i]]), 16, 0, 0);
   };
+  // The two waves that share a SIMD (w and w + 4) flush at chunks two apart, so one
+  // converts while the other keeps the MFMA unit busy; every window stays <= 64 rows.
+  const int fph = (wave >> 2) ? 2 : 0;
 
   f16v acc[4][2];  // [set][re, im]
   double a64[2][16];
@@ -360,23 +385,32 @@ __global__ void __launch_bounds__(512, 1) k_hs_split2(const u4* __restrict__ Ls,
     __syncthreads();                // everyone's have, and buffer buf^1 is free
     if (c + 1 < nchunks) issue(c + 1, buf ^ 1);
     const u4* B = lds[buf];
+    // Step k takes left slice si = S-1-k and right slice k, and runs every pair (si, t <= k):
+    // the reads are spread over the chunk instead of all waiting up front.
+    u4 rre[S], rim[S];
 #pragma unroll
-    for (int si = 0; si < S; ++si) {
+    for (int k = 0; k < S; ++k) {
+      const int si = S - 1 - k;
       const u4 lr = B[lrow + (2 * si) * 256];
       const u4 li = B[lrow + (2 * si + 1) * 256];
+      rre[k] = B[rcol + (2 * k) * 128];
+      rim[k] = B[rcol + (2 * k + 1) * 128];
       const u4 ln = li ^ u4{0x80008000u, 0x80008000u, 0x80008000u, 0x80008000u};
 #pragma unroll
-      for (int ti = 0; ti < S - si; ++ti) {
+      for (int ti = 0; ti <= k; ++ti) {
         const int st = si + ti < 3 ? si + ti : 3;
-        const bf8 brr = __builtin_bit_cast(bf8, B[rcol + (2 * ti) * 128]);
-        const bf8 bri = __builtin_bit_cast(bf8, B[rcol + (2 * ti + 1) * 128]);
+        const bf8 brr = __builtin_bit_cast(bf8, rre[ti]);
+        const bf8 bri = __builtin_bit_cast(bf8, rim[ti]);
         acc[st][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, lr), brr, acc[st][0], 0, 0, 0);
         acc[st][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, lr), bri, acc[st][1], 0, 0, 0);
         acc[st][0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, li), bri, acc[st][0], 0, 0, 0);
         acc[st][1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf8, ln), brr, acc[st][1], 0, 0, 0);
       }
     }
-    if ((c & 3) == 3 || c + 1 == nchunks) {  // 64 rows: the exact sets are still exact
+    // schedule: the four reads of step k + 1 are issued ahead of the MFMAs of step k
+    __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+    split2_schedule<0, S>();
+    if (((c + fph) & 3) == 3 || c + 1 == nchunks) {  // <= 64 rows: the exact sets are still exact
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         double sre = 0.0, sim = 0.0;
