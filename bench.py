@@ -94,6 +94,68 @@ def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
             "rel_err_vs_fp64": {"H": eh, "S": es}, "meets_1e-10": bool(eh <= 1e-10 and es <= 1e-10)}
 
 
+def factored_flops(case) -> tuple:
+    """Algorithmic flops of the type-factored forward: per upper-triangle entry and
+    type, N_t + 4 N_L complex multiply-adds (phases, H and S slots) and two complex
+    products folded in; plus the per-type T products.  Returns (contraction, total)."""
+    n, n_l = case["n_g"], case["n_l"]
+    counts = [int((case["atom_type"] == t).sum()) for t in range(case["n_types"])]
+    per_entry = sum(8.0 * (nt + 4 * n_l) + 16.0 for nt in counts if nt > 0)
+    contraction = per_entry * n * (n + 1) / 2.0
+    return contraction, contraction + 32.0 * sum(1 for nt in counts if nt > 0) * n_l * n_l * n
+
+
+def factored_leg(args, case, g, tau, T, H, S, ms_fp64) -> dict:
+    """The type-factored forward (hsbuild_forward_factored) on the same workload:
+    time to solution, speedup over the stacked FP64 path and the relative
+    Frobenius error against its H and S (upper triangles)."""
+    import torch
+
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import HSBuilder
+    n = case["n_g"]
+    bf = HSBuilder.from_case(case)
+    wsb = bf.workspace_bytes(N.HSB_MODE_FACTORED, [n])
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    H2 = torch.empty_like(H)
+    S2 = torch.empty_like(S)
+    log("factored path: workspace %.2f GB" % (wsb / 1e9))
+    kf = case["k_frac"]
+
+    for _ in range(max(1, args.warmup)):
+        bf.forward_factored(kf, g, tau, T, H2, S2, ws=ws)
+    torch.cuda.synchronize()
+    bf.set_timing(True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(args.steps, 10)
+    e0.record()
+    for _ in range(reps):
+        bf.forward_factored(kf, g, tau, T, H2, S2, ws=ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    stage_ms, _ = bf.stage_times()
+    bf.set_timing(False)
+    Hu, Su = torch.triu(H), torch.triu(S)
+    eh = (torch.linalg.norm(torch.triu(H2) - Hu) / torch.linalg.norm(Hu)).item()
+    es = (torch.linalg.norm(torch.triu(S2) - Su) / torch.linalg.norm(Su)).item()
+    del Hu, Su, H2, S2, ws
+    bf.close()
+    torch.cuda.empty_cache()
+    fc, ft = factored_flops(case)
+    kt = fc / (stage_ms[2] * 1e-3) / 1e12
+    log("factored: %.3f ms/step (contraction %.3f ms, %.2f TFLOP/s on its own %.4g TFLOP), %.1fx faster than the "
+        "stacked FP64 path, rel err vs it H %.2e S %.2e" % (ms, stage_ms[2], kt, fc / 1e12, ms_fp64 / ms, eh, es))
+    return {"ms_per_step": round(ms, 4), "steps": reps, "speedup_vs_fp64": round(ms_fp64 / ms, 3),
+            "own_flops_per_step": ft, "own_tflops": round(ft / (ms * 1e-3) / 1e12, 4),
+            "stages_ms": {"coefficients": round(stage_ms[0], 4), "t_products": round(stage_ms[1], 4),
+                          "fact_contraction": round(stage_ms[2], 4)},
+            "roofline": {"kernel": "k_hs_fact", "bound": "mfma", "achieved": round(kt, 4),
+                         "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                         "frac": round(kt / FP64_MFMA_PEAK_TFLOPS, 4), "algorithmic_flops_per_launch": fc},
+            "rel_err_vs_fp64": {"H": eh, "S": es}}
+
+
 def batch_leg(args) -> dict:
     """The multi-k workload (64 k-points, N_G 2800-3400, T shared): one captured
     graph with a persistent contraction, against 64 sequential forward calls."""
@@ -216,6 +278,7 @@ def main() -> int:
                     help="run the autotuner before timing (default: the library's default options)")
     ap.add_argument("--waves", type=int, default=0, help="contraction waves per workgroup (4 or 8; skips tuning)")
     ap.add_argument("--tile-group", type=int, default=None, help="contraction tile order (skips tuning)")
+    ap.add_argument("--no-factored", action="store_true", help="skip the type-factored leg")
     ap.add_argument("--split-slices", type=int, default=5,
                     help="also time the BF16 split-precision path with this many slices (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -330,6 +393,8 @@ def main() -> int:
                      "algorithmic_flops_per_launch": flops_hs},
         "split_speedup": None,
     }
+    if not args.no_factored:
+        result["factored"] = factored_leg(args, case, g, tau, T, H, S, ms_step)
     if args.split_slices > 0:
         result["split"] = split_leg(args, case, b, g, tau, T, H, S, ws, ms_step, flops)
         result["split_speedup"] = result["split"]["speedup"]

@@ -63,7 +63,7 @@ enum {
 enum { HSB_FP64 = 0, HSB_SPLIT_FP16 = 1, HSB_SPLIT_BF16 = 2 };
 
 /* Workspace modes for hsbuild_workspace_bytes. */
-enum { HSB_MODE_FORWARD = 0, HSB_MODE_BACKWARD = 1, HSB_MODE_BATCH = 2, HSB_MODE_COEFFICIENTS = 3 };
+enum { HSB_MODE_FORWARD = 0, HSB_MODE_BACKWARD = 1, HSB_MODE_BATCH = 2, HSB_MODE_COEFFICIENTS = 3, HSB_MODE_FACTORED = 4 };
 
 #define HSB_MAX_TYPES 16
 #define HSB_MAX_LMAX 12
@@ -113,6 +113,19 @@ int hsbuild_coefficients(hsbuild_t h, const double k_frac[3], int32_t ng, const 
  * split-precision (Ozaki slice) contraction. */
 int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
                     const void* T, void* H, void* S, void* ws, size_t ws_bytes, void* stream);
+
+/* H and S of one k-point by the type-factored ("compressed") contraction,
+ * the compression of A and B that Sec. 7 proposes: each atom's coefficients
+ * are its type's coefficients at the origin times the structure phase
+ * e^{i K_G . tau_a}, so (Eqs. 4-5)
+ *   H = sum_t P_t .* (W0_t^H T_t W0_t),  S = sum_t P_t .* (W0_t^H Lam_t W0_t),
+ *   P_t[G'][G] = sum over the atoms a of type t of e^{-i K_G' . tau_a} e^{i K_G . tau_a}
+ * (.* entrywise), with contraction width sum_t (N_t + 4 N_L) per entry
+ * instead of 4 N_atoms N_L.  Same arguments and results as hsbuild_forward
+ * (equal up to FP64 rounding); always FP64, whatever the handle's precision.
+ * Workspace: hsbuild_workspace_bytes(h, HSB_MODE_FACTORED, 1, &ng). */
+int hsbuild_forward_factored(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
+                             const void* T, void* H, void* S, void* ws, size_t ws_bytes, void* stream);
 
 /* H and S from caller-given matching coefficients, the input the paper's
  * HSDLA algorithm starts from (Alg. 1, Alg. 3): coef is device complex128

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhsbuild.so")
-SOURCES = ["hsbuild.cpp", "k_coef.hip", "k_tprod.hip", "k_hs.hip", "k_adjoint.hip", "k_split.hip"]
+SOURCES = ["hsbuild.cpp", "k_coef.hip", "k_tprod.hip", "k_hs.hip", "k_adjoint.hip", "k_split.hip", "k_fact.hip"]
 ARCH = "gfx950"
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-x", "hip", "--offload-arch=" + ARCH,

@@ -44,6 +44,9 @@ struct Layout {
   size_t PH = 0, PS = 0, partT = 0, partTau = 0;  // backward only
   int K_pad2 = 0;                                  // split only: stacked rows padded to 32
   size_t mx = 0, scale = 0, slL = 0, slS = 0, slY = 0;  // split only
+  // factored only: rows [R_f] of X (E and W0 blocks), XL = lam X, Yx (Y0 on W0 rows, 0 on E rows)
+  int R_f = 0;
+  size_t X = 0, XL = 0, Yx = 0, lamx = 0, kind = 0, tau0 = 0;
 };
 
 // Per-k-point entry of the batched contraction's tile list (device copy in the workspace).
@@ -92,6 +95,22 @@ hipError_t launch_split_slices(int precision, int S, const double2* X, const dou
 // Upper triangle of C = conj(L)^T R from the slices (C: [n][n]).
 hipError_t launch_hs_split(int precision, int S, const void* L, const void* R, const double* scL, const double* scR,
                            int QK, int n, int n_pad, int gr, double2* C, hipStream_t s);
+
+// ---- type-factored form ----
+// Number of 64 x 64 tiles of the factored contraction.
+int fact_tiles(int n_pad);
+// E[a][G] = e^{i K_G . tau_a}, rows a < n_atoms of a [*][n_pad] array.
+hipError_t launch_phases(int n_atoms, int n_pad, const double* kv, const double* tau, double2* E, hipStream_t s);
+// Row blocks of the factored layout: per type with atoms, round16(N_t) E rows then
+// round16(2 N_L) W0 rows.  lamx[r] and the kind of every 16-row chunk.
+hipError_t launch_fact_rows(const CellArgs& c, const TypeConsts* consts, int rows, double* lamx, int* kind,
+                            hipStream_t s);
+// XL[r][G] = lam[r] X[r][G] for r < rows.
+hipError_t launch_scale_rows(const double2* X, const double* lam, int rows, int n_pad, double2* XL, hipStream_t s);
+// Upper triangles of H = sum_t P_t * (W0_t^H Y0_t), S = sum_t P_t * (W0_t^H Lam_t W0_t), P_t = E_t^H E_t,
+// from the per-type row blocks of X, XL = lam X and Yx (nch chunks of 16 rows, kinds in kind[]).
+hipError_t launch_hs_fact(const double2* X, const double2* XL, const double2* Yx, const int* kind, int nch, int n,
+                          int n_pad, int gr, double2* H, double2* S, int64_t ldh, hipStream_t s);
 
 // ---- adjoint ----
 int gradtau_blocks(int n);

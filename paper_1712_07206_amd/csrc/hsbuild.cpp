@@ -61,6 +61,16 @@ int fail(hsbuild_t h, int code, const char* fmt, ...) {
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
 
+// Rows of the factored layout: per type with atoms, round16(N_t) phase rows and round16(2 N_L) W0 rows.
+int fact_rows(const hsbuild_s& h) {
+  int rows = 0;
+  for (int t = 0; t < h.n_types; ++t) {
+    const int nt = h.cell.type_start[t + 1] - h.cell.type_start[t];
+    if (nt > 0) rows += (int)round_up(nt, 16) + (int)round_up(2 * h.n_l, 16);
+  }
+  return rows;
+}
+
 Layout make_layout(const hsbuild_s& h, int ng, int mode) {
   Layout L;
   L.n = ng;
@@ -78,6 +88,17 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
   L.kv = take(np * 4 * sizeof(double));
   L.ang = take((size_t)h.n_l * np * sizeof(double2));
   L.ab = take((size_t)h.n_types * (h.l_max + 1) * np * sizeof(double2));
+  if (mode == HSB_MODE_FACTORED) {
+    L.R_f = fact_rows(h);
+    L.tau0 = take(4 * sizeof(double));
+    L.lamx = take((size_t)L.R_f * sizeof(double));
+    L.kind = take((size_t)(L.R_f / 16) * sizeof(int));
+    L.X = take((size_t)L.R_f * np * sizeof(double2));
+    L.XL = take((size_t)L.R_f * np * sizeof(double2));
+    L.Yx = take((size_t)L.R_f * np * sizeof(double2));
+    L.end = off;
+    return L;
+  }
   if (mode != HSB_MODE_COEFFICIENTS) {
     L.lam = take((size_t)L.K_pad * sizeof(double));
     L.W = take((size_t)L.K_pad * np * sizeof(double2));
@@ -386,7 +407,8 @@ size_t hsbuild_workspace_bytes(hsbuild_t h, int32_t mode, int32_t n_k, const int
     fail(h, HSB_ERR_ARG, "ng must point to n_k >= 1 sizes");
     return 0;
   }
-  if (mode == HSB_MODE_FORWARD || mode == HSB_MODE_COEFFICIENTS || mode == HSB_MODE_BACKWARD) {
+  if (mode == HSB_MODE_FORWARD || mode == HSB_MODE_COEFFICIENTS || mode == HSB_MODE_BACKWARD ||
+      mode == HSB_MODE_FACTORED) {
     if (n_k != 1 || check_ng(h, ng[0])) return 0;
     return make_layout(*h, ng[0], mode).end;
   }
@@ -440,6 +462,86 @@ int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32
   } else {
     rc = enqueue_split(h, L, w, (double2*)H, (double2*)S, s);
   }
+  mark(h, 3, s);
+  return rc;
+}
+
+int hsbuild_forward_factored(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
+                             const void* T, void* H, void* S, void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return HSB_ERR_ARG;
+  h->err.clear();
+  if (!k_frac || !g || !tau || !T || !H || !S) return fail(h, HSB_ERR_ARG, "null k_frac, g, tau, T, H or S");
+  if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
+  int rc = check_ng(h, ng);
+  if (rc) return rc;
+  const Layout L = make_layout(*h, ng, HSB_MODE_FACTORED);
+  if ((rc = check_ws(h, L, ws, ws_bytes))) return rc;
+  if ((rc = check_device(h))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  const int64_t np = L.n_pad;
+  const int M = 2 * h->n_l, Mp = (int)round_up(M, 16);
+  double2* X = (double2*)(w + L.X);
+  double2* XL = (double2*)(w + L.XL);
+  double2* Yx = (double2*)(w + L.Yx);
+  mark(h, 0, s);
+  CellArgs c;
+  if ((rc = enqueue_tables(h, L, k_frac, g, w, s, c))) return rc;
+  const TypeConsts* dconsts = (const TypeConsts*)(w + L.consts);
+  rc = launched(h, launch_fact_rows(c, dconsts, L.R_f, (double*)(w + L.lamx), (int*)(w + L.kind), s), "k_fact_rows");
+  if (rc) return rc;
+  // origin of every type (phase 1): two zero double2 = four zero doubles
+  if ((rc = launched(h, launch_zero_rows((double2*)(w + L.tau0), 2, 0, 1, s), "k_zero_rows"))) return rc;
+  int base = 0;
+  for (int t = 0; t < h->n_types; ++t) {
+    const int a0 = c.type_start[t], nt = c.type_start[t + 1] - a0;
+    if (nt == 0) continue;
+    const int Ep = (int)round_up(nt, 16), rw = base + Ep;
+    // phase rows of the type's atoms, zero pad rows; Yx is zero on the whole phase block
+    rc = launched(h, launch_phases(nt, L.n_pad, (const double*)(w + L.kv), tau + 3 * a0, X + (int64_t)base * np, s),
+                  "k_phases");
+    if (!rc) rc = launched(h, launch_zero_rows(X, np, base + nt, rw, s), "k_zero_rows");
+    if (!rc) rc = launched(h, launch_zero_rows(Yx, np, base, rw, s), "k_zero_rows");
+    // W0_t: the type's coefficients at the origin (one-atom cell of type t), zero pad rows
+    CellArgs c1 = c;
+    c1.n_types = 1;
+    c1.n_atoms = 1;
+    c1.type_start[0] = 0;
+    c1.type_start[1] = 1;
+    c1.r_mt[0] = c.r_mt[t];
+    const double2* ab_t = (const double2*)(w + L.ab) + (int64_t)t * (h->l_max + 1) * np;
+    if (!rc)
+      rc = launched(h, launch_assemble(c1, L.n_pad, (const double2*)(w + L.ang), ab_t, (const double*)(w + L.kv),
+                                       (const double*)(w + L.tau0), X + (int64_t)rw * np, np, L.n_pad, s),
+                    "k_assemble");
+    if (!rc) rc = launched(h, launch_zero_rows(X, np, rw + M, rw + Mp, s), "k_zero_rows");
+    if (!rc) rc = launched(h, launch_zero_rows(Yx, np, rw + M, rw + Mp, s), "k_zero_rows");
+    if (rc) return rc;
+    base = rw + Mp;
+  }
+  mark(h, 1, s);
+  base = 0;
+  for (int t = 0; t < h->n_types; ++t) {
+    const int nt = c.type_start[t + 1] - c.type_start[t];
+    if (nt == 0) continue;
+    const int rw = base + (int)round_up(nt, 16);
+    CellArgs c1 = c;
+    c1.n_types = 1;
+    c1.n_atoms = 1;
+    c1.type_start[0] = 0;
+    c1.type_start[1] = 1;
+    rc = launched(h, launch_tprod(c1, (const double2*)T + (int64_t)t * M * M, X + (int64_t)rw * np,
+                                  Yx + (int64_t)rw * np, L.n_pad, s),
+                  "k_tprod");
+    if (rc) return rc;
+    base = rw + Mp;
+  }
+  rc = launched(h, launch_scale_rows(X, (const double*)(w + L.lamx), L.R_f, L.n_pad, XL, s), "k_scale_rows");
+  if (rc) return rc;
+  mark(h, 2, s);
+  rc = launched(h, launch_hs_fact(X, XL, Yx, (const int*)(w + L.kind), L.R_f / 16, ng, L.n_pad, h->tile_group,
+                                  (double2*)H, (double2*)S, ng, s),
+                "k_hs_fact");
   mark(h, 3, s);
   return rc;
 }
