@@ -156,6 +156,50 @@ def factored_leg(args, case, g, tau, T, H, S, ms_fp64) -> dict:
             "rel_err_vs_fp64": {"H": eh, "S": es}}
 
 
+def hsdla_leg(args, case, g, tau, T, H, S, ms_fp64) -> dict:
+    """The paper's BLAS sequence on rocBLAS (hsbuild_forward_hsdla), Alg. 3 and
+    Alg. 1, on the same workload: time per build, the fused path's speedup over
+    each and the relative Frobenius error against the fused path's H and S."""
+    import torch
+
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import HSBuilder
+    n, n_at, n_l = case["n_g"], case["n_atoms"], case["n_l"]
+    k_c = n_at * n_l
+    bb = HSBuilder.from_case(case)
+    wsb = bb.workspace_bytes(N.HSB_MODE_HSDLA, [n])
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    H2 = torch.empty_like(H)
+    S2 = torch.empty_like(S)
+    log("rocBLAS HSDLA: workspace %.2f GB" % (wsb / 1e9))
+    out = {}
+    Hu, Su = torch.triu(H), torch.triu(S)
+    for alg, flops in ((3, 20.0 * k_c * n * n + 24.0 * n_at * n_l * n_l * n),
+                       (1, 24.0 * k_c * n * n + 24.0 * n_at * n_l * n_l * n)):
+        bb.forward_hsdla(alg, case["k_frac"], g, tau, T, H2, S2, ws=ws)  # warm (rocBLAS loads its kernels)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        reps = max(1, min(args.steps, 3))
+        e0.record()
+        for _ in range(reps):
+            bb.forward_hsdla(alg, case["k_frac"], g, tau, T, H2, S2, ws=ws)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        eh = (torch.linalg.norm(torch.triu(H2) - Hu) / torch.linalg.norm(Hu)).item()
+        es = (torch.linalg.norm(torch.triu(S2) - Su) / torch.linalg.norm(Su)).item()
+        log("rocBLAS Alg. %d: %.3f ms/build (%.2f TFLOP/s on its own %.4g TFLOP); fused FP64 path %.2fx faster; "
+            "rel err vs fused H %.2e S %.2e" % (alg, ms, flops / (ms * 1e-3) / 1e12, flops / 1e12, ms / ms_fp64, eh, es))
+        out["alg%d" % alg] = {"ms_per_build": round(ms, 4), "reps": reps, "paper_flops": flops,
+                              "tflops_on_paper_flops": round(flops / (ms * 1e-3) / 1e12, 4),
+                              "fused_speedup": round(ms / ms_fp64, 4), "rel_err_vs_fused": {"H": eh, "S": es}}
+    del Hu, Su, H2, S2, ws
+    bb.close()
+    torch.cuda.empty_cache()
+    out["note"] = "rocBLAS zherk/zher2k/zherkx/zgemm/zhemm in the order of the paper's algorithms, same GPU and inputs"
+    return out
+
+
 def batch_leg(args) -> dict:
     """The multi-k workload (64 k-points, N_G 2800-3400, T shared): one captured
     graph with a persistent contraction, against 64 sequential forward calls."""
@@ -279,6 +323,7 @@ def main() -> int:
     ap.add_argument("--waves", type=int, default=0, help="contraction waves per workgroup (4 or 8; skips tuning)")
     ap.add_argument("--tile-group", type=int, default=None, help="contraction tile order (skips tuning)")
     ap.add_argument("--no-factored", action="store_true", help="skip the type-factored leg")
+    ap.add_argument("--no-hsdla", action="store_true", help="skip the rocBLAS HSDLA baseline leg")
     ap.add_argument("--split-slices", type=int, default=5,
                     help="also time the BF16 split-precision path with this many slices (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -395,6 +440,8 @@ def main() -> int:
     }
     if not args.no_factored:
         result["factored"] = factored_leg(args, case, g, tau, T, H, S, ms_step)
+    if not args.no_hsdla:
+        result["hsdla_rocblas"] = hsdla_leg(args, case, g, tau, T, H, S, ms_step)
     if args.split_slices > 0:
         result["split"] = split_leg(args, case, b, g, tau, T, H, S, ws, ms_step, flops)
         result["split_speedup"] = result["split"]["speedup"]

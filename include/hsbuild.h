@@ -63,7 +63,8 @@ enum {
 enum { HSB_FP64 = 0, HSB_SPLIT_FP16 = 1, HSB_SPLIT_BF16 = 2 };
 
 /* Workspace modes for hsbuild_workspace_bytes. */
-enum { HSB_MODE_FORWARD = 0, HSB_MODE_BACKWARD = 1, HSB_MODE_BATCH = 2, HSB_MODE_COEFFICIENTS = 3, HSB_MODE_FACTORED = 4 };
+enum { HSB_MODE_FORWARD = 0, HSB_MODE_BACKWARD = 1, HSB_MODE_BATCH = 2, HSB_MODE_COEFFICIENTS = 3, HSB_MODE_FACTORED = 4,
+       HSB_MODE_HSDLA = 5 };
 
 #define HSB_MAX_TYPES 16
 #define HSB_MAX_LMAX 12
@@ -126,6 +127,22 @@ int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32
  * Workspace: hsbuild_workspace_bytes(h, HSB_MODE_FACTORED, 1, &ng). */
 int hsbuild_forward_factored(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
                              const void* T, void* H, void* S, void* ws, size_t ws_bytes, void* stream);
+
+/* The paper's own algorithm on the vendor BLAS (rocBLAS), a baseline for the
+ * fused kernels: A and B stacks built on the GPU as for hsbuild_forward, then
+ * the BLAS-3 sequence of Alg. 3 (algorithm = 3: zherk, zherk on U B, per-atom
+ * zgemm + zhemm, zher2k, per-atom zhemm, zherkx) or of Alg. 1 (algorithm = 1)
+ * with H_AA by a per-atom zhemm and a general zgemm, the branch Alg. 1 takes
+ * when the Cholesky factorisation of T_AA fails (as it does for T_AA with
+ * negative diagonal entries).  Same H and S as hsbuild_forward up to FP64
+ * rounding; algorithm 3 writes the upper triangles only, algorithm 1 writes
+ * both triangles of H (its strict lower triangle is not meaningful).
+ * Workspace: hsbuild_workspace_bytes(h, HSB_MODE_HSDLA, 1, &ng), which
+ * includes the device memory rocBLAS asks for (the library binds it to the
+ * caller's workspace).  The first call on a handle creates its rocBLAS handle. */
+int hsbuild_forward_hsdla(hsbuild_t h, int32_t algorithm, const double k_frac[3], int32_t ng, const int32_t* g,
+                          const double* tau, const void* T, void* H, void* S, void* ws, size_t ws_bytes,
+                          void* stream);
 
 /* H and S from caller-given matching coefficients, the input the paper's
  * HSDLA algorithm starts from (Alg. 1, Alg. 3): coef is device complex128

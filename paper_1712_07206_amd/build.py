@@ -16,7 +16,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhsbuild.so")
-SOURCES = ["hsbuild.cpp", "k_coef.hip", "k_tprod.hip", "k_hs.hip", "k_adjoint.hip", "k_split.hip", "k_fact.hip"]
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+SOURCES = ["hsbuild.cpp", "k_coef.hip", "k_tprod.hip", "k_hs.hip", "k_adjoint.hip", "k_split.hip", "k_fact.hip",
+           "hsdla_blas.cpp"]
 ARCH = "gfx950"
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-x", "hip", "--offload-arch=" + ARCH,
@@ -50,7 +52,8 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-o", tmp]
+    cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-L" + os.path.join(ROCM, "lib"),
+           "-lrocblas", "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed: %s\n%s%s" % (" ".join(cmd), res.stdout, res.stderr))

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <cstddef>
 #include <cstdint>
+#include <string>
 
 #include "hsbuild.h"
 
@@ -47,6 +48,8 @@ struct Layout {
   // factored only: rows [R_f] of X (E and W0 blocks), XL = lam X, Yx (Y0 on W0 rows, 0 on E rows)
   int R_f = 0;
   size_t X = 0, XL = 0, Yx = 0, lamx = 0, kind = 0, tau0 = 0;
+  // BLAS baseline only: A and B stacks, X scratch, rocBLAS's device memory
+  size_t hA = 0, hB = 0, hX = 0, blas = 0, blas_bytes = 0;
 };
 
 // Per-k-point entry of the batched contraction's tile list (device copy in the workspace).
@@ -66,6 +69,12 @@ hipError_t launch_lambda(const CellArgs& c, const TypeConsts* consts, int K_pad,
 // out[(atom*2N_L + (A|B)*N_L + L) * ld + G] for G < n_store.
 hipError_t launch_assemble(const CellArgs& c, int n_pad, const double2* ang, const double2* ab, const double* kv,
                            const double* tau, double2* out, int64_t ld, int n_store, hipStream_t s);
+// The same with A and B in separate stacks: A rows atom*N_L + L, B rows N_atoms*N_L + atom*N_L + L.
+hipError_t launch_assemble_split(const CellArgs& c, int n_pad, const double2* ang, const double2* ab, const double* kv,
+                                 const double* tau, double2* out, int64_t ld, int n_store, hipStream_t s);
+// X = U B over the stacked B rows (atom, L), U = diag(||udot_l||) of the atom's type.
+hipError_t launch_udot_scale(const CellArgs& c, const TypeConsts* consts, int n_pad, const double2* B, double2* X,
+                             hipStream_t s);
 // dst[r][G] = src[r][G] for G < ng, 0 up to n_pad (rows r < rows; rows <= 65535).
 hipError_t launch_pack_rows(const double2* src, int ng, int rows, double2* dst, int n_pad, hipStream_t s);
 // rows [row0, row1) of a [*][ld] complex array set to zero.
@@ -111,6 +120,16 @@ hipError_t launch_scale_rows(const double2* X, const double* lam, int rows, int 
 // from the per-type row blocks of X, XL = lam X and Yx (nch chunks of 16 rows, kinds in kind[]).
 hipError_t launch_hs_fact(const double2* X, const double2* XL, const double2* Yx, const int* kind, int nch, int n,
                           int n_pad, int gr, double2* H, double2* S, int64_t ldh, hipStream_t s);
+
+// ---- the paper's algorithm on rocBLAS (baseline) ----
+int hsdla_blas_create(int device, void** handle, std::string& err);
+void hsdla_blas_destroy(void* handle);
+int hsdla_blas_workspace(void* handle, int algorithm, const CellArgs& c, int ng, int n_pad, size_t* bytes,
+                         std::string& err);
+int hsdla_blas_bind(void* handle, void* ws, size_t bytes, hipStream_t s, std::string& err);
+int hsdla_blas_enqueue(void* handle, int algorithm, const CellArgs& c, const TypeConsts* consts, int ng, int n_pad,
+                       const double2* T, const double2* A, const double2* B, double2* X, double2* H, double2* S,
+                       hipStream_t s, bool query, std::string& err);
 
 // ---- adjoint ----
 int gradtau_blocks(int n);

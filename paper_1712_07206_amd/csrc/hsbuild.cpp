@@ -41,6 +41,10 @@ struct hsbuild_s {
   int meta_cap = 0;
   std::vector<double> key_f;
   std::vector<int64_t> key_i;
+  // BLAS baseline: rocBLAS handle (created on first use) and its device-memory need per basis size
+  void* rocblas = nullptr;
+  int blas_ng = -1;
+  size_t blas_need = 0;
 };
 
 namespace {
@@ -88,6 +92,16 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
   L.kv = take(np * 4 * sizeof(double));
   L.ang = take((size_t)h.n_l * np * sizeof(double2));
   L.ab = take((size_t)h.n_types * (h.l_max + 1) * np * sizeof(double2));
+  if (mode == HSB_MODE_HSDLA) {
+    const size_t KA = (size_t)h.n_atoms * h.n_l;
+    L.hA = take(2 * KA * np * sizeof(double2));  // A stack, then the B stack right after it
+    L.hB = L.hA + KA * np * sizeof(double2);
+    L.hX = take(KA * np * sizeof(double2));
+    L.blas_bytes = h.blas_ng == ng ? h.blas_need : 0;
+    L.blas = take(L.blas_bytes);
+    L.end = off;
+    return L;
+  }
   if (mode == HSB_MODE_FACTORED) {
     L.R_f = fact_rows(h);
     L.tau0 = take(4 * sizeof(double));
@@ -268,6 +282,27 @@ BatchLayout make_batch_layout(const hsbuild_s& h, int n_k, const int32_t* ng) {
   return B;
 }
 
+// rocBLAS handle and its device-memory need for basis size ng (both algorithms).
+int blas_prepare(hsbuild_t h, int ng) {
+  if (!h->rocblas) {
+    std::string err;
+    if (hsdla_blas_create(h->device, &h->rocblas, err)) return fail(h, HSB_ERR_DEVICE, "%s", err.c_str());
+  }
+  if (h->blas_ng == ng) return HSB_OK;
+  const int n_pad = (int)round_up(ng, kTileN);
+  size_t need = 0;
+  for (int alg : {1, 3}) {
+    size_t b = 0;
+    std::string err;
+    if (hsdla_blas_workspace(h->rocblas, alg, h->cell, ng, n_pad, &b, err))
+      return fail(h, HSB_ERR_DEVICE, "%s", err.c_str());
+    need = std::max(need, b);
+  }
+  h->blas_ng = ng;
+  h->blas_need = need;
+  return HSB_OK;
+}
+
 void drop_graph(hsbuild_t h) {
   if (h->graph_exec) {
     if (h->graph_done) (void)hipEventSynchronize(h->graph_done);
@@ -396,6 +431,7 @@ void hsbuild_destroy(hsbuild_t h) {
   drop_graph(h);
   if (h->graph_done) (void)hipEventDestroy(h->graph_done);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  hsdla_blas_destroy(h->rocblas);
   if (h->meta_host) (void)hipHostFree(h->meta_host);
   if (h->consts) (void)hipHostFree(h->consts);
   delete h;
@@ -408,8 +444,9 @@ size_t hsbuild_workspace_bytes(hsbuild_t h, int32_t mode, int32_t n_k, const int
     return 0;
   }
   if (mode == HSB_MODE_FORWARD || mode == HSB_MODE_COEFFICIENTS || mode == HSB_MODE_BACKWARD ||
-      mode == HSB_MODE_FACTORED) {
+      mode == HSB_MODE_FACTORED || mode == HSB_MODE_HSDLA) {
     if (n_k != 1 || check_ng(h, ng[0])) return 0;
+    if (mode == HSB_MODE_HSDLA && blas_prepare(h, ng[0])) return 0;
     return make_layout(*h, ng[0], mode).end;
   }
   if (mode == HSB_MODE_BATCH) {
@@ -544,6 +581,43 @@ int hsbuild_forward_factored(hsbuild_t h, const double k_frac[3], int32_t ng, co
                 "k_hs_fact");
   mark(h, 3, s);
   return rc;
+}
+
+int hsbuild_forward_hsdla(hsbuild_t h, int32_t algorithm, const double k_frac[3], int32_t ng, const int32_t* g,
+                          const double* tau, const void* T, void* H, void* S, void* ws, size_t ws_bytes,
+                          void* stream) {
+  if (!h) return HSB_ERR_ARG;
+  h->err.clear();
+  if (algorithm != 1 && algorithm != 3) return fail(h, HSB_ERR_ARG, "algorithm must be 1 or 3 (got %d)", algorithm);
+  if (!k_frac || !g || !tau || !T || !H || !S) return fail(h, HSB_ERR_ARG, "null k_frac, g, tau, T, H or S");
+  if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
+  int rc = check_ng(h, ng);
+  if (rc) return rc;
+  if ((rc = check_device(h))) return rc;
+  if ((rc = blas_prepare(h, ng))) return rc;
+  const Layout L = make_layout(*h, ng, HSB_MODE_HSDLA);
+  if ((rc = check_ws(h, L, ws, ws_bytes))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  std::string err;
+  if (hsdla_blas_bind(h->rocblas, L.blas_bytes ? w + L.blas : nullptr, L.blas_bytes, s, err))
+    return fail(h, HSB_ERR_DEVICE, "%s", err.c_str());
+  mark(h, 0, s);
+  CellArgs c;
+  if ((rc = enqueue_tables(h, L, k_frac, g, w, s, c))) return rc;
+  // A stack (rows (atom, L)) followed by the B stack
+  rc = launched(h, launch_assemble_split(c, L.n_pad, (const double2*)(w + L.ang), (const double2*)(w + L.ab),
+                                         (const double*)(w + L.kv), tau, (double2*)(w + L.hA), L.n_pad, L.n_pad, s),
+                "k_assemble");
+  if (rc) return rc;
+  mark(h, 1, s);
+  mark(h, 2, s);
+  if (hsdla_blas_enqueue(h->rocblas, algorithm, c, (const TypeConsts*)(w + L.consts), ng, L.n_pad, (const double2*)T,
+                         (const double2*)(w + L.hA), (const double2*)(w + L.hB), (double2*)(w + L.hX), (double2*)H,
+                         (double2*)S, s, false, err))
+    return fail(h, HSB_ERR_DEVICE, "%s", err.c_str());
+  mark(h, 3, s);
+  return HSB_OK;
 }
 
 int hsbuild_forward_coefficients(hsbuild_t h, int32_t ng, const void* coef, const void* T, void* H, void* S,

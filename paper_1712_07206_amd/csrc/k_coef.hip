@@ -105,7 +105,7 @@ constexpr int kAtomGroup = 8;
 __global__ void __launch_bounds__(256) k_assemble(CellArgs c, int n_pad, const double2* __restrict__ ang,
                                                   const double2* __restrict__ ab, const double* __restrict__ kv,
                                                   const double* __restrict__ tau, double2* __restrict__ out,
-                                                  int64_t ld, int n_store) {
+                                                  int64_t ld, int n_store, int rows_per_atom, int64_t b_off) {
   const int G = blockIdx.x * blockDim.x + threadIdx.x;
   const int a0 = blockIdx.y * kAtomGroup;
   const int na = min(kAtomGroup, c.n_atoms - a0);
@@ -120,7 +120,7 @@ __global__ void __launch_bounds__(256) k_assemble(CellArgs c, int n_pad, const d
     sincos(arg, &ps[q], &pc[q]);
     abt[q] = ab + (int64_t)atom_type_of(c, atom) * (c.l_max + 1) * n_pad + G;
   }
-  const int rows = 2 * c.n_l;
+  const int rows = rows_per_atom;
   int L = 0;
   for (int l = 0; l <= c.l_max; ++l) {
     double par[kAtomGroup], pai[kAtomGroup], pbr[kAtomGroup], pbi[kAtomGroup];
@@ -138,10 +138,26 @@ __global__ void __launch_bounds__(256) k_assemble(CellArgs c, int n_pad, const d
         if (q < na) {
           const int64_t rowA = (int64_t)(a0 + q) * rows + L;
           out[rowA * ld + G] = make_double2(par[q] * y.x - pai[q] * y.y, par[q] * y.y + pai[q] * y.x);
-          out[(rowA + c.n_l) * ld + G] = make_double2(pbr[q] * y.x - pbi[q] * y.y, pbr[q] * y.y + pbi[q] * y.x);
+          out[(rowA + b_off) * ld + G] = make_double2(pbr[q] * y.x - pbi[q] * y.y, pbr[q] * y.y + pbi[q] * y.x);
         }
       }
     }
+  }
+}
+
+// X = U B over the stacked B rows (atom, L): row r scaled by ||udot_l|| of the atom's type.
+__global__ void __launch_bounds__(256) k_udot_scale(CellArgs c, const TypeConsts* __restrict__ consts, int n_pad,
+                                                    const double2* __restrict__ B, double2* __restrict__ X) {
+  const int G = blockIdx.x * blockDim.x + threadIdx.x;
+  if (G >= n_pad) return;
+  const int rows = c.n_atoms * c.n_l;
+  for (int r = blockIdx.y; r < rows; r += gridDim.y) {
+    const int atom = r / c.n_l, L = r % c.n_l;
+    int l = 0;
+    while ((l + 1) * (l + 1) <= L) ++l;
+    const double u = sqrt(consts->udot2[atom_type_of(c, atom)][l]);
+    const double2 v = B[(int64_t)r * n_pad + G];
+    X[(int64_t)r * n_pad + G] = make_double2(u * v.x, u * v.y);
   }
 }
 
@@ -177,7 +193,24 @@ hipError_t launch_lambda(const CellArgs& c, const TypeConsts* consts, int K_pad,
 hipError_t launch_assemble(const CellArgs& c, int n_pad, const double2* ang, const double2* ab, const double* kv,
                            const double* tau, double2* out, int64_t ld, int n_store, hipStream_t s) {
   dim3 grid((n_store + 255) / 256, (c.n_atoms + kAtomGroup - 1) / kAtomGroup);
-  hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, c, n_pad, ang, ab, kv, tau, out, ld, n_store);
+  hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, c, n_pad, ang, ab, kv, tau, out, ld, n_store, 2 * c.n_l,
+                     (int64_t)c.n_l);
+  return hipGetLastError();
+}
+
+hipError_t launch_assemble_split(const CellArgs& c, int n_pad, const double2* ang, const double2* ab, const double* kv,
+                                 const double* tau, double2* out, int64_t ld, int n_store, hipStream_t s) {
+  dim3 grid((n_store + 255) / 256, (c.n_atoms + kAtomGroup - 1) / kAtomGroup);
+  hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, c, n_pad, ang, ab, kv, tau, out, ld, n_store, c.n_l,
+                     (int64_t)c.n_atoms * c.n_l);
+  return hipGetLastError();
+}
+
+hipError_t launch_udot_scale(const CellArgs& c, const TypeConsts* consts, int n_pad, const double2* B, double2* X,
+                             hipStream_t s) {
+  const int rows = c.n_atoms * c.n_l;
+  dim3 grid((n_pad + 255) / 256, rows < 1024 ? rows : 1024);
+  hipLaunchKernelGGL(k_udot_scale, grid, dim3(256), 0, s, c, consts, n_pad, B, X);
   return hipGetLastError();
 }
 

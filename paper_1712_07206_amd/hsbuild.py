@@ -166,6 +166,28 @@ class HSBuilder:
                                                  _ptr(ws), ws.numel(), _stream()), self._h)
         return H, S
 
+    def forward_hsdla(self, algorithm: int, k_frac, g: torch.Tensor, tau: torch.Tensor, T: torch.Tensor,
+                      H: Optional[torch.Tensor] = None, S: Optional[torch.Tensor] = None,
+                      ws: Optional[torch.Tensor] = None):
+        """H and S by the paper's BLAS sequence on rocBLAS (hsbuild_forward_hsdla):
+        algorithm 3 (refined) or 1 (original, H_AA by a full zgemm)."""
+        ng = int(g.shape[0])
+        g = _dev(g, torch.int32, "g", (ng, 3))
+        tau = _dev(tau, torch.float64, "tau", (self.n_atoms, 3))
+        T = _dev(T, torch.complex128, "T", (self.n_types, 2 * self.n_l, 2 * self.n_l))
+        if H is None:
+            H = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+        if S is None:
+            S = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+        H = _dev(H, torch.complex128, "H", (ng, ng))
+        S = _dev(S, torch.complex128, "S", (ng, ng))
+        if ws is None:
+            ws = self.workspace(N.HSB_MODE_HSDLA, [ng])
+        kf = (ctypes.c_double * 3)(*[float(x) for x in k_frac])
+        N.check(N.lib().hsbuild_forward_hsdla(self._h, int(algorithm), kf, ng, _ptr(g), _ptr(tau), _ptr(T), _ptr(H),
+                                              _ptr(S), _ptr(ws), ws.numel(), _stream()), self._h)
+        return H, S
+
     def backward(self, k_frac, g: torch.Tensor, tau: torch.Tensor, T: torch.Tensor, gH: torch.Tensor,
                  gS: torch.Tensor, gT: Optional[torch.Tensor] = None, gtau: Optional[torch.Tensor] = None):
         """Gradients of a real loss with Hermitian dL/dH = gH and dL/dS = gS
