@@ -66,9 +66,11 @@ __global__ void __launch_bounds__(256) k_fact_rows(CellArgs c, const TypeConsts*
   const int rr = r - base;  // base is a multiple of 16
   double lam;
   int kd;
+  int valid;  // data rows in this row's chunk
   if (rr < Ep) {
     lam = rr < nt ? 1.0 : 0.0;
     kd = rr / FK == Ep / FK - 1 ? 3 : 0;
+    valid = min(FK, nt - rr / FK * FK);
   } else {
     const int m = rr - Ep;
     if (m < c.n_l) {
@@ -82,7 +84,9 @@ __global__ void __launch_bounds__(256) k_fact_rows(CellArgs c, const TypeConsts*
       lam = 0.0;
     }
     kd = m / FK == Mp / FK - 1 ? 2 : 1;
+    valid = min(FK, K - m / FK * FK);
   }
+  kd |= ((valid + 3) / 4 - 1) << 2;
   lamx[r] = lam;
   if (rr % FK == 0) kind[r / FK] = kd;
 }
@@ -102,8 +106,9 @@ typedef __attribute__((address_space(3))) void* lds_ptr;
 
 // Rows of X, XL and Yx come type by type: the type's E rows, then its W0 rows,
 // each block padded with zero rows to a multiple of 16, so every 16-row chunk is
-// one kind: kind[c] = 0 (phases), 3 (the type's last phase chunk), 1 (W0 rows),
-// 2 (the type's last W0 chunk, after which M * P is folded into H and S).
+// one kind: kind[c] & 3 = 0 (phases), 3 (the type's last phase chunk), 1 (W0 rows),
+// 2 (the type's last W0 chunk, after which M * P is folded into H and S); kind[c] >> 2
+// is the number of 4-row steps of the chunk that hold data rows, minus one.
 // XL = lam X (lam = 1 on phase rows, ||udot_l||^2 on B rows) and Yx is zero on
 // phase rows, so a phase chunk adds E^H E to the S slot and nothing to the H slot.
 __global__ void __launch_bounds__(FNT, 1) k_hs_fact(const d2* __restrict__ X, const d2* __restrict__ XL,
@@ -153,16 +158,20 @@ __global__ void __launch_bounds__(FNT, 1) k_hs_fact(const d2* __restrict__ X, co
   issue(0, 0);
   for (int c = 0; c < nch; ++c) {
     const int b = c & 1;
-    const int kd = kind[c];         // uniform
+    const int kc = kind[c];         // uniform
+    const int kd = kc & 3, nks = (kc >> 2) + 1;
+    const bool hslot = kd == 1 || kd == 2;
     __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of chunk c have landed
     __syncthreads();                // everyone's have, and buffer b^1 is free
     if (c + 1 < nch) issue(c + 1, b ^ 1);
     const d2* L = lds[b];
     const d2* R = lds[b] + FK * FM;
     const d2* Yl = lds[b] + 2 * FK * FM;
-    // one MFMA path for every chunk: on phase chunks Y is zero and the S slot collects P
+    // every chunk adds X^H XL to the S slot (P_t on phase chunks); W0 chunks also add
+    // X^H Yx to the H slot.  Only the 4-row steps that hold data rows are run.
 #pragma unroll
     for (int ks = 0; ks < FK / 4; ++ks) {
+      if (ks >= nks) break;
       const int kk = ks * 4 + (lane >> 4);
       double ar[2], ai[2], an[2];
 #pragma unroll
@@ -174,14 +183,19 @@ __global__ void __launch_bounds__(FNT, 1) k_hs_fact(const d2* __restrict__ X, co
       const d2 wv = R[kk * FM + wc * 16 + (lane & 15)];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        mhR[i] = MFMA(ar[i], yv.x, mhR[i]);
-        mhI[i] = MFMA(ar[i], yv.y, mhI[i]);
         msR[i] = MFMA(ar[i], wv.x, msR[i]);
         msI[i] = MFMA(ar[i], wv.y, msI[i]);
-        mhR[i] = MFMA(ai[i], yv.y, mhR[i]);
-        mhI[i] = MFMA(an[i], yv.x, mhI[i]);
         msR[i] = MFMA(ai[i], wv.y, msR[i]);
         msI[i] = MFMA(an[i], wv.x, msI[i]);
+      }
+      if (hslot) {
+#pragma unroll
+        for (int i = 0; i < 2; ++i) {
+          mhR[i] = MFMA(ar[i], yv.x, mhR[i]);
+          mhI[i] = MFMA(ar[i], yv.y, mhI[i]);
+          mhR[i] = MFMA(ai[i], yv.y, mhR[i]);
+          mhI[i] = MFMA(an[i], yv.x, mhI[i]);
+        }
       }
     }
     if (kd == 3) {  // the type's last phase chunk: the S slot holds P_t
