@@ -20,6 +20,16 @@ this order:
 6. (loss workload only) W then V: Hermitian N_G x N_G, off-diagonal complex
    normal with E|z|^2 = 1/N_G^2, real diagonal N(0, 1/N_G^2).
 
+Inversion-symmetric workloads (`inversion=True`) place each type's atoms as
+pairs (tau, -tau) about the origin, the first atom of a type with an odd count
+at the origin itself (at most one such type), so the positions are drawn one
+per pair, and the distance rule covers both members.  Their T blocks come
+from the same draws, made invariant under the two symmetries that make H and
+S real: time reversal, T[(X,l,m),(X',l',m')] -> (-1)^(m+m') conj(T[(X,l,-m),(X',l',-m')])
+(the block is replaced by the mean of itself and its image), and inversion
+at the site, which removes the entries with l + l' odd.  `partner[a]` is the
+atom paired with a (a itself at the origin).
+
 The plane-wave basis of a k-point is the N_G reciprocal vectors G with the
 smallest |k+G|, ties broken lexicographically on the integer triple; the
 cut-off K_max is the midpoint between the N_G-th and (N_G+1)-th norms, so the
@@ -50,6 +60,7 @@ class CellConfig:
     ng_range: Optional[tuple] = None  # inclusive per-k basis-size range (multi-k)
     min_sep: float = 3.0
     with_loss: bool = False
+    inversion: bool = False
 
     @property
     def n_types(self) -> int:
@@ -73,6 +84,11 @@ CONFIGS = {
                   n_k=64, ng_range=(2800, 3400)),
     4: CellConfig(4, "cubic24_2x32_l10_ng6000", (24.0, 24.0, 24.0), (32, 32), (2.2, 2.2), 10,
                   n_g=6000, with_loss=True),
+    # inversion-symmetric cells (real-symmetric H and S)
+    5: CellConfig(5, "cubic16_inv_2x8+7_l6_ng1500", (16.0, 16.0, 16.0), (8, 7), (1.8, 2.0), 6, n_g=1500,
+                  inversion=True),
+    6: CellConfig(6, "cubic30_inv_4x32_l10_ng12000", (30.0, 30.0, 30.0), (32, 32, 32, 32),
+                  (2.2, 2.2, 2.2, 2.2), 10, n_g=12000, inversion=True),
 }
 
 
@@ -106,6 +122,66 @@ def basis_for_k(lattice: np.ndarray, k_frac: np.ndarray, n_g: int):
         raise ValueError("tie at the basis cut-off: N_G=%d cannot be met exactly" % n_g)
     g = grid[order[:n_g]].astype(np.int32)
     return np.ascontiguousarray(g), 0.5 * (k_lo + k_hi)
+
+
+def _min_image_ok(f, placed, lattice, need):
+    if len(placed) == 0:
+        return True
+    d = f - np.asarray(placed)
+    d -= np.round(d)
+    return bool(np.all(np.linalg.norm(d @ lattice, axis=1) >= need))
+
+
+def _place_pairs(rng, lattice, cfg: CellConfig):
+    """Inversion-symmetric placement: per type, an atom at the origin if the
+    count is odd, then pairs (f, -f) in consecutive slots."""
+    radii = np.asarray(cfg.r_mt, dtype=np.float64)
+    types, frac, partner, rads = [], [], [], []
+    if sum(n % 2 for n in cfg.atoms_per_type) > 1:
+        raise ValueError("%s: at most one type may have an atom at the origin" % cfg.name)
+    for t, n in enumerate(cfg.atoms_per_type):
+        if n % 2:
+            need = np.maximum(cfg.min_sep, radii[t] + np.asarray(rads)) if rads else 0.0
+            if not _min_image_ok(np.zeros(3), frac, lattice, need):
+                raise RuntimeError("origin is occupied in %s" % cfg.name)
+            partner.append(len(frac))
+            types.append(t)
+            frac.append(np.zeros(3))
+            rads.append(radii[t])
+        for _pair in range(n // 2):
+            for _attempt in range(200000):
+                f = rng.uniform(0.0, 1.0, 3)
+                need = np.maximum(cfg.min_sep, radii[t] + np.asarray(rads)) if rads else 0.0
+                d2 = (2.0 * f) - np.round(2.0 * f)  # separation of f and -f
+                if (_min_image_ok(f, frac, lattice, need) and _min_image_ok(-f, frac, lattice, need)
+                        and np.linalg.norm(d2 @ lattice) >= max(cfg.min_sep, 2 * radii[t])):
+                    break
+            else:
+                raise RuntimeError("could not place a pair of type %d in %s" % (t, cfg.name))
+            i = len(frac)
+            partner.extend([i + 1, i])
+            types.extend([t, t])
+            frac.extend([f, -f])
+            rads.extend([radii[t], radii[t]])
+    return np.asarray(types, dtype=np.int32), np.asarray(frac) @ lattice, np.asarray(partner, dtype=np.int32)
+
+
+def _symmetric_T(T, l_max):
+    """The time-reversal mean and the site-inversion projection of a per-type
+    Hermitian block on (A|B, l, m), L = l^2 + l + m."""
+    n_l = (l_max + 1) ** 2
+    lv = np.concatenate([[l] * (2 * l + 1) for l in range(l_max + 1)])
+    mv = np.concatenate([np.arange(-l, l + 1) for l in range(l_max + 1)])
+    flip = np.concatenate([lv * lv + lv - mv, n_l + lv * lv + lv - mv])  # index of (X, l, -m)
+    sign = np.concatenate([(-1.0) ** mv, (-1.0) ** mv])
+    ll = np.concatenate([lv, lv])
+    out = []
+    for A in T:
+        image = sign[:, None] * sign[None, :] * np.conj(A[np.ix_(flip, flip)])
+        B = 0.5 * (A + image)
+        B[(ll[:, None] + ll[None, :]) % 2 == 1] = 0.0
+        out.append(0.5 * (B + B.conj().T))
+    return np.stack(out)
 
 
 def _place_atoms(rng, lattice, cfg: CellConfig):
@@ -158,12 +234,18 @@ def _draw(cfg: CellConfig, n_g_override: Optional[int]):
     targets = None
     if cfg.ng_range is not None:
         targets = rng.integers(cfg.ng_range[0], cfg.ng_range[1] + 1, cfg.n_k)
-    atom_type, tau = _place_atoms(rng, lattice, cfg)
+    partner = None
+    if cfg.inversion:
+        atom_type, tau, partner = _place_pairs(rng, lattice, cfg)
+    else:
+        atom_type, tau = _place_atoms(rng, lattice, cfg)
     radial = _radial(rng, cfg.n_types, cfg.l_max)
     udot_norm2 = rng.uniform(0.01, 0.1, (cfg.n_types, cfg.l_max + 1))
     m = 2 * cfg.n_l
     T = np.stack([_hermitian_block(rng, m, lambda n: rng.uniform(-2.0, 2.0, n), 0.05)
                   for _ in range(cfg.n_types)])
+    if cfg.inversion:
+        T = _symmetric_T(T, cfg.l_max)
     case = dict(
         name=cfg.name, config=cfg.index, lattice=lattice, omega=float(abs(np.linalg.det(lattice))),
         n_types=cfg.n_types, n_atoms=cfg.n_atoms, l_max=cfg.l_max, n_l=cfg.n_l,
@@ -171,6 +253,8 @@ def _draw(cfg: CellConfig, n_g_override: Optional[int]):
         r_mt=np.asarray(cfg.r_mt, dtype=np.float64), radial=radial, udot_norm2=udot_norm2,
         T=np.ascontiguousarray(T),
     )
+    if partner is not None:
+        case["partner"] = partner
     return rng, case, k_frac, targets
 
 

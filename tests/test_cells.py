@@ -75,3 +75,21 @@ def test_loss_matrices_hermitian():
         M = c[key]
         assert M.shape == (300, 300)
         np.testing.assert_array_equal(M, M.conj().T)
+
+
+def test_inversion_cells_are_paired():
+    from flapw_cells import make_case
+    for idx in (5, 6):
+        case = make_case(idx, n_g=64)
+        p, tau, t = case["partner"], case["tau"], case["atom_type"]
+        assert np.array_equal(p[p], np.arange(len(p)))
+        assert np.array_equal(t[p], t)
+        assert np.abs(tau[p] + tau).max() == 0.0
+        assert int((p == np.arange(len(p))).sum()) <= 1  # at most the origin atom
+        # muffin tins keep the minimum separation, pairs included
+        lat = case["lattice"]
+        frac = tau @ np.linalg.inv(lat)
+        for i in range(len(tau)):
+            d = frac[i] - frac[i + 1:]
+            d -= np.round(d)
+            assert np.all(np.linalg.norm(d @ lat, axis=1) >= 3.0 - 1e-9)

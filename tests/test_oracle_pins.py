@@ -398,3 +398,26 @@ def test_flops_vs_paper_alg3_counts():
         paper = 20.0 * n_a * n_l * n_g ** 2 + 24.0 * n_a * n_l ** 2 * n_g
         ours = o.flops_forward(n_a, n_l, n_g)
         assert 1.2 < paper / ours < 1.26
+
+
+def test_inversion_symmetric_cell_gives_real_h_and_s():
+    """With the atoms in inversion pairs about the origin and T invariant under
+    time reversal and site inversion, each pair's contribution is twice the
+    real part of one member's, so H and S are real symmetric (the real case of
+    Sec. 2.1).  Breaking either symmetry brings back an imaginary part."""
+    from flapw_cells import make_case
+    case = make_case(5, n_g=300)
+    H, S = o.hs(case)
+    assert np.linalg.norm(H.imag) <= 1e-13 * np.linalg.norm(H)
+    assert np.linalg.norm(S.imag) <= 1e-13 * np.linalg.norm(S)
+    # a general Hermitian T on the same positions: H complex, S (T-free) still real
+    rng = np.random.default_rng(3)
+    m = 2 * case["n_l"]
+    Z = rng.normal(size=(case["n_types"], m, m)) + 1j * rng.normal(size=(case["n_types"], m, m))
+    H2, _ = o.hs(dict(case, T=0.05 * (Z + np.conj(np.transpose(Z, (0, 2, 1))))))
+    assert np.linalg.norm(H2.imag) > 1e-3 * np.linalg.norm(H2)
+    # move one atom off its pair position: S picks up an imaginary part
+    tau = case["tau"].copy()
+    tau[0] += np.array([0.31, -0.2, 0.05])
+    _, S3 = o.hs(dict(case, tau=tau))
+    assert np.linalg.norm(S3.imag) > 1e-3 * np.linalg.norm(S3)
