@@ -200,6 +200,63 @@ def hsdla_leg(args, case, g, tau, T, H, S, ms_fp64) -> dict:
     return out
 
 
+def real_leg(args) -> dict:
+    """The inversion-symmetric cell of the bench shape (4 types x 32 atoms as 16
+    inversion pairs each, l_max 10, N_G 12000): hsbuild_forward (complex) and
+    hsbuild_forward_real (real symmetric) on the same inputs; time of each and
+    the difference of the real outputs from the complex ones' real parts."""
+    import numpy as np
+    import torch
+
+    from flapw_cells import make_case
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    case = make_case(6)
+    n, n_at, n_l = case["n_g"], case["n_atoms"], case["n_l"]
+    n_rep = int((case["partner"] >= np.arange(n_at)).sum())
+    flops_c = 16.0 * n_at * n_l * n * (n + 1) + 32.0 * n_at * n_l * n_l * n
+    flops_r = 8.0 * n_rep * n_l * n * (n + 1) + 32.0 * n_rep * n_l * n_l * n
+    b = HSBuilder.from_case(case)
+    g, tau, T = case_tensors(case)
+    Hc = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    Sc = torch.empty_like(Hc)
+    Hr = torch.empty((n, n), dtype=torch.float64, device="cuda")
+    Sr = torch.empty_like(Hr)
+    wsb = max(b.workspace_bytes(N.HSB_MODE_FORWARD, [n]), b.workspace_bytes(N.HSB_MODE_REAL, [n]))
+    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    kf = case["k_frac"]
+    reps = max(1, min(args.steps, 3))
+    ms_c = timed(lambda: b.forward(kf, g, tau, T, Hc, Sc, ws=ws), reps)
+    ms_r = timed(lambda: b.forward_real(kf, g, tau, case["partner"], T, Hr, Sr, ws=ws), reps)
+    Hcu, Scu = torch.triu(Hc), torch.triu(Sc)
+    imag = (torch.linalg.norm(Hcu.imag) / torch.linalg.norm(Hcu)).item()
+    eh = (torch.linalg.norm(torch.triu(Hr) - Hcu.real) / torch.linalg.norm(Hcu.real)).item()
+    es = (torch.linalg.norm(torch.triu(Sr) - Scu.real) / torch.linalg.norm(Scu.real)).item()
+    del Hc, Sc, Hr, Sr, Hcu, Scu, ws
+    b.close()
+    torch.cuda.empty_cache()
+    log("real-symmetric %s: complex path %.3f ms, real path %.3f ms (%.2fx), %.2f TFLOP/s on its own %.4g TFLOP; "
+        "rel err vs complex H %.2e S %.2e, |Im H|/|H| %.1e" % (case["name"], ms_c, ms_r, ms_c / ms_r,
+                                                            flops_r / (ms_r * 1e-3) / 1e12, flops_r / 1e12, eh, es,
+                                                            imag))
+    return {"workload": case["name"], "n_g": n, "representatives": n_rep, "ms_complex": round(ms_c, 4),
+            "ms_real": round(ms_r, 4), "speedup": round(ms_c / ms_r, 4), "flops_real": flops_r,
+            "flops_complex": flops_c, "real_tflops": round(flops_r / (ms_r * 1e-3) / 1e12, 4),
+            "complex_imag_rel": imag, "rel_err_vs_complex": {"H": eh, "S": es}}
+
+
 def batch_leg(args) -> dict:
     """The multi-k workload (64 k-points, N_G 2800-3400, T shared): one captured
     graph with a persistent contraction, against 64 sequential forward calls."""
@@ -324,6 +381,7 @@ def main() -> int:
     ap.add_argument("--tile-group", type=int, default=None, help="contraction tile order (skips tuning)")
     ap.add_argument("--no-factored", action="store_true", help="skip the type-factored leg")
     ap.add_argument("--no-hsdla", action="store_true", help="skip the rocBLAS HSDLA baseline leg")
+    ap.add_argument("--no-real", action="store_true", help="skip the real-symmetric (inversion) leg")
     ap.add_argument("--split-slices", type=int, default=5,
                     help="also time the BF16 split-precision path with this many slices (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -447,6 +505,8 @@ def main() -> int:
         result["split_speedup"] = result["split"]["speedup"]
     del H, S, ws
     torch.cuda.empty_cache()
+    if not args.no_real:
+        result["real_symmetric"] = real_leg(args)
     if not args.no_adjoint:
         result["adjoint"] = adjoint_leg(args)
     if not args.no_batch:

@@ -64,7 +64,7 @@ enum { HSB_FP64 = 0, HSB_SPLIT_FP16 = 1, HSB_SPLIT_BF16 = 2 };
 
 /* Workspace modes for hsbuild_workspace_bytes. */
 enum { HSB_MODE_FORWARD = 0, HSB_MODE_BACKWARD = 1, HSB_MODE_BATCH = 2, HSB_MODE_COEFFICIENTS = 3, HSB_MODE_FACTORED = 4,
-       HSB_MODE_HSDLA = 5 };
+       HSB_MODE_HSDLA = 5, HSB_MODE_REAL = 6 };
 
 #define HSB_MAX_TYPES 16
 #define HSB_MAX_LMAX 12
@@ -127,6 +127,24 @@ int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32
  * Workspace: hsbuild_workspace_bytes(h, HSB_MODE_FACTORED, 1, &ng). */
 int hsbuild_forward_factored(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
                              const void* T, void* H, void* S, void* ws, size_t ws_bytes, void* stream);
+
+/* H and S of an inversion-symmetric cell as real symmetric matrices (the
+ * real case that Sec. 2.1 allows besides the complex Hermitian one).
+ * partner: host int32 [n_atoms], partner[a] = the atom at -tau_a (a itself for
+ * an atom at the origin); it must be an involution within each type.  The
+ * caller guarantees the symmetry: tau_partner[a] = -tau_a, and each T_t
+ * invariant under time reversal, T[(X,l,m),(X',l',m')] = (-1)^(m+m')
+ * conj(T[(X,l,-m),(X',l',-m')]), with no entries of odd l + l'.  Then each
+ * pair contributes twice the real part of one member's term, so only one atom
+ * of each pair is built and the contraction keeps only real parts: about a
+ * quarter of the work of hsbuild_forward.  H, S: device double [ng][ng],
+ * upper triangle written; equal to the real parts of hsbuild_forward's
+ * outputs up to FP64 rounding (undefined if the symmetry does not hold).
+ * Other arguments as hsbuild_forward (FP64 whatever the precision).
+ * Workspace: hsbuild_workspace_bytes(h, HSB_MODE_REAL, 1, &ng). */
+int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
+                         const int32_t* partner, const void* T, double* H, double* S, void* ws, size_t ws_bytes,
+                         void* stream);
 
 /* The paper's own algorithm on the vendor BLAS (rocBLAS), a baseline for the
  * fused kernels: A and B stacks built on the GPU as for hsbuild_forward, then

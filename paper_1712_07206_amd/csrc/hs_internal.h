@@ -50,6 +50,8 @@ struct Layout {
   size_t X = 0, XL = 0, Yx = 0, lamx = 0, kind = 0, tau0 = 0;
   // BLAS baseline only: A and B stacks, X scratch, rocBLAS's device memory
   size_t hA = 0, hB = 0, hX = 0, blas = 0, blas_bytes = 0;
+  // real-symmetric only: representative indices and weights, their positions, row weights
+  size_t rep = 0, repw = 0, tau_rep = 0, wrow = 0;
 };
 
 // Per-k-point entry of the batched contraction's tile list (device copy in the workspace).
@@ -72,6 +74,10 @@ hipError_t launch_assemble(const CellArgs& c, int n_pad, const double2* ang, con
 // The same with A and B in separate stacks: A rows atom*N_L + L, B rows N_atoms*N_L + atom*N_L + L.
 hipError_t launch_assemble_split(const CellArgs& c, int n_pad, const double2* ang, const double2* ab, const double* kv,
                                  const double* tau, double2* out, int64_t ld, int n_store, hipStream_t s);
+// Inversion pairs: tau_rep[r] = tau[rep[r]] (r < n_rep); with lam non-null, wrow[k] = w[k / rows]
+// over the stacked rows (0 for k >= n_rep rows) and lam[k] *= wrow[k], k < K_pad.
+hipError_t launch_rep_setup(const double* tau, const int* rep, const double* w, int n_rep, int rows, int K_pad,
+                            double* tau_rep, double* wrow, double* lam, hipStream_t s);
 // X = U B over the stacked B rows (atom, L), U = diag(||udot_l||) of the atom's type.
 hipError_t launch_udot_scale(const CellArgs& c, const TypeConsts* consts, int n_pad, const double2* B, double2* X,
                              hipStream_t s);
@@ -87,6 +93,10 @@ hipError_t launch_tprod(const CellArgs& c, const double2* T, const double2* W, d
 // waves: 4 (64 x 32 per wave) or 8 (32 x 32 per wave).
 hipError_t launch_hs_fp64(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
                           int gr, int waves, double2* H, double2* S, int64_t ldh, hipStream_t s);
+
+// The same contraction keeping only the real parts, Re(W^H Y) and Re(W^H lam W), as doubles.
+hipError_t launch_hs_fp64_real(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
+                               int gr, int waves, double* H, double* S, int64_t ldh, hipStream_t s);
 
 // Number of 128 x 64 tiles the contraction covers for a padded basis size.
 int hs_tiles(int n_pad);

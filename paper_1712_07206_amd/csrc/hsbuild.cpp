@@ -41,6 +41,11 @@ struct hsbuild_s {
   int meta_cap = 0;
   std::vector<double> key_f;
   std::vector<int64_t> key_i;
+  // real-symmetric path: pinned sources of the representative upload and its completion event
+  int32_t* rep_host = nullptr;
+  double* repw_host = nullptr;
+  hipEvent_t rep_done = nullptr;
+  bool rep_pending = false;
   // BLAS baseline: rocBLAS handle (created on first use) and its device-memory need per basis size
   void* rocblas = nullptr;
   int blas_ng = -1;
@@ -127,6 +132,12 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
     L.slS = take(planes);
     L.slY = take(planes);
   }
+  if (mode == HSB_MODE_REAL) {
+    L.rep = take((size_t)h.n_atoms * sizeof(int32_t));
+    L.repw = take((size_t)h.n_atoms * sizeof(double));
+    L.tau_rep = take((size_t)h.n_atoms * 3 * sizeof(double));
+    L.wrow = take((size_t)L.K_pad * sizeof(double));
+  }
   if (mode == HSB_MODE_BACKWARD) {
     const size_t M = 2 * (size_t)h.n_l;
     L.PH = take((size_t)L.K_pad * np * sizeof(double2));
@@ -179,9 +190,10 @@ void destroy_events(hsbuild_t h) {
 }
 
 // Uploads the type constants and builds K vectors, angular factors and (a, b).
+// base: the cell to use instead of the handle's (the representatives of inversion pairs).
 int enqueue_tables(hsbuild_t h, const Layout& L, const double k_frac[3], const int32_t* g, char* ws,
-                   hipStream_t s, CellArgs& c) {
-  c = h->cell;
+                   hipStream_t s, CellArgs& c, const CellArgs* base = nullptr) {
+  c = base ? *base : h->cell;
   for (int i = 0; i < 3; ++i) c.kfrac[i] = k_frac[i];
   TypeConsts* dconsts = (TypeConsts*)(ws + L.consts);
   hipError_t e = hipMemcpyAsync(dconsts, h->consts, sizeof(TypeConsts), hipMemcpyHostToDevice, s);
@@ -193,9 +205,9 @@ int enqueue_tables(hsbuild_t h, const Layout& L, const double k_frac[3], const i
 
 // Tables, stacked coefficients W (pad rows zeroed), Y = T W per atom and lam.
 int enqueue_operands(hsbuild_t h, const Layout& L, const double k_frac[3], const int32_t* g, const double* tau,
-                     const void* T, char* ws, hipStream_t s) {
+                     const void* T, char* ws, hipStream_t s, const CellArgs* base = nullptr) {
   CellArgs c;
-  int rc = enqueue_tables(h, L, k_frac, g, ws, s, c);
+  int rc = enqueue_tables(h, L, k_frac, g, ws, s, c, base);
   if (rc) return rc;
   double2* W = (double2*)(ws + L.W);
   double2* Y = (double2*)(ws + L.Y);
@@ -432,6 +444,12 @@ void hsbuild_destroy(hsbuild_t h) {
   if (h->graph_done) (void)hipEventDestroy(h->graph_done);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   hsdla_blas_destroy(h->rocblas);
+  if (h->rep_done) {
+    (void)hipEventSynchronize(h->rep_done);
+    (void)hipEventDestroy(h->rep_done);
+  }
+  if (h->rep_host) (void)hipHostFree(h->rep_host);
+  if (h->repw_host) (void)hipHostFree(h->repw_host);
   if (h->meta_host) (void)hipHostFree(h->meta_host);
   if (h->consts) (void)hipHostFree(h->consts);
   delete h;
@@ -444,7 +462,7 @@ size_t hsbuild_workspace_bytes(hsbuild_t h, int32_t mode, int32_t n_k, const int
     return 0;
   }
   if (mode == HSB_MODE_FORWARD || mode == HSB_MODE_COEFFICIENTS || mode == HSB_MODE_BACKWARD ||
-      mode == HSB_MODE_FACTORED || mode == HSB_MODE_HSDLA) {
+      mode == HSB_MODE_FACTORED || mode == HSB_MODE_HSDLA || mode == HSB_MODE_REAL) {
     if (n_k != 1 || check_ng(h, ng[0])) return 0;
     if (mode == HSB_MODE_HSDLA && blas_prepare(h, ng[0])) return 0;
     return make_layout(*h, ng[0], mode).end;
@@ -579,6 +597,90 @@ int hsbuild_forward_factored(hsbuild_t h, const double k_frac[3], int32_t ng, co
   rc = launched(h, launch_hs_fact(X, XL, Yx, (const int*)(w + L.kind), L.R_f / 16, ng, L.n_pad, h->tile_group,
                                   (double2*)H, (double2*)S, ng, s),
                 "k_hs_fact");
+  mark(h, 3, s);
+  return rc;
+}
+
+int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
+                         const int32_t* partner, const void* T, double* H, double* S, void* ws, size_t ws_bytes,
+                         void* stream) {
+  if (!h) return HSB_ERR_ARG;
+  h->err.clear();
+  if (!k_frac || !g || !tau || !partner || !T || !H || !S)
+    return fail(h, HSB_ERR_ARG, "null k_frac, g, tau, partner, T, H or S");
+  if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
+  int rc = check_ng(h, ng);
+  if (rc) return rc;
+  // representatives: the lower index of each inversion pair (weight 2), atoms paired with themselves (weight 1)
+  const CellArgs& cell = h->cell;
+  auto type_of = [&](int a) {
+    int t = 0;
+    while (t + 1 < cell.n_types && a >= cell.type_start[t + 1]) ++t;
+    return t;
+  };
+  std::vector<int32_t> rep;
+  std::vector<double> wt;
+  CellArgs crep = cell;
+  for (int t = 0; t <= HSB_MAX_TYPES; ++t) crep.type_start[t] = 0;
+  for (int a = 0; a < h->n_atoms; ++a) {
+    const int p = partner[a];
+    if (p < 0 || p >= h->n_atoms || partner[p] != a)
+      return fail(h, HSB_ERR_ARG, "partner is not an involution at atom %d", a);
+    if (type_of(p) != type_of(a)) return fail(h, HSB_ERR_ARG, "atoms %d and %d are paired but differ in type", a, p);
+    if (p >= a) {
+      rep.push_back(a);
+      wt.push_back(p == a ? 1.0 : 2.0);
+      crep.type_start[type_of(a) + 1] += 1;
+    }
+  }
+  for (int t = 0; t < cell.n_types; ++t) crep.type_start[t + 1] += crep.type_start[t];
+  const int n_rep = (int)rep.size();
+  crep.n_atoms = n_rep;
+  const Layout L = make_layout(*h, ng, HSB_MODE_REAL);
+  if ((rc = check_ws(h, L, ws, ws_bytes))) return rc;
+  if ((rc = check_device(h))) return rc;
+  Layout Lr = L;  // the stacked rows of the representatives only
+  Lr.K = 2 * n_rep * h->n_l;
+  Lr.K_pad = (int)round_up(Lr.K, kTileK);
+  hipStream_t s = (hipStream_t)stream;
+  char* w = (char*)ws;
+  // upload the representatives from pinned memory (after the previous upload has been consumed)
+  if (!h->rep_host) {
+    if (hipHostMalloc((void**)&h->rep_host, sizeof(int32_t) * h->n_atoms, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&h->repw_host, sizeof(double) * h->n_atoms, hipHostMallocDefault) != hipSuccess ||
+        hipEventCreateWithFlags(&h->rep_done, hipEventDisableTiming) != hipSuccess)
+      return fail(h, HSB_ERR_DEVICE, "pinned buffer or event for the representatives");
+  }
+  if (h->rep_pending && hipEventSynchronize(h->rep_done) != hipSuccess)
+    return fail(h, HSB_ERR_DEVICE, "hipEventSynchronize failed");
+  h->rep_pending = false;
+  std::memcpy(h->rep_host, rep.data(), sizeof(int32_t) * n_rep);
+  std::memcpy(h->repw_host, wt.data(), sizeof(double) * n_rep);
+  mark(h, 0, s);
+  hipError_t e = hipMemcpyAsync(w + L.rep, h->rep_host, sizeof(int32_t) * n_rep, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(w + L.repw, h->repw_host, sizeof(double) * n_rep, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipEventRecord(h->rep_done, s);
+  if (e != hipSuccess) return launched(h, e, "upload of the representatives");
+  h->rep_pending = true;
+  const int rows = 2 * h->n_l;
+  double* tau_rep = (double*)(w + L.tau_rep);
+  rc = launched(h, launch_rep_setup(tau, (const int*)(w + L.rep), (const double*)(w + L.repw), n_rep, rows, 0,
+                                    tau_rep, nullptr, nullptr, s),
+                "k_rep_setup");
+  if (rc) return rc;
+  if ((rc = enqueue_operands(h, Lr, k_frac, g, tau_rep, T, w, s, &crep))) return rc;
+  // weights: lam *= w per row (S), Y rows times w (H)
+  double* lam = (double*)(w + L.lam);
+  double* wrow = (double*)(w + L.wrow);
+  double2* Y = (double2*)(w + L.Y);
+  rc = launched(h, launch_rep_setup(tau, (const int*)(w + L.rep), (const double*)(w + L.repw), n_rep, rows, Lr.K_pad,
+                                    tau_rep, wrow, lam, s),
+                "k_rep_setup");
+  if (!rc) rc = launched(h, launch_scale_rows(Y, wrow, Lr.K_pad, L.n_pad, Y, s), "k_scale_rows");
+  if (!rc)
+    rc = launched(h, launch_hs_fp64_real((const double2*)(w + L.W), Y, lam, Lr.K_pad, ng, L.n_pad, h->tile_group,
+                                         h->hs_waves, H, S, ng, s),
+                  "k_hs_fp64 (real)");
   mark(h, 3, s);
   return rc;
 }

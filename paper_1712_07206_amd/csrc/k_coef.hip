@@ -161,6 +161,26 @@ __global__ void __launch_bounds__(256) k_udot_scale(CellArgs c, const TypeConsts
   }
 }
 
+// Representatives of inversion pairs: tau_rep[r] = tau[rep[r]], wrow[k] = w[k / rows] for
+// the k < n_rep rows stacked rows (0 on pad rows), lam[k] *= wrow[k].
+__global__ void __launch_bounds__(256) k_rep_setup(const double* __restrict__ tau, const int* __restrict__ rep,
+                                                   const double* __restrict__ w, int n_rep, int rows, int K_pad,
+                                                   double* __restrict__ tau_rep, double* __restrict__ wrow,
+                                                   double* __restrict__ lam) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < n_rep) {
+    const int a = rep[k];
+    tau_rep[3 * k + 0] = tau[3 * a + 0];
+    tau_rep[3 * k + 1] = tau[3 * a + 1];
+    tau_rep[3 * k + 2] = tau[3 * a + 2];
+  }
+  if (k < K_pad && lam) {
+    const double v = k < n_rep * rows ? w[k / rows] : 0.0;
+    wrow[k] = v;
+    lam[k] *= v;
+  }
+}
+
 // Caller-given coefficients [rows][ng] into the padded layout [rows][n_pad] (zeros for G >= ng).
 __global__ void __launch_bounds__(256) k_pack_rows(const double2* __restrict__ src, int ng, int rows,
                                                    double2* __restrict__ dst, int n_pad) {
@@ -203,6 +223,14 @@ hipError_t launch_assemble_split(const CellArgs& c, int n_pad, const double2* an
   dim3 grid((n_store + 255) / 256, (c.n_atoms + kAtomGroup - 1) / kAtomGroup);
   hipLaunchKernelGGL(k_assemble, grid, dim3(256), 0, s, c, n_pad, ang, ab, kv, tau, out, ld, n_store, c.n_l,
                      (int64_t)c.n_atoms * c.n_l);
+  return hipGetLastError();
+}
+
+hipError_t launch_rep_setup(const double* tau, const int* rep, const double* w, int n_rep, int rows, int K_pad,
+                            double* tau_rep, double* wrow, double* lam, hipStream_t s) {
+  const int n = n_rep > K_pad ? n_rep : K_pad;
+  hipLaunchKernelGGL(k_rep_setup, dim3((n + 255) / 256), dim3(256), 0, s, tau, rep, w, n_rep, rows, K_pad, tau_rep,
+                     wrow, lam);
   return hipGetLastError();
 }
 

@@ -48,10 +48,12 @@ struct Smem {
 
 // One 128 x 64 tile (rows row0.., columns col0..) of H and S, upper triangle stored.
 // WR x 2 waves; each wave owns (128/WR) x 32 of both outputs: MI x 2 MFMA blocks.
-template <int WR>
+// REAL: only the real parts, Re(W^H Y) and Re(W^H lam W), into double outputs (the
+// real-symmetric case: half the MFMAs of the complex product).
+template <int WR, bool REAL = false>
 __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, const d2* __restrict__ Y,
                                         const double* __restrict__ lam, int K_pad, int n, int n_pad, int row0,
-                                        int col0, d2* __restrict__ H, d2* __restrict__ S, int64_t ldh) {
+                                        int col0, void* __restrict__ Hv, void* __restrict__ Sv, int64_t ldh) {
   constexpr int NT = 64 * WR * 2;   // threads
   constexpr int MI = BM / WR / 16;  // row blocks per wave
   constexpr int PL = BK * BM / NT, PR = BK * BN / NT;
@@ -125,34 +127,42 @@ __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, cons
       for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) hr[i][j] = MFMA(ar[i], yre[j], hr[i][j]);
+      if constexpr (!REAL) {
 #pragma unroll
-      for (int i = 0; i < MI; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) hi[i][j] = MFMA(ar[i], yim[j], hi[i][j]);
+          for (int j = 0; j < 2; ++j) hi[i][j] = MFMA(ar[i], yim[j], hi[i][j]);
+      }
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) sr[i][j] = MFMA(ar[i], wre[j], sr[i][j]);
+      if constexpr (!REAL) {
 #pragma unroll
-      for (int i = 0; i < MI; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) si[i][j] = MFMA(ar[i], wim[j], si[i][j]);
+          for (int j = 0; j < 2; ++j) si[i][j] = MFMA(ar[i], wim[j], si[i][j]);
+      }
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) hr[i][j] = MFMA(ai[i], yim[j], hr[i][j]);
+      if constexpr (!REAL) {
 #pragma unroll
-      for (int i = 0; i < MI; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) hi[i][j] = MFMA(an[i], yre[j], hi[i][j]);
+          for (int j = 0; j < 2; ++j) hi[i][j] = MFMA(an[i], yre[j], hi[i][j]);
+      }
 #pragma unroll
       for (int i = 0; i < MI; ++i)
 #pragma unroll
         for (int j = 0; j < 2; ++j) sr[i][j] = MFMA(ai[i], wim[j], sr[i][j]);
+      if constexpr (!REAL) {
 #pragma unroll
-      for (int i = 0; i < MI; ++i)
+        for (int i = 0; i < MI; ++i)
 #pragma unroll
-        for (int j = 0; j < 2; ++j) si[i][j] = MFMA(an[i], wre[j], si[i][j]);
+          for (int j = 0; j < 2; ++j) si[i][j] = MFMA(an[i], wre[j], si[i][j]);
+      }
     }
     if (c + 1 < nchunks) HS_LSTORE(b ^ 1);
     __syncthreads();
@@ -171,17 +181,22 @@ __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, cons
         const int col = col0 + wc * 32 + j * 16 + (lane & 15);
         if (row < n && col < n && col >= row) {
           const int64_t o = (int64_t)row * ldh + col;
-          H[o] = d2{hr[i][j][q], hi[i][j][q]};
-          S[o] = d2{sr[i][j][q], si[i][j][q]};
+          if constexpr (REAL) {
+            ((double*)Hv)[o] = hr[i][j][q];
+            ((double*)Sv)[o] = sr[i][j][q];
+          } else {
+            ((d2*)Hv)[o] = d2{hr[i][j][q], hi[i][j][q]};
+            ((d2*)Sv)[o] = d2{sr[i][j][q], si[i][j][q]};
+          }
         }
       }
 }
 
-template <int WR>
+template <int WR, bool REAL>
 __global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64(const d2* __restrict__ W, const d2* __restrict__ Y,
                                                      const double* __restrict__ lam, int K_pad, int n, int n_pad,
-                                                     int nbr, int num_wg, int gr, d2* __restrict__ H,
-                                                     d2* __restrict__ S, int64_t ldh) {
+                                                     int nbr, int num_wg, int gr, void* __restrict__ H,
+                                                     void* __restrict__ S, int64_t ldh) {
   __shared__ Smem sm;
   // dispatch is round-robin over XCDs: give XCD x the contiguous range of tile numbers
   const int x = blockIdx.x % kXcds;
@@ -191,7 +206,7 @@ __global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64(const d2* __restrict__ 
   int row0, col0;
   tile_origin(w, nbr, gr, row0, col0);
   if (col0 >= n) return;
-  hs_tile<WR>(sm, W, Y, lam, K_pad, n, n_pad, row0, col0, H, S, ldh);
+  hs_tile<WR, REAL>(sm, W, Y, lam, K_pad, n, n_pad, row0, col0, H, S, ldh);
 }
 
 template <int WR>
@@ -216,8 +231,8 @@ __global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64_batch(const d2* __restr
     int row0, col0;
     tile_origin(t - m.tile_start, m.nbr, gr, row0, col0);
     if (col0 >= m.n) continue;  // uniform across the workgroup
-    hs_tile<WR>(sm, ws + m.w_off, ws + m.y_off, lam, K_pad, m.n, m.n_pad, row0, col0, H + m.out_off,
-                S + m.out_off, m.n);
+    hs_tile<WR, false>(sm, ws + m.w_off, ws + m.y_off, lam, K_pad, m.n, m.n_pad, row0, col0, H + m.out_off,
+                       S + m.out_off, m.n);
   }
 }
 
@@ -233,11 +248,24 @@ hipError_t launch_hs_fp64(const double2* W, const double2* Y, const double* lam,
   const int nbr = n_pad / BM;
   const int num_wg = hs_tiles(n_pad);  // two 128 x 64 tiles per upper-triangle 128 x 128 super-tile
   if (waves == 8)
-    hipLaunchKernelGGL(k_hs_fp64<4>, dim3(num_wg), dim3(512), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad, n, n_pad,
-                       nbr, num_wg, gr, (d2*)H, (d2*)S, ldh);
+    hipLaunchKernelGGL((k_hs_fp64<4, false>), dim3(num_wg), dim3(512), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad,
+                       n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
   else
-    hipLaunchKernelGGL(k_hs_fp64<2>, dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad, n, n_pad,
-                       nbr, num_wg, gr, (d2*)H, (d2*)S, ldh);
+    hipLaunchKernelGGL((k_hs_fp64<2, false>), dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad,
+                       n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
+  return hipGetLastError();
+}
+
+hipError_t launch_hs_fp64_real(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
+                               int gr, int waves, double* H, double* S, int64_t ldh, hipStream_t s) {
+  const int nbr = n_pad / BM;
+  const int num_wg = hs_tiles(n_pad);
+  if (waves == 8)
+    hipLaunchKernelGGL((k_hs_fp64<4, true>), dim3(num_wg), dim3(512), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad,
+                       n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
+  else
+    hipLaunchKernelGGL((k_hs_fp64<2, true>), dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad,
+                       n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
   return hipGetLastError();
 }
 

@@ -188,6 +188,33 @@ class HSBuilder:
                                               _ptr(S), _ptr(ws), ws.numel(), _stream()), self._h)
         return H, S
 
+    def forward_real(self, k_frac, g: torch.Tensor, tau: torch.Tensor, partner, T: torch.Tensor,
+                     H: Optional[torch.Tensor] = None, S: Optional[torch.Tensor] = None,
+                     ws: Optional[torch.Tensor] = None):
+        """Real-symmetric H and S of an inversion-symmetric cell
+        (hsbuild_forward_real): float64 upper triangles.  partner[a] is the
+        atom at -tau_a (a for an atom at the origin)."""
+        ng = int(g.shape[0])
+        g = _dev(g, torch.int32, "g", (ng, 3))
+        tau = _dev(tau, torch.float64, "tau", (self.n_atoms, 3))
+        T = _dev(T, torch.complex128, "T", (self.n_types, 2 * self.n_l, 2 * self.n_l))
+        part = np.ascontiguousarray(np.asarray(partner, dtype=np.int32).reshape(-1))
+        if part.shape != (self.n_atoms,):
+            raise ValueError("partner must have one entry per atom")
+        if H is None:
+            H = torch.empty((ng, ng), dtype=torch.float64, device="cuda")
+        if S is None:
+            S = torch.empty((ng, ng), dtype=torch.float64, device="cuda")
+        H = _dev(H, torch.float64, "H", (ng, ng))
+        S = _dev(S, torch.float64, "S", (ng, ng))
+        if ws is None:
+            ws = self.workspace(N.HSB_MODE_REAL, [ng])
+        kf = (ctypes.c_double * 3)(*[float(x) for x in k_frac])
+        N.check(N.lib().hsbuild_forward_real(self._h, kf, ng, _ptr(g), _ptr(tau),
+                                             part.ctypes.data_as(ctypes.c_void_p), _ptr(T), _ptr(H), _ptr(S),
+                                             _ptr(ws), ws.numel(), _stream()), self._h)
+        return H, S
+
     def backward(self, k_frac, g: torch.Tensor, tau: torch.Tensor, T: torch.Tensor, gH: torch.Tensor,
                  gS: torch.Tensor, gT: Optional[torch.Tensor] = None, gtau: Optional[torch.Tensor] = None):
         """Gradients of a real loss with Hermitian dL/dH = gH and dL/dS = gS
