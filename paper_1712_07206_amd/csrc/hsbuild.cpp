@@ -35,6 +35,8 @@ struct hsbuild_s {
   // batch: persistent-kernel grid, captured graph and the arguments it was captured for
   int num_cus = 0;
   hipStream_t cap_stream = nullptr;
+  hipStream_t aux[4] = {};            // branches of the batch graph's operand builds
+  hipEvent_t fork = nullptr, join[4] = {};
   hipGraphExec_t graph_exec = nullptr;
   hipEvent_t graph_done = nullptr;
   BatchMeta* meta_host = nullptr;  // pinned, source of the graph's metadata upload
@@ -191,12 +193,14 @@ void destroy_events(hsbuild_t h) {
 
 // Uploads the type constants and builds K vectors, angular factors and (a, b).
 // base: the cell to use instead of the handle's (the representatives of inversion pairs).
+// shared: the constants are already in the workspace (batch branches) and are not uploaded again.
 int enqueue_tables(hsbuild_t h, const Layout& L, const double k_frac[3], const int32_t* g, char* ws,
-                   hipStream_t s, CellArgs& c, const CellArgs* base = nullptr) {
+                   hipStream_t s, CellArgs& c, const CellArgs* base = nullptr, bool shared = false) {
   c = base ? *base : h->cell;
   for (int i = 0; i < 3; ++i) c.kfrac[i] = k_frac[i];
   TypeConsts* dconsts = (TypeConsts*)(ws + L.consts);
-  hipError_t e = hipMemcpyAsync(dconsts, h->consts, sizeof(TypeConsts), hipMemcpyHostToDevice, s);
+  hipError_t e = hipSuccess;
+  if (!shared) e = hipMemcpyAsync(dconsts, h->consts, sizeof(TypeConsts), hipMemcpyHostToDevice, s);
   if (e != hipSuccess) return launched(h, e, "upload of type constants");
   e = launch_tables(c, dconsts, L.n, L.n_pad, g, (double2*)(ws + L.ang), (double2*)(ws + L.ab),
                     (double*)(ws + L.kv), s);
@@ -204,16 +208,19 @@ int enqueue_tables(hsbuild_t h, const Layout& L, const double k_frac[3], const i
 }
 
 // Tables, stacked coefficients W (pad rows zeroed), Y = T W per atom and lam.
+// shared: constants and lam are already in the workspace (batch branches).
 int enqueue_operands(hsbuild_t h, const Layout& L, const double k_frac[3], const int32_t* g, const double* tau,
-                     const void* T, char* ws, hipStream_t s, const CellArgs* base = nullptr) {
+                     const void* T, char* ws, hipStream_t s, const CellArgs* base = nullptr, bool shared = false) {
   CellArgs c;
-  int rc = enqueue_tables(h, L, k_frac, g, ws, s, c, base);
+  int rc = enqueue_tables(h, L, k_frac, g, ws, s, c, base, shared);
   if (rc) return rc;
   double2* W = (double2*)(ws + L.W);
   double2* Y = (double2*)(ws + L.Y);
-  rc = launched(h, launch_lambda(c, (const TypeConsts*)(ws + L.consts), L.K_pad, (double*)(ws + L.lam), s),
-                "k_lambda");
-  if (rc) return rc;
+  if (!shared) {
+    rc = launched(h, launch_lambda(c, (const TypeConsts*)(ws + L.consts), L.K_pad, (double*)(ws + L.lam), s),
+                  "k_lambda");
+    if (rc) return rc;
+  }
   rc = launched(h, launch_assemble(c, L.n_pad, (const double2*)(ws + L.ang), (const double2*)(ws + L.ab),
                                    (const double*)(ws + L.kv), tau, W, L.n_pad, L.n_pad, s),
                 "k_assemble");
@@ -258,9 +265,13 @@ int enqueue_split(hsbuild_t h, const Layout& L, char* w, double2* H, double2* S,
                   "split contraction (H)");
 }
 
+// Operand builds of the k-points run in kBranches parallel graph branches, each with its own tables.
+constexpr int kBranches = 4;
+
 struct BatchLayout {
   int K = 0, K_pad = 0, max_n_pad = 0;
-  size_t consts = 0, lam = 0, kv = 0, ang = 0, ab = 0, meta = 0, end = 0;
+  size_t consts = 0, lam = 0, meta = 0, end = 0;
+  size_t kv[kBranches] = {}, ang[kBranches] = {}, ab[kBranches] = {};
   std::vector<size_t> W, Y;
   std::vector<int> n_pad;
 };
@@ -282,9 +293,11 @@ BatchLayout make_batch_layout(const hsbuild_s& h, int n_k, const int32_t* ng) {
   const size_t np = (size_t)B.max_n_pad;
   B.consts = take(sizeof(TypeConsts));
   B.lam = take((size_t)B.K_pad * sizeof(double));
-  B.kv = take(np * 4 * sizeof(double));
-  B.ang = take((size_t)h.n_l * np * sizeof(double2));
-  B.ab = take((size_t)h.n_types * (h.l_max + 1) * np * sizeof(double2));
+  for (int b = 0; b < kBranches; ++b) {
+    B.kv[b] = take(np * 4 * sizeof(double));
+    B.ang[b] = take((size_t)h.n_l * np * sizeof(double2));
+    B.ab[b] = take((size_t)h.n_types * (h.l_max + 1) * np * sizeof(double2));
+  }
   B.meta = take((size_t)n_k * sizeof(BatchMeta));
   for (int k = 0; k < n_k; ++k) {
     B.W.push_back(take((size_t)B.K_pad * B.n_pad[k] * sizeof(double2)));
@@ -443,6 +456,11 @@ void hsbuild_destroy(hsbuild_t h) {
   drop_graph(h);
   if (h->graph_done) (void)hipEventDestroy(h->graph_done);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  for (int b = 0; b < 4; ++b) {
+    if (h->aux[b]) (void)hipStreamDestroy(h->aux[b]);
+    if (h->join[b]) (void)hipEventDestroy(h->join[b]);
+  }
+  if (h->fork) (void)hipEventDestroy(h->fork);
   hsdla_blas_destroy(h->rocblas);
   if (h->rep_done) {
     (void)hipEventSynchronize(h->rep_done);
@@ -846,7 +864,6 @@ int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t*
       h->meta_cap = n_k;
     }
     int total = 0;
-    int64_t g_row = 0;
     for (int k = 0; k < n_k; ++k) {
       BatchMeta& m = h->meta_host[k];
       m.w_off = (int64_t)(B.W[k] / sizeof(double2));
@@ -858,13 +875,30 @@ int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t*
       m.tile_start = total;
       total += hs_tiles(B.n_pad[k]);
     }
+    for (int b = 0; b < kBranches; ++b) {
+      if (!h->aux[b] && hipStreamCreateWithFlags(&h->aux[b], hipStreamNonBlocking) != hipSuccess)
+        return fail(h, HSB_ERR_DEVICE, "hipStreamCreateWithFlags failed");
+      if (!h->join[b] && hipEventCreateWithFlags(&h->join[b], hipEventDisableTiming) != hipSuccess)
+        return fail(h, HSB_ERR_DEVICE, "hipEventCreate failed");
+    }
+    if (!h->fork && hipEventCreateWithFlags(&h->fork, hipEventDisableTiming) != hipSuccess)
+      return fail(h, HSB_ERR_DEVICE, "hipEventCreate failed");
     hipStream_t cs = h->cap_stream;
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeRelaxed) != hipSuccess)
       return fail(h, HSB_ERR_DEVICE, "hipStreamBeginCapture failed");
     char* w = (char*)ws;
     rc = HSB_OK;
     h->capturing = true;
+    // shared inputs once: type constants and lam; then the k-points' operands in parallel branches
+    hipError_t ef = hipMemcpyAsync(w + B.consts, h->consts, sizeof(TypeConsts), hipMemcpyHostToDevice, cs);
+    if (ef == hipSuccess) ef = launch_lambda(h->cell, (const TypeConsts*)(w + B.consts), B.K_pad, (double*)(w + B.lam), cs);
+    if (ef == hipSuccess) ef = hipEventRecord(h->fork, cs);
+    for (int b = 0; b < kBranches && ef == hipSuccess; ++b) ef = hipStreamWaitEvent(h->aux[b], h->fork, 0);
+    if (ef != hipSuccess) rc = launched(h, ef, "batch graph fork");
+    std::vector<int64_t> g_rows(n_k, 0);
+    for (int k = 1; k < n_k; ++k) g_rows[k] = g_rows[k - 1] + ng[k - 1];
     for (int k = 0; k < n_k && rc == HSB_OK; ++k) {
+      const int b = k % kBranches;
       Layout L;
       L.n = ng[k];
       L.n_pad = B.n_pad[k];
@@ -872,13 +906,17 @@ int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t*
       L.K_pad = B.K_pad;
       L.consts = B.consts;
       L.lam = B.lam;
-      L.kv = B.kv;
-      L.ang = B.ang;
-      L.ab = B.ab;
+      L.kv = B.kv[b];
+      L.ang = B.ang[b];
+      L.ab = B.ab[b];
       L.W = B.W[k];
       L.Y = B.Y[k];
-      rc = enqueue_operands(h, L, k_frac + 3 * k, g + 3 * g_row, tau, T, w, cs);
-      g_row += ng[k];
+      rc = enqueue_operands(h, L, k_frac + 3 * k, g + 3 * g_rows[k], tau, T, w, h->aux[b], nullptr, true);
+    }
+    for (int b = 0; b < kBranches; ++b) {  // join every branch back, also after an error
+      hipError_t ej = hipEventRecord(h->join[b], h->aux[b]);
+      if (ej == hipSuccess) ej = hipStreamWaitEvent(cs, h->join[b], 0);
+      if (ej != hipSuccess && rc == HSB_OK) rc = launched(h, ej, "batch graph join");
     }
     if (rc == HSB_OK) {
       hipError_t e = hipMemcpyAsync(w + B.meta, h->meta_host, sizeof(BatchMeta) * n_k, hipMemcpyHostToDevice, cs);
