@@ -54,6 +54,17 @@ def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
     from paper_1712_07206_amd import _native as N
     from paper_1712_07206_amd.hsbuild import HSBuilder, hermitian_full
     n = case["n_g"]
+    # the FP64 path re-timed next to the split one, so both run at the same clock and temperature
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(2):
+        code = b64.forward_raw(case["k_frac"], n, g, tau, T, H, S, ws, ws.numel())
+        if code != N.HSB_OK:
+            raise N.HSBuildError(code, N.last_error(b64._h))
+    e1.record()
+    torch.cuda.synchronize()
+    ms_fp64_adj = e0.elapsed_time(e1) / 2
     H64, S64 = hermitian_full(H), hermitian_full(S)
     b64.close()
     del ws
@@ -82,13 +93,14 @@ def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
     stage_ms, _ = bs.stage_times()
     eh = (torch.linalg.norm(hermitian_full(H) - H64) / torch.linalg.norm(H64)).item()
     es = (torch.linalg.norm(hermitian_full(S) - S64) / torch.linalg.norm(S64)).item()
-    log("split bf16 x%d: %.3f ms/step (contraction stage %.3f ms), speedup %.3f, rel err vs FP64 H %.2e S %.2e"
-        % (args.split_slices, ms, stage_ms[2], ms_fp64 / ms, eh, es))
+    log("split bf16 x%d: %.3f ms/step (contraction stage %.3f ms); FP64 path next to it %.3f ms: speedup %.3f; "
+        "rel err vs FP64 H %.2e S %.2e" % (args.split_slices, ms, stage_ms[2], ms_fp64_adj, ms_fp64_adj / ms, eh, es))
     del wss, H64, S64
     bs.close()
     torch.cuda.empty_cache()
     return {"precision": "bf16", "slices": args.split_slices, "slice_bits": 8, "ms_per_step": round(ms, 4),
-            "fp64_equiv_tflops": round(flops / (ms * 1e-3) / 1e12, 4), "speedup": round(ms_fp64 / ms, 4),
+            "fp64_equiv_tflops": round(flops / (ms * 1e-3) / 1e12, 4), "speedup": round(ms_fp64_adj / ms, 4),
+            "fp64_ms_adjacent": round(ms_fp64_adj, 4), "speedup_vs_headline_fp64": round(ms_fp64 / ms, 4),
             "stages_ms": {"coefficients": round(stage_ms[0], 4), "t_products": round(stage_ms[1], 4),
                           "split_contraction": round(stage_ms[2], 4)},
             "rel_err_vs_fp64": {"H": eh, "S": es}, "meets_1e-10": bool(eh <= 1e-10 and es <= 1e-10)}
@@ -371,7 +383,7 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--config", type=int, default=2, help="workload index (default: the full-size cell)")
     ap.add_argument("--ng", type=int, default=None, help="override the basis size")
-    ap.add_argument("--cpu-ng", type=int, default=5400, help="basis size of the oracle sample")
+    ap.add_argument("--cpu-ng", type=int, default=6600, help="basis size of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-k-point batch leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
