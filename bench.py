@@ -357,6 +357,67 @@ def adjoint_leg(args) -> dict:
             "fp64_tflops": round(flops / (ms * 1e-3) / 1e12, 4)}
 
 
+def oracle_table() -> list:
+    """The oracle on the host next to the GPU path at the same sizes: forward at
+    cfg0, cfg1 (N_G 3000, also single-threaded) and cfg2 at N_G 3000, and the
+    gradient at the differentiation cell at N_G 800."""
+    import torch
+    from threadpoolctl import threadpool_info, threadpool_limits
+
+    from flapw_cells import make_case
+    from oracle import hs_oracle as o
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
+
+    def gpu_ms(fn, reps=5):
+        fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    rows = []
+    for idx, n_g, single in ((0, None, False), (1, 3000, False), (1, 3000, True), (2, 3000, False)):
+        case = make_case(idx, n_g=n_g)
+        n = case["n_g"]
+        flops = o.flops_forward(case["n_atoms"], case["n_l"], n)
+        t0 = time.perf_counter()
+        if single:
+            with threadpool_limits(limits=1, user_api="blas"):
+                o.hs(case)
+        else:
+            o.hs(case)
+        dt = time.perf_counter() - t0
+        b = HSBuilder.from_case(case)
+        g, tau, T = case_tensors(case)
+        ms = gpu_ms(lambda: b.forward(case["k_frac"], g, tau, T))
+        b.close()
+        rows.append({"what": "forward", "workload": case["name"], "n_g": n, "oracle_threads": 1 if single else threads,
+                     "oracle_s": round(dt, 4), "oracle_gflops": round(flops / dt / 1e9, 2), "gpu_ms": round(ms, 4),
+                     "gpu_tflops": round(flops / (ms * 1e-3) / 1e12, 3), "ratio": round(dt * 1e3 / ms, 1)})
+        log("oracle table: %s" % json.dumps(rows[-1]))
+    case = make_case(4, n_g=800)
+    n = case["n_g"]
+    t0 = time.perf_counter()
+    o.loss_gradients(case, case["W"], case["V"])
+    dt = time.perf_counter() - t0
+    b = HSBuilder.from_case(case)
+    g, tau, T = case_tensors(case)
+    gH = torch.as_tensor(case["W"], device="cuda")
+    gS = torch.as_tensor(case["V"], device="cuda")
+    ms = gpu_ms(lambda: b.backward(case["k_frac"], g, tau, T, gH, gS))
+    b.close()
+    rows.append({"what": "gradient", "workload": case["name"], "n_g": n, "oracle_threads": threads,
+                 "oracle_s": round(dt, 4), "gpu_ms": round(ms, 4), "ratio": round(dt * 1e3 / ms, 1),
+                 "note": "the oracle's gradient takes the per-atom route (different from the GPU's adjoint)"})
+    log("oracle table: %s" % json.dumps(rows[-1]))
+    return rows
+
+
 def recorded_traffic(workload: str, options: dict):
     """HBM bytes per launch of the contraction kernel from the committed
     rocprofv3 PMC record, only if the kernel source and its options are the
@@ -385,6 +446,8 @@ def main() -> int:
     ap.add_argument("--ng", type=int, default=None, help="override the basis size")
     ap.add_argument("--cpu-ng", type=int, default=6600, help="basis size of the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="also time the oracle at cfg0, cfg1, cfg2 (N_G 3000) and the gradient, next to the GPU")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-k-point batch leg")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint leg")
     ap.add_argument("--tune", action="store_true",
@@ -530,6 +593,8 @@ def main() -> int:
         log("oracle: %.4f TFLOP/s on %d threads" % (result["cpu_baseline"]["value"], result["cpu_baseline"]["cores"]))
     else:
         result["cpu_baseline"] = None
+    if args.oracle_table:
+        result["oracle_table"] = oracle_table()
     print(json.dumps(result))
     sys.stdout.flush()
     return 0
