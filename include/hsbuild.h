@@ -26,14 +26,18 @@
  *   - complex values are complex128, interleaved (re, im) doubles;
  *   - matrices are row-major; H and S are indexed [G'][G] in the caller's G
  *     order, leading dimension N_G; only the upper triangle (column >= row,
- *     diagonal included) is written, the strict lower triangle is untouched;
+ *     diagonal included) is written, the strict lower triangle is untouched
+ *     (exceptions: hsbuild_forward_real writes doubles, and algorithm 1 of
+ *     hsbuild_forward_hsdla writes both triangles of H);
  *   - all arguments are validated on the host before anything is enqueued; on
  *     an error nothing is launched and the outputs are untouched;
  *   - calls are asynchronous and stream-ordered on `stream` (a hipStream_t,
  *     NULL = the default stream); device faults surface at the caller's
  *     synchronisation;
  *   - the caller owns every device buffer, the workspace included; the
- *     library allocates no device memory;
+ *     library's kernels allocate no device memory (the rocBLAS baseline binds
+ *     rocBLAS to a region of the caller's workspace; the rocBLAS handle itself
+ *     is created by rocBLAS on the first hsbuild_forward_hsdla call);
  *   - a handle is not thread-safe: use one handle per stream.
  */
 #ifndef HSBUILD_H

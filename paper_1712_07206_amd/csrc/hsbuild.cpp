@@ -309,6 +309,7 @@ BatchLayout make_batch_layout(const hsbuild_s& h, int n_k, const int32_t* ng) {
 
 // rocBLAS handle and its device-memory need for basis size ng (both algorithms).
 int blas_prepare(hsbuild_t h, int ng) {
+  if (int rc = check_device(h)) return rc;  // the rocBLAS handle belongs to the current device
   if (!h->rocblas) {
     std::string err;
     if (hsdla_blas_create(h->device, &h->rocblas, err)) return fail(h, HSB_ERR_DEVICE, "%s", err.c_str());
