@@ -236,6 +236,129 @@ __global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64_batch(const d2* __restr
   }
 }
 
+// Real-symmetric contraction on whole 128 x 128 super-tiles: Re(W^H Y) and
+// Re(W^H lam W) keep two of the four real MFMAs per complex multiply-add, so
+// with the 128 x 64 tile above a wave would read twice the LDS per MFMA.
+// Here the tile is 128 x 128 and 8 rows are staged per chunk: 8 waves of
+// 32 x 64 (2 x 4 MFMA blocks), the same MFMA work and LDS reads per chunk
+// as the complex kernel.
+constexpr int RN = 128, RK = 8;
+
+struct RSmem {
+  d2 L[2][RK][BM];
+  d2 R[2][RK][RN];
+  d2 Y[2][RK][RN];
+};
+
+__global__ void __launch_bounds__(512, 1) k_hs_real(const d2* __restrict__ W, const d2* __restrict__ Y,
+                                                    const double* __restrict__ lam, int K_pad, int n, int n_pad,
+                                                    int nbr, int num_wg, int gr, double* __restrict__ H,
+                                                    double* __restrict__ S, int64_t ldh) {
+  __shared__ RSmem sm;
+  const int x = blockIdx.x % kXcds;
+  int start, len;
+  xcd_range(x, num_wg, start, len);
+  const int w = start + blockIdx.x / kXcds;
+  int bi, bj;
+  if (gr > 0) grouped_decode(w, nbr, gr, bi, bj);
+  else tri_decode(w, nbr, bi, bj);
+  const int row0 = bi * BM, col0 = bj * RN;
+  if (col0 >= n) return;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wr = wave >> 1, wc = wave & 1;  // rows wr*32, columns wc*64
+
+  // staging: 8 x 128 per array, two elements per thread (row e/128, column e%128)
+  d2 pl[2], pr[2], py[2];
+  double pm[2];
+#define HR_GLOAD(kc)                                                       \
+  do {                                                                     \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i) {                        \
+      const int e = tid + 512 * i;                                         \
+      const int64_t r = (int64_t)((kc) + (e >> 7)) * n_pad;                \
+      pl[i] = W[r + row0 + (e & 127)];                                     \
+      pr[i] = W[r + col0 + (e & 127)];                                     \
+      py[i] = Y[r + col0 + (e & 127)];                                     \
+      pm[i] = lam[(kc) + (e >> 7)];                                        \
+    }                                                                      \
+  } while (0)
+#define HR_LSTORE(b)                                   \
+  do {                                                 \
+    _Pragma("unroll") for (int i = 0; i < 2; ++i) {    \
+      const int e = tid + 512 * i;                     \
+      sm.L[b][e >> 7][e & 127] = pl[i];                \
+      sm.R[b][e >> 7][e & 127] = pm[i] * pr[i];        \
+      sm.Y[b][e >> 7][e & 127] = py[i];                \
+    }                                                  \
+  } while (0)
+
+  d4 hr[2][4], sr[2][4];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) hr[i][j] = sr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int nchunks = K_pad / RK;
+  HR_GLOAD(0);
+  HR_LSTORE(0);
+  __syncthreads();
+  for (int c = 0; c < nchunks; ++c) {
+    const int b = c & 1;
+    if (c + 1 < nchunks) HR_GLOAD((c + 1) * RK);
+#pragma unroll
+    for (int ks = 0; ks < RK / 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      double ar[2], ai[2], yre[4], yim[4], wre[4], wim[4];
+#pragma unroll
+      for (int i = 0; i < 2; ++i) {
+        const d2 a = sm.L[b][kk][wr * 32 + i * 16 + (lane & 15)];
+        ar[i] = a.x; ai[i] = a.y;
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const d2 yv = sm.Y[b][kk][wc * 64 + j * 16 + (lane & 15)];
+        const d2 wv = sm.R[b][kk][wc * 64 + j * 16 + (lane & 15)];
+        yre[j] = yv.x; yim[j] = yv.y; wre[j] = wv.x; wim[j] = wv.y;
+      }
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) hr[i][j] = MFMA(ar[i], yre[j], hr[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sr[i][j] = MFMA(ar[i], wre[j], sr[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) hr[i][j] = MFMA(ai[i], yim[j], hr[i][j]);
+#pragma unroll
+      for (int i = 0; i < 2; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) sr[i][j] = MFMA(ai[i], wim[j], sr[i][j]);
+    }
+    if (c + 1 < nchunks) HR_LSTORE(b ^ 1);
+    __syncthreads();
+  }
+#undef HR_GLOAD
+#undef HR_LSTORE
+
+  // D layout of the 16x16 f64 MFMA: lane l, element q -> row l/16 + 4q, column l%16
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * q;
+        const int col = col0 + wc * 64 + j * 16 + (lane & 15);
+        if (row < n && col < n && col >= row) {
+          const int64_t o = (int64_t)row * ldh + col;
+          H[o] = hr[i][j][q];
+          S[o] = sr[i][j][q];
+        }
+      }
+}
+
 }  // namespace
 
 int hs_tiles(int n_pad) {
@@ -260,9 +383,9 @@ hipError_t launch_hs_fp64_real(const double2* W, const double2* Y, const double*
                                int gr, int waves, double* H, double* S, int64_t ldh, hipStream_t s) {
   const int nbr = n_pad / BM;
   const int num_wg = hs_tiles(n_pad);
-  if (waves == 8)
-    hipLaunchKernelGGL((k_hs_fp64<4, true>), dim3(num_wg), dim3(512), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad,
-                       n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
+  if (waves == 8)  // whole 128 x 128 super-tiles
+    hipLaunchKernelGGL(k_hs_real, dim3(num_wg / 2), dim3(512), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad, n,
+                       n_pad, nbr, num_wg / 2, gr, H, S, ldh);
   else
     hipLaunchKernelGGL((k_hs_fp64<2, true>), dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad,
                        n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
