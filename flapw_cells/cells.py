@@ -89,6 +89,10 @@ CONFIGS = {
                   inversion=True),
     6: CellConfig(6, "cubic30_inv_4x32_l10_ng12000", (30.0, 30.0, 30.0), (32, 32, 32, 32),
                   (2.2, 2.2, 2.2, 2.2), 10, n_g=12000, inversion=True),
+    # edge cases: the largest l_max and type count the library takes; a type without atoms
+    7: CellConfig(7, "cubic14_16x1_l12_ng400", (14.0, 14.0, 14.0), (1,) * 16, (1.2,) * 16, 12, n_g=400),
+    8: CellConfig(8, "cubic12_inv_2+0+3_l3_ng300", (12.0, 12.0, 12.0), (2, 0, 3), (1.2, 1.3, 1.4), 3, n_g=300,
+                  inversion=True),
 }
 
 
