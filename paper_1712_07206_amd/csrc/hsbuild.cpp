@@ -422,6 +422,7 @@ int hsbuild_create(const hsb_config* cfg, hsbuild_t* out) {
   h->n_l = n_l;
   h->max_ng = cfg->max_ng;
   h->precision = cfg->precision;
+  if (cfg->precision != HSB_FP64) h->tile_group = 4;  // measured best for the split contraction
   h->n_slices = cfg->n_slices;
   std::memcpy(h->lattice, cfg->lattice, sizeof h->lattice);
   for (int t = 0; t < cfg->n_types; ++t)

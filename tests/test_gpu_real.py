@@ -105,3 +105,23 @@ def test_real_rejects_bad_partner_map():
     with pytest.raises(N.HSBuildError) as e:
         _real(case, partner=cross)
     assert e.value.code == N.HSB_ERR_ARG
+
+
+def test_real_wave_variants_bitwise_equal():
+    """The 8-wave (128 x 128 tiles) and 4-wave (128 x 64 tiles) real kernels add
+    the same products in the same order for every entry."""
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    case = make_case(5)
+    n = case["n_g"]
+    b = HSBuilder.from_case(case)
+    g, tau, T = case_tensors(case)
+    out = []
+    for wv in (8, 4):
+        b.set_option(N.HSB_OPT_HS_WAVES, wv)
+        H = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+        S = torch.zeros_like(H)
+        b.forward_real(case["k_frac"], g, tau, case["partner"], T, H, S)
+        torch.cuda.synchronize()
+        out.append((H.cpu().numpy(), S.cpu().numpy()))
+    assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
