@@ -110,6 +110,9 @@ __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, cons
     if (c + 1 < nchunks) HS_GLOAD((c + 1) * BK);
 #pragma unroll
     for (int ks = 0; ks < BK / 4; ++ks) {
+      // the next chunk goes into the other buffer mid-chunk (free since the last barrier),
+      // so its LDS stores overlap the MFMAs still queued instead of delaying the barrier
+      if (ks == BK / 8 && c + 1 < nchunks) HS_LSTORE(b ^ 1);
       const int kk = ks * 4 + (lane >> 4);
       double ar[MI], ai[MI], an[MI], yre[2], yim[2], wre[2], wim[2];
 #pragma unroll
@@ -164,7 +167,6 @@ __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, cons
           for (int j = 0; j < 2; ++j) si[i][j] = MFMA(an[i], wre[j], si[i][j]);
       }
     }
-    if (c + 1 < nchunks) HS_LSTORE(b ^ 1);
     __syncthreads();
   }
 #undef HS_GLOAD
@@ -306,6 +308,7 @@ __global__ void __launch_bounds__(512, 1) k_hs_real(const d2* __restrict__ W, co
     if (c + 1 < nchunks) HR_GLOAD((c + 1) * RK);
 #pragma unroll
     for (int ks = 0; ks < RK / 4; ++ks) {
+      if (ks == RK / 8 && c + 1 < nchunks) HR_LSTORE(b ^ 1);  // as in hs_tile
       const int kk = ks * 4 + (lane >> 4);
       double ar[2], ai[2], yre[4], yim[4], wre[4], wim[4];
 #pragma unroll
@@ -336,7 +339,6 @@ __global__ void __launch_bounds__(512, 1) k_hs_real(const d2* __restrict__ W, co
 #pragma unroll
         for (int j = 0; j < 4; ++j) sr[i][j] = MFMA(ai[i], wim[j], sr[i][j]);
     }
-    if (c + 1 < nchunks) HR_LSTORE(b ^ 1);
     __syncthreads();
   }
 #undef HR_GLOAD
