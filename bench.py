@@ -279,6 +279,40 @@ def real_leg(args) -> dict:
             "complex_imag_rel": imag, "rel_err_vs_complex": {"H": eh, "S": es}}
 
 
+def eigen_leg(args) -> dict:
+    """The downstream generalized eigenproblem H c = lambda S c (rocSOLVER zhegvd
+    through hsbuild_eigensolve) on the bench cell's H and S (built by the
+    type-factored path), eigenvalues and eigenvectors."""
+    import torch
+
+    from flapw_cells import make_case
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    case = make_case(args.config, n_g=args.ng)
+    n = case["n_g"]
+    b = HSBuilder.from_case(case)
+    g, tau, T = case_tensors(case)
+    H, S = b.forward_factored(case["k_frac"], g, tau, T)
+    H0, S0 = H.clone(), S.clone()
+    b.eigensolve(H, S, vectors=True)  # warm (rocSOLVER loads its kernels)
+    H.copy_(H0)
+    S.copy_(S0)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    w, info = b.eigensolve(H, S, vectors=True)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1)
+    lo, hi = float(w[0]), float(w[-1])
+    del H, S, H0, S0, w
+    b.close()
+    torch.cuda.empty_cache()
+    log("eigensolve %s N_G=%d: %.1f ms with eigenvectors (rocSOLVER zhegvd), info %d, lambda in [%.4g, %.4g]"
+        % (case["name"], n, ms, info, lo, hi))
+    return {"workload": case["name"], "n_g": n, "ms_with_vectors": round(ms, 2), "info": info,
+            "lambda_min": lo, "lambda_max": hi, "library": "rocSOLVER zhegvd"}
+
+
 def batch_leg(args) -> dict:
     """The multi-k workload (64 k-points, N_G 2800-3400, T shared): one captured
     graph with a persistent contraction, against 64 sequential forward calls."""
@@ -467,6 +501,7 @@ def main() -> int:
     ap.add_argument("--no-factored", action="store_true", help="skip the type-factored leg")
     ap.add_argument("--no-hsdla", action="store_true", help="skip the rocBLAS HSDLA baseline leg")
     ap.add_argument("--no-real", action="store_true", help="skip the real-symmetric (inversion) leg")
+    ap.add_argument("--no-eigen", action="store_true", help="skip the generalized eigensolve leg")
     ap.add_argument("--split-slices", type=int, default=5,
                     help="also time the BF16 split-precision path with this many slices (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -594,6 +629,8 @@ def main() -> int:
         result["real_symmetric"] = real_leg(args)
     if not args.no_adjoint:
         result["adjoint"] = adjoint_leg(args)
+    if not args.no_eigen:
+        result["eigensolve"] = eigen_leg(args)
     if not args.no_batch:
         result["batch"] = batch_leg(args)
         result["batch_speedup"] = result["batch"]["speedup"]

@@ -68,7 +68,7 @@ enum { HSB_FP64 = 0, HSB_SPLIT_FP16 = 1, HSB_SPLIT_BF16 = 2 };
 
 /* Workspace modes for hsbuild_workspace_bytes. */
 enum { HSB_MODE_FORWARD = 0, HSB_MODE_BACKWARD = 1, HSB_MODE_BATCH = 2, HSB_MODE_COEFFICIENTS = 3, HSB_MODE_FACTORED = 4,
-       HSB_MODE_HSDLA = 5, HSB_MODE_REAL = 6 };
+       HSB_MODE_HSDLA = 5, HSB_MODE_REAL = 6, HSB_MODE_EIGEN = 7 };
 
 #define HSB_MAX_TYPES 16
 #define HSB_MAX_LMAX 12
@@ -165,6 +165,21 @@ int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const 
 int hsbuild_forward_hsdla(hsbuild_t h, int32_t algorithm, const double k_frac[3], int32_t ng, const int32_t* g,
                           const double* tau, const void* T, void* H, void* S, void* ws, size_t ws_bytes,
                           void* stream);
+
+/* The generalized eigenproblem H c = lambda S c that H and S are built for
+ * (Sec. 2.1), on the vendor library (rocSOLVER zhegvd).  H, S: device
+ * complex128 [ng][ng] holding the upper triangles hsbuild_forward writes; both
+ * are overwritten: with vectors = 1, row j of H receives the eigenvector c_j
+ * (normalised to c_j^H S c_j = 1), and S the Cholesky factor.  w: device double
+ * [ng], the eigenvalues in ascending order.  info: device int32 [1], rocSOLVER's
+ * status (0 = success; > ng: S is not positive definite; 1..ng: no
+ * convergence) -- read it after synchronising.  S must be positive definite:
+ * the muffin-tin S alone has rank <= 2 N_atoms N_L, so ng must stay below that
+ * (the interstitial part that makes S definite in general is not built here).
+ * Workspace: hsbuild_workspace_bytes(h, HSB_MODE_EIGEN, 1, &ng), which includes
+ * the device memory rocSOLVER asks for. */
+int hsbuild_eigensolve(hsbuild_t h, int32_t ng, void* H, void* S, double* w, int32_t vectors, int32_t* info, void* ws,
+                       size_t ws_bytes, void* stream);
 
 /* H and S from caller-given matching coefficients, the input the paper's
  * HSDLA algorithm starts from (Alg. 1, Alg. 3): coef is device complex128

@@ -232,3 +232,11 @@ def flops_forward(n_atoms: int, n_l: int, n_g: int) -> float:
     the per-atom T products (2N_L x 2N_L times 2N_L x N_G, complex)."""
     k_c = n_atoms * n_l
     return 16.0 * k_c * n_g * (n_g + 1) + 32.0 * n_atoms * n_l * n_l * n_g
+
+
+def generalized_eigenvalues(H: np.ndarray, S: np.ndarray) -> np.ndarray:
+    """Eigenvalues, ascending, of the generalized problem H c = lambda S c that
+    H and S are built for (Sec. 2.1), with S Hermitian positive definite: the
+    library routine for the Hermitian-definite pencil (scipy.linalg.eigh)."""
+    from scipy import linalg
+    return linalg.eigh(H, S, eigvals_only=True)

@@ -32,9 +32,10 @@ HSB_MODE_COEFFICIENTS = 3
 HSB_MODE_FACTORED = 4
 HSB_MODE_HSDLA = 5
 HSB_MODE_REAL = 6
+HSB_MODE_EIGEN = 7
 
 EXPORTS = ("hsbuild_create", "hsbuild_destroy", "hsbuild_workspace_bytes", "hsbuild_coefficients",
-           "hsbuild_forward", "hsbuild_forward_factored", "hsbuild_forward_hsdla", "hsbuild_forward_real",
+           "hsbuild_forward", "hsbuild_forward_factored", "hsbuild_forward_hsdla", "hsbuild_forward_real", "hsbuild_eigensolve",
            "hsbuild_forward_coefficients",
            "hsbuild_backward",
            "hsbuild_batch", "hsbuild_last_error",
@@ -94,6 +95,9 @@ def lib():
     L.hsbuild_forward_real.argtypes = [c_void_p, POINTER(c_double), c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                        c_void_p, c_void_p, c_void_p, c_size_t, c_void_p]
     L.hsbuild_forward_real.restype = c_int
+    L.hsbuild_eigensolve.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_void_p,
+                                     c_size_t, c_void_p]
+    L.hsbuild_eigensolve.restype = c_int
     L.hsbuild_forward_coefficients.argtypes = [c_void_p, c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
                                                c_size_t, c_void_p]
     L.hsbuild_forward_coefficients.restype = c_int

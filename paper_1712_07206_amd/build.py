@@ -53,7 +53,7 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
         objs = list(ex.map(compile_one, SOURCES))
     tmp = LIB + ".tmp"
     cmd = [hipcc, "-shared", "-fPIC", "--offload-arch=" + ARCH, *objs, "-L" + os.path.join(ROCM, "lib"),
-           "-lrocblas", "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-o", tmp]
+           "-lrocblas", "-lrocsolver", "-Wl,-rpath," + os.path.join(ROCM, "lib"), "-o", tmp]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError("link failed: %s\n%s%s" % (" ".join(cmd), res.stdout, res.stderr))

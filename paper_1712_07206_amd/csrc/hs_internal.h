@@ -52,6 +52,8 @@ struct Layout {
   size_t hA = 0, hB = 0, hX = 0, blas = 0, blas_bytes = 0;
   // real-symmetric only: representative indices and weights, their positions, row weights
   size_t rep = 0, repw = 0, tau_rep = 0, wrow = 0;
+  // eigensolve only: rocSOLVER's off-diagonal scratch
+  size_t eigE = 0;
 };
 
 // Per-k-point entry of the batched contraction's tile list (device copy in the workspace).
@@ -140,6 +142,12 @@ int hsdla_blas_bind(void* handle, void* ws, size_t bytes, hipStream_t s, std::st
 int hsdla_blas_enqueue(void* handle, int algorithm, const CellArgs& c, const TypeConsts* consts, int ng, int n_pad,
                        const double2* T, const double2* A, const double2* B, double2* X, double2* H, double2* S,
                        hipStream_t s, bool query, std::string& err);
+
+int eig_enqueue(void* handle, int n, double2* H, double2* S, double* w, double* E, int* info, bool vectors,
+                std::string& err);
+int eig_workspace(void* handle, int n, bool vectors, size_t* bytes, std::string& err);
+// a[i] = conj(a[i]) for i < count.
+hipError_t launch_conj(double2* a, int64_t count, hipStream_t s);
 
 // ---- adjoint ----
 int gradtau_blocks(int n);

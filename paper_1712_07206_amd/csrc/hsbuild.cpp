@@ -52,6 +52,8 @@ struct hsbuild_s {
   void* rocblas = nullptr;
   int blas_ng = -1;
   size_t blas_need = 0;
+  int eig_ng = -1;  // rocSOLVER's device-memory need of the eigensolve for basis size eig_ng
+  size_t eig_need = 0;
 };
 
 namespace {
@@ -99,6 +101,13 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
   L.kv = take(np * 4 * sizeof(double));
   L.ang = take((size_t)h.n_l * np * sizeof(double2));
   L.ab = take((size_t)h.n_types * (h.l_max + 1) * np * sizeof(double2));
+  if (mode == HSB_MODE_EIGEN) {
+    L.eigE = take((size_t)ng * sizeof(double));
+    L.blas_bytes = h.eig_ng == ng ? h.eig_need : 0;
+    L.blas = take(L.blas_bytes);
+    L.end = off;
+    return L;
+  }
   if (mode == HSB_MODE_HSDLA) {
     const size_t KA = (size_t)h.n_atoms * h.n_l;
     L.hA = take(2 * KA * np * sizeof(double2));  // A stack, then the B stack right after it
@@ -329,6 +338,26 @@ int blas_prepare(hsbuild_t h, int ng) {
   return HSB_OK;
 }
 
+// rocBLAS handle and the eigensolve's device-memory need for basis size ng (vectors included).
+int eig_prepare(hsbuild_t h, int ng) {
+  if (int rc = check_device(h)) return rc;
+  if (!h->rocblas) {
+    std::string err;
+    if (hsdla_blas_create(h->device, &h->rocblas, err)) return fail(h, HSB_ERR_DEVICE, "%s", err.c_str());
+  }
+  if (h->eig_ng == ng) return HSB_OK;
+  size_t need = 0;
+  for (bool v : {false, true}) {
+    size_t b = 0;
+    std::string err;
+    if (eig_workspace(h->rocblas, ng, v, &b, err)) return fail(h, HSB_ERR_DEVICE, "%s", err.c_str());
+    need = std::max(need, b);
+  }
+  h->eig_ng = ng;
+  h->eig_need = need;
+  return HSB_OK;
+}
+
 void drop_graph(hsbuild_t h) {
   if (h->graph_exec) {
     if (h->graph_done) (void)hipEventSynchronize(h->graph_done);
@@ -482,9 +511,10 @@ size_t hsbuild_workspace_bytes(hsbuild_t h, int32_t mode, int32_t n_k, const int
     return 0;
   }
   if (mode == HSB_MODE_FORWARD || mode == HSB_MODE_COEFFICIENTS || mode == HSB_MODE_BACKWARD ||
-      mode == HSB_MODE_FACTORED || mode == HSB_MODE_HSDLA || mode == HSB_MODE_REAL) {
+      mode == HSB_MODE_FACTORED || mode == HSB_MODE_HSDLA || mode == HSB_MODE_REAL || mode == HSB_MODE_EIGEN) {
     if (n_k != 1 || check_ng(h, ng[0])) return 0;
     if (mode == HSB_MODE_HSDLA && blas_prepare(h, ng[0])) return 0;
+    if (mode == HSB_MODE_EIGEN && eig_prepare(h, ng[0])) return 0;
     return make_layout(*h, ng[0], mode).end;
   }
   if (mode == HSB_MODE_BATCH) {
@@ -703,6 +733,30 @@ int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const 
                   "k_hs_fp64 (real)");
   mark(h, 3, s);
   return rc;
+}
+
+int hsbuild_eigensolve(hsbuild_t h, int32_t ng, void* H, void* S, double* w, int32_t vectors, int32_t* info, void* ws,
+                       size_t ws_bytes, void* stream) {
+  if (!h) return HSB_ERR_ARG;
+  h->err.clear();
+  if (!H || !S || !w || !info) return fail(h, HSB_ERR_ARG, "null H, S, w or info");
+  if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
+  if (vectors != 0 && vectors != 1) return fail(h, HSB_ERR_ARG, "vectors must be 0 or 1 (got %d)", vectors);
+  int rc = check_ng(h, ng);
+  if (rc) return rc;
+  if ((rc = eig_prepare(h, ng))) return rc;
+  const Layout L = make_layout(*h, ng, HSB_MODE_EIGEN);
+  if ((rc = check_ws(h, L, ws, ws_bytes))) return rc;
+  hipStream_t s = (hipStream_t)stream;
+  char* wsp = (char*)ws;
+  std::string err;
+  if (hsdla_blas_bind(h->rocblas, L.blas_bytes ? wsp + L.blas : nullptr, L.blas_bytes, s, err))
+    return fail(h, HSB_ERR_DEVICE, "%s", err.c_str());
+  if (eig_enqueue(h->rocblas, ng, (double2*)H, (double2*)S, w, (double*)(wsp + L.eigE), (int*)info, vectors != 0,
+                  err))
+    return fail(h, HSB_ERR_DEVICE, "%s", err.c_str());
+  if (vectors) return launched(h, launch_conj((double2*)H, (int64_t)ng * ng, s), "k_conj");
+  return HSB_OK;
 }
 
 int hsbuild_forward_hsdla(hsbuild_t h, int32_t algorithm, const double k_frac[3], int32_t ng, const int32_t* g,

@@ -14,6 +14,7 @@
 // Z_a^T = M_A,a T_BA^T + M_B,a T_BB^T / 2 with T's blocks read transposed in
 // place (row-major T is column-major T^T).
 #include <rocblas/rocblas.h>
+#include <rocsolver/rocsolver.h>
 
 #include <string>
 
@@ -102,6 +103,46 @@ int hsdla_blas_enqueue(void* handle, int algorithm, const CellArgs& c, const Typ
                      &c1, h, ng),
        "zgemm (H_AA, full)");
 #undef RB
+  return HSB_OK;
+}
+
+// Generalized eigenproblem H c = lambda S c by rocSOLVER zhegvd on the row-major
+// upper triangles (BLAS's lower triangle of the transposes, conj(H) and conj(S),
+// which have the same eigenvalues and conjugated eigenvectors).  E: [n] doubles of
+// scratch; info: device int.  With vectors, H receives the eigenvectors of the
+// transposed problem column by column, i.e. row j of the row-major array holds
+// conj(c_j); the caller conjugates them.
+int eig_enqueue(void* handle, int n, double2* H, double2* S, double* w, double* E, int* info, bool vectors,
+                std::string& err) {
+  rocblas_handle rb = (rocblas_handle)handle;
+  const rocblas_status st =
+      rocsolver_zhegvd(rb, rocblas_eform_ax, vectors ? rocblas_evect_original : rocblas_evect_none, rocblas_fill_lower,
+                       n, (rocblas_double_complex*)H, n, (rocblas_double_complex*)S, n, w, E, info);
+  if (st != rocblas_status_success && st != rocblas_status_size_increased && st != rocblas_status_size_unchanged) {
+    err = std::string("rocsolver_zhegvd: ") + rb_name(st);
+    return HSB_ERR_DEVICE;
+  }
+  return HSB_OK;
+}
+
+// rocSOLVER's device-memory need for eig_enqueue at size n (size-query mode).
+int eig_workspace(void* handle, int n, bool vectors, size_t* bytes, std::string& err) {
+  rocblas_handle rb = (rocblas_handle)handle;
+  rocblas_status st = rocblas_start_device_memory_size_query(rb);
+  if (st != rocblas_status_success) {
+    err = std::string("rocBLAS size query: ") + rb_name(st);
+    return HSB_ERR_DEVICE;
+  }
+  double2* p = (double2*)(uintptr_t)256;
+  const int rc = eig_enqueue(handle, n, p, p, (double*)p, (double*)p, (int*)p, vectors, err);
+  size_t sz = 0;
+  st = rocblas_stop_device_memory_size_query(rb, &sz);
+  if (rc) return rc;
+  if (st != rocblas_status_success) {
+    err = std::string("rocBLAS size query: ") + rb_name(st);
+    return HSB_ERR_DEVICE;
+  }
+  *bytes = sz;
   return HSB_OK;
 }
 

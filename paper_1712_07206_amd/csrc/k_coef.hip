@@ -181,6 +181,11 @@ __global__ void __launch_bounds__(256) k_rep_setup(const double* __restrict__ ta
   }
 }
 
+__global__ void __launch_bounds__(256) k_conj(double2* __restrict__ a, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) a[i].y = -a[i].y;
+}
+
 // Caller-given coefficients [rows][ng] into the padded layout [rows][n_pad] (zeros for G >= ng).
 __global__ void __launch_bounds__(256) k_pack_rows(const double2* __restrict__ src, int ng, int rows,
                                                    double2* __restrict__ dst, int n_pad) {
@@ -231,6 +236,12 @@ hipError_t launch_rep_setup(const double* tau, const int* rep, const double* w, 
   const int n = n_rep > K_pad ? n_rep : K_pad;
   hipLaunchKernelGGL(k_rep_setup, dim3((n + 255) / 256), dim3(256), 0, s, tau, rep, w, n_rep, rows, K_pad, tau_rep,
                      wrow, lam);
+  return hipGetLastError();
+}
+
+hipError_t launch_conj(double2* a, int64_t count, hipStream_t s) {
+  if (count <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_conj, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, s, a, count);
   return hipGetLastError();
 }
 

@@ -215,6 +215,20 @@ class HSBuilder:
                                              _ptr(ws), ws.numel(), _stream()), self._h)
         return H, S
 
+    def eigensolve(self, H: torch.Tensor, S: torch.Tensor, vectors: bool = True):
+        """Generalized eigenproblem H c = lambda S c (hsbuild_eigensolve) on the
+        upper triangles of a forward call, in place: returns (eigenvalues,
+        rocSOLVER info); with vectors, row j of H becomes the eigenvector c_j."""
+        ng = int(H.shape[0])
+        H = _dev(H, torch.complex128, "H", (ng, ng))
+        S = _dev(S, torch.complex128, "S", (ng, ng))
+        w = torch.empty(ng, dtype=torch.float64, device="cuda")
+        info = torch.zeros(1, dtype=torch.int32, device="cuda")
+        ws = self.workspace(N.HSB_MODE_EIGEN, [ng])
+        N.check(N.lib().hsbuild_eigensolve(self._h, ng, _ptr(H), _ptr(S), _ptr(w), 1 if vectors else 0, _ptr(info),
+                                           _ptr(ws), ws.numel(), _stream()), self._h)
+        return w, int(info.item())
+
     def backward(self, k_frac, g: torch.Tensor, tau: torch.Tensor, T: torch.Tensor, gH: torch.Tensor,
                  gS: torch.Tensor, gT: Optional[torch.Tensor] = None, gtau: Optional[torch.Tensor] = None):
         """Gradients of a real loss with Hermitian dL/dH = gH and dL/dS = gS

@@ -421,3 +421,24 @@ def test_inversion_symmetric_cell_gives_real_h_and_s():
     tau[0] += np.array([0.31, -0.2, 0.05])
     _, S3 = o.hs(dict(case, tau=tau))
     assert np.linalg.norm(S3.imag) > 1e-3 * np.linalg.norm(S3)
+
+
+def test_generalized_eigenvalues_by_an_independent_reduction():
+    """The pencil's eigenvalues equal those of the standard problem
+    L^{-1} H L^{-H} (S = L L^H, Cholesky by hand-written forward substitution
+    in numpy, eigenvalues by numpy's eigvalsh); on the bench cell at N_G = 400
+    the muffin-tin S is positive definite (2 N_at N_L = 30976 > N_G)."""
+    from flapw_cells import make_case
+    case = make_case(2, n_g=400)
+    H, S = o.hs(case)
+    w = o.generalized_eigenvalues(H, S)
+    L = np.linalg.cholesky(S)
+    n = len(S)
+    Linv = np.zeros_like(S)
+    eye = np.eye(n, dtype=S.dtype)
+    for i in range(n):  # forward substitution, row by row
+        Linv[i] = (eye[i] - L[i, :i] @ Linv[:i]) / L[i, i]
+    ref = np.linalg.eigvalsh(Linv @ H @ Linv.conj().T)
+    assert np.abs(w - ref).max() <= 1e-9 * np.abs(ref).max()
+    # the pencil is not the standard problem: S != I changes the spectrum
+    assert np.abs(np.linalg.eigvalsh(H) - ref).max() > 1e-3 * np.abs(ref).max()
