@@ -201,3 +201,29 @@ def test_options_null_handle():
     ms = (ctypes.c_double * 3)()
     n = ctypes.c_int32()
     assert L.hsbuild_stage_times(None, ms, ctypes.byref(n)) == N.HSB_ERR_ARG
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/hsbuild.h compiles as C99 and C++17 on its own, and a C program
+    linked against the library resolves every declared entry point (nothing is
+    called: no GPU here)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    names = declared_functions()
+    src = tmp_path / "abi.c"
+    src.write_text('#include "hsbuild.h"\n#include <stdio.h>\n'
+                   "int main(void) {\n  void* p[] = {" + ", ".join("(void*)&%s" % n for n in names) + "};\n"
+                   '  printf("%d\\n", (int)(sizeof p / sizeof p[0]));\n  return 0;\n}\n')
+    inc = os.path.join(ROOT, "include")
+    libdir = os.path.dirname(N.LIB_PATH)
+    exe = tmp_path / "abi"
+    subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-I", inc, str(src), "-L", libdir, "-lhsbuild",
+                    "-Wl,-rpath," + libdir, "-Wl,--unresolved-symbols=ignore-in-shared-libs", "-o", str(exe)],
+                   check=True)
+    gxx = shutil.which("g++")
+    if gxx is not None:
+        subprocess.run([gxx, "-std=c++17", "-Wall", "-Werror", "-x", "c++", "-fsyntax-only", "-I", inc,
+                        str(src)], check=True)
