@@ -35,9 +35,10 @@
  *     NULL = the default stream); device faults surface at the caller's
  *     synchronisation;
  *   - the caller owns every device buffer, the workspace included; the
- *     library's kernels allocate no device memory (the rocBLAS baseline binds
- *     rocBLAS to a region of the caller's workspace; the rocBLAS handle itself
- *     is created by rocBLAS on the first hsbuild_forward_hsdla call);
+ *     library's kernels allocate no device memory (the rocBLAS/rocSOLVER
+ *     paths bind the vendor library to a region of the caller's workspace;
+ *     the rocBLAS handle itself is created by rocBLAS the first time a handle
+ *     sizes or runs hsbuild_forward_hsdla or hsbuild_eigensolve);
  *   - a handle is not thread-safe: use one handle per stream.
  */
 #ifndef HSBUILD_H
@@ -161,7 +162,7 @@ int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const 
  * both triangles of H (its strict lower triangle is not meaningful).
  * Workspace: hsbuild_workspace_bytes(h, HSB_MODE_HSDLA, 1, &ng), which
  * includes the device memory rocBLAS asks for (the library binds it to the
- * caller's workspace).  The first call on a handle creates its rocBLAS handle. */
+ * caller's workspace). */
 int hsbuild_forward_hsdla(hsbuild_t h, int32_t algorithm, const double k_frac[3], int32_t ng, const int32_t* g,
                           const double* tau, const void* T, void* H, void* S, void* ws, size_t ws_bytes,
                           void* stream);
