@@ -331,6 +331,10 @@ def batch_leg(args) -> dict:
     ng = [int(x) for x in case["n_g"]]
     k_c = case["n_atoms"] * case["n_l"]
     flops = sum(16.0 * k_c * n * (n + 1) + 32.0 * case["n_atoms"] * case["n_l"] ** 2 * n for n in ng)
+    from paper_1712_07206_amd import autotune
+    tuned = autotune.tune_batch(b, case["k_frac"], gl, tau, T)
+    log("batch autotuner: waves %d, tile group %d (%s)" % (tuned["waves"], tuned["tile_group"], ", ".join(
+        "%s %.1f ms" % kv for kv in tuned["candidates_ms"].items())))
     H, S, off = b.batch(case["k_frac"], gl, tau, T)  # captures the graph
     torch.cuda.synchronize()
     e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -363,7 +367,9 @@ def batch_leg(args) -> dict:
     torch.cuda.empty_cache()
     return {"workload": case["name"], "n_k": n_k, "n_g_min": min(ng), "n_g_max": max(ng),
             "ms_graph": round(ms_graph, 4), "ms_sequential": round(ms_seq, 4),
-            "speedup": round(ms_seq / ms_graph, 4), "fp64_equiv_tflops": round(flops / (ms_graph * 1e-3) / 1e12, 4)}
+            "speedup": round(ms_seq / ms_graph, 4), "fp64_equiv_tflops": round(flops / (ms_graph * 1e-3) / 1e12, 4),
+            "autotuned": {"waves": tuned["waves"], "tile_group": tuned["tile_group"],
+                          "candidates_ms": {k: round(v, 3) for k, v in tuned["candidates_ms"].items()}}}
 
 
 def adjoint_leg(args) -> dict:

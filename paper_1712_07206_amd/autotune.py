@@ -88,3 +88,31 @@ def tune(builder, k_frac, g, tau, T, precision: int = N.HSB_FP64, groups: Iterab
         os.replace(tmp, path)
     del H, S, ws
     return result
+
+
+def tune_batch(builder, k_frac, g_list, tau, T, groups: Iterable[int] = (8, 4), waves: Iterable[int] = (8, 4),
+               reps: int = 1) -> dict:
+    """Times hsbuild_batch (one captured graph, one persistent contraction over
+    every k-point's tiles) for each (waves, tile order) and keeps the fastest.
+    Each candidate re-captures the graph once, untimed."""
+    times = {}
+    H = S = None
+    for wv in waves:
+        for gr in groups:
+            builder.set_option(N.HSB_OPT_HS_WAVES, wv)
+            builder.set_option(N.HSB_OPT_TILE_GROUP, gr)
+            H, S, _ = builder.batch(k_frac, g_list, tau, T, H, S)  # capture
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            for _ in range(reps):
+                builder.batch(k_frac, g_list, tau, T, H, S)
+            e1.record()
+            torch.cuda.synchronize()
+            times[(wv, gr)] = e0.elapsed_time(e1) / reps
+    best = min(times, key=times.get)
+    builder.set_option(N.HSB_OPT_HS_WAVES, best[0])
+    builder.set_option(N.HSB_OPT_TILE_GROUP, best[1])
+    del H, S
+    return {"waves": best[0], "tile_group": best[1], "ms": times[best],
+            "candidates_ms": {"w%d_g%d" % k: v for k, v in times.items()}}

@@ -120,3 +120,31 @@ def test_batch_error_paths():
     with pytest.raises(N.HSBuildError) as e:
         b.batch(case["k_frac"], gl, tau, T, out_off=[0, -5])
     assert e.value.code == N.HSB_ERR_ARG
+
+
+def test_batch_autotuner_picks_a_candidate_and_keeps_results():
+    """tune_batch times the candidates on the batch call itself and leaves the
+    fastest set; every candidate gives bitwise the same blocks."""
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd import autotune
+    from paper_1712_07206_amd.hsbuild import HSBuilder
+    case = make_batch_case(3, n_k=3)
+    b = HSBuilder.from_case(case)
+    tau = torch.as_tensor(case["tau"], device="cuda")
+    T = torch.as_tensor(case["T"], device="cuda")
+    gl = [torch.as_tensor(g, device="cuda") for g in case["g"]]
+    ng = [int(x) for x in case["n_g"]]
+
+    def upper_blocks(H, off):  # only the written upper triangles are defined
+        return [torch.triu(H[int(off[k]): int(off[k]) + ng[k] ** 2].view(ng[k], ng[k])) for k in range(len(ng))]
+
+    H0, S0, off = b.batch(case["k_frac"], gl, tau, T)
+    torch.cuda.synchronize()
+    ref = upper_blocks(H0, off) + upper_blocks(S0, off)
+    res = autotune.tune_batch(b, case["k_frac"], gl, tau, T)
+    assert (res["waves"], res["tile_group"]) in {(8, 8), (8, 4), (4, 8), (4, 4)}
+    assert b.get_option(N.HSB_OPT_HS_WAVES) == res["waves"]
+    H1, S1, off1 = b.batch(case["k_frac"], gl, tau, T)
+    torch.cuda.synchronize()
+    got = upper_blocks(H1, off1) + upper_blocks(S1, off1)
+    assert all(torch.equal(a, c) for a, c in zip(ref, got))
