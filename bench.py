@@ -593,7 +593,13 @@ def main() -> int:
     log("timed %d steps: %.3f ms/step (wall %.3f s); stages ms: coef %.3f, tprod %.3f, hs %.3f over %d calls"
         % (args.steps, ms_step, wall, stage_ms[0], stage_ms[1], stage_ms[2], calls))
     tflops = flops / (ms_step * 1e-3) / 1e12
-    hs_tflops = flops_hs / (stage_ms[2] * 1e-3) / 1e12
+    # The 8-wave contraction forms each complex product from three real ones
+    # (12 instead of 16 flops per stacked row and upper-triangle entry pair), the
+    # 4-wave one from four: the roofline prices the kernel on the products it
+    # has to execute, the headline on the conventional count.
+    flops_hs_exec = (12.0 if options["waves"] == 8 else 16.0) * k_c * n * (n + 1)
+    hs_tflops = flops_hs_exec / (stage_ms[2] * 1e-3) / 1e12
+    hs_equiv = flops_hs / (stage_ms[2] * 1e-3) / 1e12
 
     result = {
         "metric": METRIC,
@@ -612,6 +618,8 @@ def main() -> int:
         "config": {"workload": case["name"], "n_atoms": n_at, "n_types": case["n_types"], "l_max": case["l_max"],
                    "n_l": n_l, "n_g": n, "k_c": k_c, "precision": "fp64", "flops_per_step": flops},
         "pct_fp64_mfma_peak": round(100.0 * tflops / FP64_MFMA_PEAK_TFLOPS, 2),
+        "pct_note": "FP64-equivalent rate (conventional 8-flop complex multiply-add count) over the FP64 MFMA "
+                    "peak; the 3-product complex form lets it pass 100%",
         "contraction_options": options,
         "stages_ms": {"coefficients": round(stage_ms[0], 4), "t_products": round(stage_ms[1], 4),
                       "hs_contraction": round(stage_ms[2], 4)},
@@ -619,7 +627,9 @@ def main() -> int:
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(hs_tflops / FP64_MFMA_PEAK_TFLOPS, 4),
                      "traffic": recorded_traffic(case["name"], options),
-                     "algorithmic_flops_per_launch": flops_hs},
+                     "algorithmic_flops_per_launch": flops_hs_exec,
+                     "complex_form": "3M" if options["waves"] == 8 else "4M",
+                     "fp64_equiv_tflops": round(hs_equiv, 4)},
         "split_speedup": None,
     }
     if not args.no_factored:

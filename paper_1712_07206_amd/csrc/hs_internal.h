@@ -42,6 +42,7 @@ struct TypeConsts {
 struct Layout {
   int n = 0, n_pad = 0, K = 0, K_pad = 0;
   size_t W = 0, Y = 0, ang = 0, ab = 0, kv = 0, lam = 0, consts = 0, end = 0;
+  size_t WL = 0;  // lam W (the FP64 contraction's S operand), forward in FP64 only
   size_t PH = 0, PS = 0, partT = 0, partTau = 0;  // backward only
   int K_pad2 = 0;                                  // split only: stacked rows padded to 32
   size_t mx = 0, scale = 0, slL = 0, slS = 0, slY = 0;  // split only
@@ -58,7 +59,7 @@ struct Layout {
 
 // Per-k-point entry of the batched contraction's tile list (device copy in the workspace).
 struct BatchMeta {
-  int64_t w_off, y_off;  // W_k and Y_k, in complex elements from the workspace base
+  int64_t w_off, wl_off, y_off;  // W_k, lam W_k and Y_k, in complex elements from the workspace base
   int64_t out_off;       // H_k, S_k, in complex elements from the output bases (ld = n)
   int n, n_pad, nbr, tile_start;
 };
@@ -90,11 +91,13 @@ hipError_t launch_zero_rows(double2* a, int64_t ld, int row0, int row1, hipStrea
 // Y_atom = T_type(atom) W_atom for every atom (rows of W/Y per atom: 2N_L).
 hipError_t launch_tprod(const CellArgs& c, const double2* T, const double2* W, double2* Y, int n_pad,
                         hipStream_t s);
-// Upper triangles of H = W^H Y and S = W^H diag(lam) W over K_pad rows.
+// Upper triangles of H = W^H Y and S = W^H WL over K_pad rows (WL = diag(lam) W, prepared).
 // gr: tile order (0 row-major, > 0 super-rows taken in groups of gr).
 // waves: 4 (64 x 32 per wave) or 8 (32 x 32 per wave).
-hipError_t launch_hs_fp64(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
-                          int gr, int waves, double2* H, double2* S, int64_t ldh, hipStream_t s);
+// waves 8: three real MFMAs per complex multiply-add (3M form, operands WL and Y); waves 4: the plain
+// four-MFMA form (lam applied to W while staging).
+hipError_t launch_hs_fp64(const double2* W, const double2* WL, const double2* Y, const double* lam, int K_pad, int n,
+                          int n_pad, int gr, int waves, double2* H, double2* S, int64_t ldh, hipStream_t s);
 
 // The same contraction keeping only the real parts, Re(W^H Y) and Re(W^H lam W), as doubles.
 hipError_t launch_hs_fp64_real(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,

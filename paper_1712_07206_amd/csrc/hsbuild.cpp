@@ -134,6 +134,7 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
     L.W = take((size_t)L.K_pad * np * sizeof(double2));
     L.Y = take((size_t)L.K_pad * np * sizeof(double2));
   }
+  if (mode == HSB_MODE_FORWARD && h.precision == HSB_FP64) L.WL = take((size_t)L.K_pad * np * sizeof(double2));
   if (mode == HSB_MODE_FORWARD && h.precision != HSB_FP64) {
     L.K_pad2 = (int)round_up(L.K, 32);
     const size_t planes = (size_t)2 * h.n_slices * np * L.K_pad2 * 2;  // bytes per sliced operand
@@ -240,6 +241,9 @@ int enqueue_operands(hsbuild_t h, const Layout& L, const double k_frac[3], const
   if (rc) return rc;
   mark(h, 1, s);
   rc = launched(h, launch_tprod(c, (const double2*)T, W, Y, L.n_pad, s), "k_tprod");
+  if (!rc && L.WL)  // the FP64 contraction's S operand, lam W
+    rc = launched(h, launch_scale_rows(W, (const double*)(ws + L.lam), L.K_pad, L.n_pad, (double2*)(ws + L.WL), s),
+                  "k_scale_rows");
   mark(h, 2, s);
   return rc;
 }
@@ -281,7 +285,7 @@ struct BatchLayout {
   int K = 0, K_pad = 0, max_n_pad = 0;
   size_t consts = 0, lam = 0, meta = 0, end = 0;
   size_t kv[kBranches] = {}, ang[kBranches] = {}, ab[kBranches] = {};
-  std::vector<size_t> W, Y;
+  std::vector<size_t> W, WL, Y;
   std::vector<int> n_pad;
 };
 
@@ -310,6 +314,7 @@ BatchLayout make_batch_layout(const hsbuild_s& h, int n_k, const int32_t* ng) {
   B.meta = take((size_t)n_k * sizeof(BatchMeta));
   for (int k = 0; k < n_k; ++k) {
     B.W.push_back(take((size_t)B.K_pad * B.n_pad[k] * sizeof(double2)));
+    B.WL.push_back(take((size_t)B.K_pad * B.n_pad[k] * sizeof(double2)));
     B.Y.push_back(take((size_t)B.K_pad * B.n_pad[k] * sizeof(double2)));
   }
   B.end = off;
@@ -561,8 +566,9 @@ int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32
   mark(h, 0, s);
   if ((rc = enqueue_operands(h, L, k_frac, g, tau, T, w, s))) return rc;
   if (h->precision == HSB_FP64) {
-    rc = launched(h, launch_hs_fp64((const double2*)(w + L.W), (const double2*)(w + L.Y), (const double*)(w + L.lam),
-                                    L.K_pad, ng, L.n_pad, h->tile_group, h->hs_waves, (double2*)H, (double2*)S, ng, s),
+    rc = launched(h, launch_hs_fp64((const double2*)(w + L.W), (const double2*)(w + L.WL), (const double2*)(w + L.Y),
+                                    (const double*)(w + L.lam), L.K_pad, ng, L.n_pad, h->tile_group, h->hs_waves,
+                                    (double2*)H, (double2*)S, ng, s),
                   "k_hs_fp64");
   } else {
     rc = enqueue_split(h, L, w, (double2*)H, (double2*)S, s);
@@ -828,10 +834,14 @@ int hsbuild_forward_coefficients(hsbuild_t h, int32_t ng, const void* coef, cons
   if ((rc = launched(h, launch_zero_rows(W, L.n_pad, L.K, L.K_pad, s), "k_zero_rows"))) return rc;
   if ((rc = launched(h, launch_zero_rows(Y, L.n_pad, L.K, L.K_pad, s), "k_zero_rows"))) return rc;
   if ((rc = launched(h, launch_tprod(c, (const double2*)T, W, Y, L.n_pad, s), "k_tprod"))) return rc;
-  if (h->precision == HSB_FP64)
-    return launched(h, launch_hs_fp64(W, Y, (const double*)(w + L.lam), L.K_pad, ng, L.n_pad, h->tile_group,
+  if (h->precision == HSB_FP64) {
+    double2* WL = (double2*)(w + L.WL);
+    if ((rc = launched(h, launch_scale_rows(W, (const double*)(w + L.lam), L.K_pad, L.n_pad, WL, s), "k_scale_rows")))
+      return rc;
+    return launched(h, launch_hs_fp64(W, WL, Y, (const double*)(w + L.lam), L.K_pad, ng, L.n_pad, h->tile_group,
                                       h->hs_waves, (double2*)H, (double2*)S, ng, s),
                     "k_hs_fp64");
+  }
   return enqueue_split(h, L, w, (double2*)H, (double2*)S, s);
 }
 
@@ -923,6 +933,7 @@ int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t*
     for (int k = 0; k < n_k; ++k) {
       BatchMeta& m = h->meta_host[k];
       m.w_off = (int64_t)(B.W[k] / sizeof(double2));
+      m.wl_off = (int64_t)(B.WL[k] / sizeof(double2));
       m.y_off = (int64_t)(B.Y[k] / sizeof(double2));
       m.out_off = out_off[k];
       m.n = ng[k];
@@ -966,6 +977,7 @@ int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t*
       L.ang = B.ang[b];
       L.ab = B.ab[b];
       L.W = B.W[k];
+      L.WL = B.WL[k];
       L.Y = B.Y[k];
       rc = enqueue_operands(h, L, k_frac + 3 * k, g + 3 * g_rows[k], tau, T, w, h->aux[b], nullptr, true);
     }

@@ -194,11 +194,139 @@ __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, cons
       }
 }
 
+// The complex contraction with three real products per complex multiply-add
+// (the Gauss/3M form): for Re + i Im = conj(a) b,
+//   P1 = a_r b_r,  P2 = a_i b_i,  P3 = (a_r - a_i)(b_r + b_i),
+//   Re = P1 + P2,  Im = P3 - P1 + P2,
+// each P summed over k in its own accumulator and combined in the epilogue:
+// 3 MFMAs where the plain form issues 4, for the same sums up to rounding.  The
+// operand sums are formed in registers after the LDS reads.  The three K-chunk
+// operands (W at the G' rows, lam W and Y at the G columns; lam W prepared in HBM)
+// are copied straight into double-buffered LDS with global_load_lds_dwordx4, one
+// barrier per chunk, so no staging registers are held across the MFMAs.
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+template <int WR>
+__device__ __forceinline__ void hs_tile3m(Smem& sm, const d2* __restrict__ W, const d2* __restrict__ WL,
+                                          const d2* __restrict__ Y, int K_pad, int n, int n_pad, int row0, int col0,
+                                          d2* __restrict__ H, d2* __restrict__ S, int64_t ldh) {
+  constexpr int NWV = 2 * WR;              // waves
+  constexpr int MI = BM / WR / 16;         // row blocks per wave
+  constexpr int NCP = BK * 2 + BK + BK;    // 1 KB copies per chunk: L rows are two copies, R and Y one
+  constexpr int CPW = NCP / NWV;           // copies per wave
+  static_assert(NCP % NWV == 0, "copy map");
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+
+  // copy j: j < 2 BK: L row j/2, half j%2; then BK rows of lam W (R); then BK rows of Y
+  const d2* src0[CPW];
+  int dst[CPW];  // d2 offset inside one buffer of sm (L, R, Y are consecutive members)
+#pragma unroll
+  for (int i = 0; i < CPW; ++i) {
+    const int j = wave + NWV * i;
+    if (j < 2 * BK) {
+      src0[i] = W + (int64_t)(j >> 1) * n_pad + row0 + (j & 1) * 64;
+      dst[i] = (j >> 1) * BM + (j & 1) * 64;
+    } else if (j < 3 * BK) {
+      const int r = j - 2 * BK;
+      src0[i] = WL + (int64_t)r * n_pad + col0;
+      dst[i] = 2 * BK * BM + r * BN;  // after L[2][BK][BM]
+    } else {
+      const int r = j - 3 * BK;
+      src0[i] = Y + (int64_t)r * n_pad + col0;
+      dst[i] = 2 * BK * BM + 2 * BK * BN + r * BN;  // after R[2][BK][BN]
+    }
+  }
+  d2* base = &sm.L[0][0][0];
+  auto issue = [&](int c, int buf) {
+#pragma unroll
+    for (int i = 0; i < CPW; ++i) {
+      const int j = wave + NWV * i;
+      // the buffer index moves L by BK*BM and R, Y by BK*BN elements
+      const int off = dst[i] + buf * (j < 2 * BK ? BK * BM : BK * BN);
+      __builtin_amdgcn_global_load_lds((const void*)(src0[i] + (int64_t)c * BK * n_pad + lane),
+                                       (lds_ptr)(base + off), 16, 0, 0);
+    }
+  };
+
+  d4 h1[MI][2], h2[MI][2], h3[MI][2], s1[MI][2], s2[MI][2], s3[MI][2];
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+      h1[i][j] = h2[i][j] = h3[i][j] = s1[i][j] = s2[i][j] = s3[i][j] = d4{0.0, 0.0, 0.0, 0.0};
+
+  const int nchunks = K_pad / BK;
+  issue(0, 0);
+  for (int c = 0; c < nchunks; ++c) {
+    const int b = c & 1;
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of chunk c have landed
+    __syncthreads();                // everyone's have, and buffer b^1 is free
+    if (c + 1 < nchunks) issue(c + 1, b ^ 1);
+#pragma unroll
+    for (int ks = 0; ks < BK / 4; ++ks) {
+      const int kk = ks * 4 + (lane >> 4);
+      double ar[MI], ai[MI], ad[MI], yre[2], yim[2], ys[2], wre[2], wim[2], wsum[2];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        const d2 a = sm.L[b][kk][wr * (BM / WR) + i * 16 + (lane & 15)];
+        ar[i] = a.x; ai[i] = a.y; ad[i] = a.x - a.y;
+      }
+#pragma unroll
+      for (int j = 0; j < 2; ++j) {
+        const d2 yv = sm.Y[b][kk][wc * 32 + j * 16 + (lane & 15)];
+        const d2 wv = sm.R[b][kk][wc * 32 + j * 16 + (lane & 15)];
+        yre[j] = yv.x; yim[j] = yv.y; ys[j] = yv.x + yv.y;
+        wre[j] = wv.x; wim[j] = wv.y; wsum[j] = wv.x + wv.y;
+      }
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          h1[i][j] = MFMA(ar[i], yre[j], h1[i][j]);
+          s1[i][j] = MFMA(ar[i], wre[j], s1[i][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          h2[i][j] = MFMA(ai[i], yim[j], h2[i][j]);
+          s2[i][j] = MFMA(ai[i], wim[j], s2[i][j]);
+        }
+#pragma unroll
+      for (int i = 0; i < MI; ++i)
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          h3[i][j] = MFMA(ad[i], ys[j], h3[i][j]);
+          s3[i][j] = MFMA(ad[i], wsum[j], s3[i][j]);
+        }
+    }
+  }
+
+  // D layout of the 16x16 f64 MFMA: lane l, element q -> row l/16 + 4q, column l%16
+#pragma unroll
+  for (int i = 0; i < MI; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int row = row0 + wr * (BM / WR) + i * 16 + (lane >> 4) + 4 * q;
+        const int col = col0 + wc * 32 + j * 16 + (lane & 15);
+        if (row < n && col < n && col >= row) {
+          const int64_t o = (int64_t)row * ldh + col;
+          const double p1 = h1[i][j][q], p2 = h2[i][j][q], q1 = s1[i][j][q], q2 = s2[i][j][q];
+          H[o] = d2{p1 + p2, h3[i][j][q] - p1 + p2};
+          S[o] = d2{q1 + q2, s3[i][j][q] - q1 + q2};
+        }
+      }
+}
+
 template <int WR, bool REAL>
-__global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64(const d2* __restrict__ W, const d2* __restrict__ Y,
-                                                     const double* __restrict__ lam, int K_pad, int n, int n_pad,
-                                                     int nbr, int num_wg, int gr, void* __restrict__ H,
-                                                     void* __restrict__ S, int64_t ldh) {
+__global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64(const d2* __restrict__ W, const d2* __restrict__ WL,
+                                                     const d2* __restrict__ Y, const double* __restrict__ lam,
+                                                     int K_pad, int n, int n_pad, int nbr, int num_wg, int gr,
+                                                     void* __restrict__ H, void* __restrict__ S, int64_t ldh) {
   __shared__ Smem sm;
   // dispatch is round-robin over XCDs: give XCD x the contiguous range of tile numbers
   const int x = blockIdx.x % kXcds;
@@ -208,7 +336,9 @@ __global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64(const d2* __restrict__ 
   int row0, col0;
   tile_origin(w, nbr, gr, row0, col0);
   if (col0 >= n) return;
-  hs_tile<WR, REAL>(sm, W, Y, lam, K_pad, n, n_pad, row0, col0, H, S, ldh);
+  if constexpr (REAL) hs_tile<WR, true>(sm, W, Y, lam, K_pad, n, n_pad, row0, col0, H, S, ldh);
+  else if constexpr (WR == 4) hs_tile3m<WR>(sm, W, WL, Y, K_pad, n, n_pad, row0, col0, (d2*)H, (d2*)S, ldh);
+  else hs_tile<WR, false>(sm, W, Y, lam, K_pad, n, n_pad, row0, col0, H, S, ldh);  // 64 x 32 per wave: plain form
 }
 
 template <int WR>
@@ -233,8 +363,12 @@ __global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64_batch(const d2* __restr
     int row0, col0;
     tile_origin(t - m.tile_start, m.nbr, gr, row0, col0);
     if (col0 >= m.n) continue;  // uniform across the workgroup
-    hs_tile<WR, false>(sm, ws + m.w_off, ws + m.y_off, lam, K_pad, m.n, m.n_pad, row0, col0, H + m.out_off,
-                       S + m.out_off, m.n);
+    if constexpr (WR == 4)
+      hs_tile3m<WR>(sm, ws + m.w_off, ws + m.wl_off, ws + m.y_off, K_pad, m.n, m.n_pad, row0, col0, H + m.out_off,
+                    S + m.out_off, m.n);
+    else
+      hs_tile<WR, false>(sm, ws + m.w_off, ws + m.y_off, lam, K_pad, m.n, m.n_pad, row0, col0, H + m.out_off,
+                         S + m.out_off, m.n);
   }
 }
 
@@ -368,16 +502,17 @@ int hs_tiles(int n_pad) {
   return nbr * (nbr + 1);
 }
 
-hipError_t launch_hs_fp64(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
-                          int gr, int waves, double2* H, double2* S, int64_t ldh, hipStream_t s) {
+hipError_t launch_hs_fp64(const double2* W, const double2* WL, const double2* Y, const double* lam, int K_pad, int n,
+                          int n_pad, int gr, int waves, double2* H, double2* S, int64_t ldh, hipStream_t s) {
   const int nbr = n_pad / BM;
   const int num_wg = hs_tiles(n_pad);  // two 128 x 64 tiles per upper-triangle 128 x 128 super-tile
   if (waves == 8)
-    hipLaunchKernelGGL((k_hs_fp64<4, false>), dim3(num_wg), dim3(512), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad,
-                       n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
+    hipLaunchKernelGGL((k_hs_fp64<4, false>), dim3(num_wg), dim3(512), 0, s, (const d2*)W, (const d2*)WL,
+                       (const d2*)Y, (const double*)nullptr, K_pad, n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S,
+                       ldh);
   else
-    hipLaunchKernelGGL((k_hs_fp64<2, false>), dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad,
-                       n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
+    hipLaunchKernelGGL((k_hs_fp64<2, false>), dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)WL,
+                       (const d2*)Y, lam, K_pad, n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
   return hipGetLastError();
 }
 
@@ -389,8 +524,8 @@ hipError_t launch_hs_fp64_real(const double2* W, const double2* Y, const double*
     hipLaunchKernelGGL(k_hs_real, dim3(num_wg / 2), dim3(512), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad, n,
                        n_pad, nbr, num_wg / 2, gr, H, S, ldh);
   else
-    hipLaunchKernelGGL((k_hs_fp64<2, true>), dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad,
-                       n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
+    hipLaunchKernelGGL((k_hs_fp64<2, true>), dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)nullptr,
+                       (const d2*)Y, lam, K_pad, n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
   return hipGetLastError();
 }
 

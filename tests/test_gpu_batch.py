@@ -48,21 +48,29 @@ def test_batch_equals_sequential_bitwise():
         assert np.array_equal(_block(Sc, off[k], n)[iu], s1.cpu().numpy()[iu]), k
 
 
-def test_batch_eight_wave_variant_bitwise():
+def test_batch_wave_and_order_variants():
+    """Tile order: bitwise equal at one wave count.  The 4-wave contraction takes
+    the four-product complex form and the 8-wave one the three-product form, so
+    across wave counts they agree to FP64 rounding."""
     from paper_1712_07206_amd import _native as N
     case = make_batch_case(3, n_k=3)
     b, tau, T, gl = _setup(case)
-    H1, S1, _ = b.batch(case["k_frac"], gl, tau, T)
-    H1, S1 = H1.clone(), S1.clone()
-    b.set_option(N.HSB_OPT_HS_WAVES, 8)
-    b.set_option(N.HSB_OPT_TILE_GROUP, 4)
-    H2, S2, off = b.batch(case["k_frac"], gl, tau, T)
-    torch.cuda.synchronize()
+    out = []
+    for wv, gr in ((8, 8), (8, 4), (4, 8), (4, 0)):
+        b.set_option(N.HSB_OPT_HS_WAVES, wv)
+        b.set_option(N.HSB_OPT_TILE_GROUP, gr)
+        H, S, off = b.batch(case["k_frac"], gl, tau, T)
+        torch.cuda.synchronize()
+        out.append((H.cpu().numpy(), S.cpu().numpy()))
     for k in range(3):
         n = int(case["n_g"][k])
         iu = np.triu_indices(n)
-        assert np.array_equal(_block(H1.cpu().numpy(), off[k], n)[iu], _block(H2.cpu().numpy(), off[k], n)[iu])
-        assert np.array_equal(_block(S1.cpu().numpy(), off[k], n)[iu], _block(S2.cpu().numpy(), off[k], n)[iu])
+        blk = [(_block(H, off[k], n)[iu], _block(S, off[k], n)[iu]) for H, S in out]
+        for a, c in ((0, 1), (2, 3)):
+            assert np.array_equal(blk[a][0], blk[c][0]) and np.array_equal(blk[a][1], blk[c][1]), (k, a, c)
+        for i in range(2):
+            e = float(np.linalg.norm(blk[0][i] - blk[2][i]) / np.linalg.norm(blk[2][i]))
+            assert e <= 1e-12, (k, i, e)
 
 
 def test_batch_graph_reuse_and_recapture():

@@ -165,25 +165,32 @@ def test_stage_timing_records_calls():
 
 
 def test_tile_order_options_bitwise_identical():
-    """The tile-order option only changes scheduling: H and S are bitwise equal."""
+    """The tile-order option only changes scheduling: at one wave count H and S
+    are bitwise equal.  The two wave counts take different complex-product forms
+    (three real products per complex one with 8 waves, four with 4), so across
+    them the results agree to FP64 rounding."""
     from paper_1712_07206_amd import _native as N
     from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
     case = make_case(1, n_g=1500)
     b = HSBuilder.from_case(case)
     g, tau, T = case_tensors(case)
-    ref = None
-    for wv, gr in ((4, 0), (4, 1), (4, 3), (8, 0), (8, 4), (4, 64)):
+    ref = {}
+    iu = np.triu_indices(1500)
+    for wv, gr in ((4, 0), (4, 1), (4, 3), (8, 0), (8, 4), (8, 8), (4, 64)):
         b.set_option(N.HSB_OPT_TILE_GROUP, gr)
         b.set_option(N.HSB_OPT_HS_WAVES, wv)
         assert b.get_option(N.HSB_OPT_TILE_GROUP) == gr and b.get_option(N.HSB_OPT_HS_WAVES) == wv
         H, S = b.forward(case["k_frac"], g, tau, T)
         torch.cuda.synchronize()
-        iu = np.triu_indices(1500)
         cur = (H.cpu().numpy()[iu], S.cpu().numpy()[iu])
-        if ref is None:
-            ref = cur
+        if wv not in ref:
+            ref[wv] = cur
         else:
-            assert np.array_equal(ref[0], cur[0]) and np.array_equal(ref[1], cur[1]), gr
+            assert np.array_equal(ref[wv][0], cur[0]) and np.array_equal(ref[wv][1], cur[1]), (wv, gr)
+    for i in range(2):
+        e = float(np.linalg.norm(ref[8][i] - ref[4][i]) / np.linalg.norm(ref[4][i]))
+        print("8-wave (3M) vs 4-wave form:", "HS"[i], "%.3e" % e)
+        assert e <= TOL_HS
     with pytest.raises(N.HSBuildError):
         b.set_option(N.HSB_OPT_TILE_GROUP, -1)
     with pytest.raises(N.HSBuildError):
