@@ -219,15 +219,18 @@ int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t*
 int hsbuild_set_timing(hsbuild_t h, int32_t enable);
 int hsbuild_stage_times(hsbuild_t h, double* ms_avg, int32_t* n_calls);
 
-/* Tuning options (performance only: results are bitwise independent of them).
+/* Tuning options (performance only).
  * HSB_OPT_TILE_GROUP: order in which the upper-triangle tiles of every
  * contraction are dealt to the compute units: 0 = row-major, g > 0 = super-rows
  * (128 rows; 64 for the factored kernel) taken g at a time, column by column
- * (0..64; default 8, or 4 on a handle with a split precision).
+ * (0..64; default 8, or 4 on a handle with a split precision).  Results are
+ * bitwise independent of it.
  * HSB_OPT_HS_WAVES: waves per workgroup of the FP64 contraction, 4 (64 x 32
- * outputs per wave, one wave per SIMD) or 8 (32 x 32 per wave, two per SIMD;
- * 128 x 128 tiles of 32 x 64 for hsbuild_forward_real); default 8.  Setting
- * an option drops a captured batch graph. */
+ * outputs per wave, one wave per SIMD; four real products per complex one) or
+ * 8 (32 x 32 per wave, two per SIMD; three real products per complex one, the
+ * 3M form; 128 x 128 tiles of 32 x 64 for hsbuild_forward_real, which is
+ * real); default 8.  The two complex forms agree to FP64 rounding, not
+ * bitwise.  Setting an option drops a captured batch graph. */
 enum { HSB_OPT_TILE_GROUP = 1, HSB_OPT_HS_WAVES = 2 };
 int hsbuild_set_option(hsbuild_t h, int32_t option, int32_t value);
 int hsbuild_get_option(hsbuild_t h, int32_t option, int32_t* value);
