@@ -44,6 +44,8 @@ struct Layout {
   size_t W = 0, Y = 0, ang = 0, ab = 0, kv = 0, lam = 0, consts = 0, end = 0;
   size_t WL = 0;  // lam W (the FP64 contraction's S operand), forward in FP64 only
   size_t PH = 0, PS = 0, partT = 0, partTau = 0;  // backward only
+  size_t WT = 0, gHp = 0, gSp = 0;                // backward: operands of the 3M products
+  int Kt = 0;                                     // backward: K_pad rounded up to 128
   int K_pad2 = 0;                                  // split only: stacked rows padded to 32
   size_t mx = 0, scale = 0, slL = 0, slS = 0, slY = 0;  // split only
   // factored only: rows [R_f] of X (E and W0 blocks), XL = lam X, Yx (Y0 on W0 rows, 0 on E rows)
@@ -154,9 +156,14 @@ hipError_t launch_conj(double2* a, int64_t count, hipStream_t s);
 
 // ---- adjoint ----
 int gradtau_blocks(int n);
-// P_H = W gH and P_S = W gS ([K_pad][n_pad]); gH, gS are [n][n].
-hipError_t launch_pgemm(const double2* W, const double2* gH, const double2* gS, int K_pad, int n, int n_pad,
-                        double2* PH, double2* PS, hipStream_t s);
+// P_H = W gH and P_S = W gS ([K_pad][n_pad]) in the 3M form from W^T ([n_pad][Kt], Kt a multiple
+// of 128, zeros past K_pad) and gS, gH zero-padded to [n_pad][n_pad].
+hipError_t launch_pgemm3m(const double2* WT, const double2* gSp, const double2* gHp, int Kt, int K_pad, int n_pad,
+                          double2* PH, double2* PS, hipStream_t s);
+// WT[G][k] = W[k][G] (k < K_pad), 0 for K_pad <= k < Kt.
+hipError_t launch_transpose(const double2* W, int K_pad, int n_pad, int Kt, double2* WT, hipStream_t s);
+// gp = g ([n][n]) zero-padded to [n_pad][n_pad].
+hipError_t launch_pad_square(const double2* g, int n, int n_pad, double2* gp, hipStream_t s);
 // gT[t] = sum over atoms of type t of P_H,a W_a^H (part: [n_atoms][2N_L][2N_L] scratch).
 hipError_t launch_gradT(const CellArgs& c, const double2* PH, const double2* W, int n_pad, double2* part,
                         double2* gT, hipStream_t s);

@@ -154,6 +154,10 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
     const size_t M = 2 * (size_t)h.n_l;
     L.PH = take((size_t)L.K_pad * np * sizeof(double2));
     L.PS = take((size_t)L.K_pad * np * sizeof(double2));
+    L.Kt = (int)round_up(L.K_pad, 128);
+    L.WT = take((size_t)np * L.Kt * sizeof(double2));
+    L.gHp = take((size_t)np * np * sizeof(double2));
+    L.gSp = take((size_t)np * np * sizeof(double2));
     L.partT = take((size_t)h.n_atoms * M * M * sizeof(double2));
     L.partTau = take((size_t)h.n_atoms * gradtau_blocks(ng) * 3 * sizeof(double));
   }
@@ -864,8 +868,14 @@ int hsbuild_backward(hsbuild_t h, const double k_frac[3], int32_t ng, const int3
   const double2* W = (const double2*)(w + L.W);
   double2* PH = (double2*)(w + L.PH);
   double2* PS = (double2*)(w + L.PS);
-  rc = launched(h, launch_pgemm(W, (const double2*)gH, (const double2*)gS, L.K_pad, ng, L.n_pad, PH, PS, s),
-                "k_pgemm");
+  // P_H = W gH, P_S = W gS in the 3M form, from W^T and zero-padded gH, gS
+  double2* WT = (double2*)(w + L.WT);
+  double2* gHp = (double2*)(w + L.gHp);
+  double2* gSp = (double2*)(w + L.gSp);
+  rc = launched(h, launch_transpose(W, L.K_pad, L.n_pad, L.Kt, WT, s), "k_transpose");
+  if (!rc) rc = launched(h, launch_pad_square((const double2*)gH, ng, L.n_pad, gHp, s), "k_pad_square");
+  if (!rc) rc = launched(h, launch_pad_square((const double2*)gS, ng, L.n_pad, gSp, s), "k_pad_square");
+  if (!rc) rc = launched(h, launch_pgemm3m(WT, gSp, gHp, L.Kt, L.K_pad, L.n_pad, PH, PS, s), "k_pgemm3m");
   if (rc) return rc;
   rc = launched(h, launch_gradT(c, PH, W, L.n_pad, (double2*)(w + L.partT), (double2*)gT, s), "k_gradT");
   if (rc) return rc;

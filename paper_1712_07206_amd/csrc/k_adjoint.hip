@@ -10,8 +10,8 @@
 // (A and B of Eq. 2) and H, S are the sums of Eqs. 4-5.  Nothing is kept
 // from the forward: W and Y are rebuilt by the same kernels.
 //
-//   k_pgemm        P_H and P_S in one pass (shared left operand W), FP64 MFMA,
-//                  8 waves, double-buffered LDS
+//   k_transpose,   W^T and zero-padded gH, gS for the products P_H and P_S, which
+//   k_pad_square   run in the 3M form in k_pgemm3m (with the forward's tile routine)
 //   k_gradT        per-atom partials P_H,a W_a^H (FP64 MFMA), one workgroup per
 //                  (64 x 64 tile, atom); k_gradT_reduce sums the atoms of a type
 //                  in a fixed order (deterministic)
@@ -27,141 +27,6 @@ typedef double d4 __attribute__((ext_vector_type(4)));
 typedef double d2 __attribute__((ext_vector_type(2)));
 
 #define MFMA(a, b, c) __builtin_amdgcn_mfma_f64_16x16x4f64((a), (b), (c), 0, 0, 0)
-
-// ---- P_H = W gH, P_S = W gS -------------------------------------------------------------
-// Tile 128 (k) x 64 (G) for both outputs; 8 waves of 32 x 32 (two per SIMD).  The
-// contraction runs over G' in chunks of 16 through double-buffered LDS with a
-// register prefetch of the next chunk.  W is staged transposed (sA[G'][k], padded
-// row) so the A fragment (16 k rows at one G') is a contiguous LDS read.
-constexpr int PM = 128, PN = 64, PK = 16, PT = 512;
-
-__global__ void __launch_bounds__(PT, 1) k_pgemm(const d2* __restrict__ W, const d2* __restrict__ gH,
-                                                 const d2* __restrict__ gS, int K_pad, int n, int n_pad,
-                                                 d2* __restrict__ PH, d2* __restrict__ PS) {
-  __shared__ d2 sA[2][PK][PM + 1];
-  __shared__ d2 sH[2][PK][PN];
-  __shared__ d2 sS[2][PK][PN];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-  const int wr = wave >> 1, wc = wave & 1;  // rows wr*32, columns wc*32
-  const int col0 = blockIdx.x * PN;
-  const int row0 = blockIdx.y * PM;
-  d4 hr[2][2], hi[2][2], sr[2][2], si[2][2];
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      hr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      hi[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      sr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-      si[i][j] = d4{0.0, 0.0, 0.0, 0.0};
-    }
-  // staging: A 16 x 128 (4 per thread, transposed on store), gH and gS 16 x 64 (2 each)
-  d2 pa[4], ph[2], ps[2];
-#define PG_LOAD(kc)                                                                   \
-  do {                                                                                \
-    _Pragma("unroll") for (int i = 0; i < 4; ++i) {                                   \
-      const int e = tid + PT * i;                                                     \
-      const int c = e & 15, r = e >> 4;                                               \
-      pa[i] = row0 + r < K_pad ? W[(int64_t)(row0 + r) * n_pad + (kc) + c] : d2{0.0, 0.0}; \
-    }                                                                                 \
-    _Pragma("unroll") for (int i = 0; i < 2; ++i) {                                   \
-      const int e = tid + PT * i;                                                     \
-      const int r = e >> 6, c = e & 63;                                               \
-      const int gp = (kc) + r, gc = col0 + c;                                         \
-      const bool ok = gp < n && gc < n;                                               \
-      ph[i] = ok ? gH[(int64_t)gp * n + gc] : d2{0.0, 0.0};                           \
-      ps[i] = ok ? gS[(int64_t)gp * n + gc] : d2{0.0, 0.0};                           \
-    }                                                                                 \
-  } while (0)
-#define PG_STORE(b)                                    \
-  do {                                                 \
-    _Pragma("unroll") for (int i = 0; i < 4; ++i) {    \
-      const int e = tid + PT * i;                      \
-      sA[b][e & 15][e >> 4] = pa[i];                   \
-    }                                                  \
-    _Pragma("unroll") for (int i = 0; i < 2; ++i) {    \
-      const int e = tid + PT * i;                      \
-      sH[b][e >> 6][e & 63] = ph[i];                   \
-      sS[b][e >> 6][e & 63] = ps[i];                   \
-    }                                                  \
-  } while (0)
-
-  const int nchunks = n_pad / PK;
-  PG_LOAD(0);
-  PG_STORE(0);
-  __syncthreads();
-  for (int ch = 0; ch < nchunks; ++ch) {
-    const int b = ch & 1;
-    if (ch + 1 < nchunks) PG_LOAD((ch + 1) * PK);
-#pragma unroll
-    for (int ks = 0; ks < PK / 4; ++ks) {
-      const int kk = ks * 4 + (lane >> 4);
-      double ar[2], ai[2], an[2], hre[2], him[2], sre[2], sim[2];
-#pragma unroll
-      for (int i = 0; i < 2; ++i) {
-        const d2 a = sA[b][kk][wr * 32 + i * 16 + (lane & 15)];
-        ar[i] = a.x; ai[i] = a.y; an[i] = -a.y;
-      }
-#pragma unroll
-      for (int j = 0; j < 2; ++j) {
-        const d2 bh = sH[b][kk][wc * 32 + j * 16 + (lane & 15)];
-        const d2 bs = sS[b][kk][wc * 32 + j * 16 + (lane & 15)];
-        hre[j] = bh.x; him[j] = bh.y; sre[j] = bs.x; sim[j] = bs.y;
-      }
-      // (ar + i ai)(br + i bi): re = ar br - ai bi, im = ar bi + ai br
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) hr[i][j] = MFMA(ar[i], hre[j], hr[i][j]);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) hi[i][j] = MFMA(ar[i], him[j], hi[i][j]);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) sr[i][j] = MFMA(ar[i], sre[j], sr[i][j]);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) si[i][j] = MFMA(ar[i], sim[j], si[i][j]);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) hr[i][j] = MFMA(an[i], him[j], hr[i][j]);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) hi[i][j] = MFMA(ai[i], hre[j], hi[i][j]);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) sr[i][j] = MFMA(an[i], sim[j], sr[i][j]);
-#pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) si[i][j] = MFMA(ai[i], sre[j], si[i][j]);
-    }
-    if (ch + 1 < nchunks) PG_STORE(b ^ 1);
-    __syncthreads();
-  }
-#undef PG_LOAD
-#undef PG_STORE
-#pragma unroll
-  for (int i = 0; i < 2; ++i)
-#pragma unroll
-    for (int j = 0; j < 2; ++j)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int row = row0 + wr * 32 + i * 16 + (lane >> 4) + 4 * q;
-        const int col = col0 + wc * 32 + j * 16 + (lane & 15);
-        if (row < K_pad) {
-          const int64_t o = (int64_t)row * n_pad + col;
-          PH[o] = d2{hr[i][j][q], hi[i][j][q]};
-          PS[o] = d2{sr[i][j][q], si[i][j][q]};
-        }
-      }
-}
 
 // ---- grad T partials: part[atom][r][c] = sum_G P_H[a*M + r][G] conj(W[a*M + c][G]) ---------
 constexpr int TT = 64, TKG = 16;
@@ -310,15 +175,45 @@ __global__ void __launch_bounds__(64) k_gradtau_reduce(const double* __restrict_
   gtau[i] = -2.0 * acc;
 }
 
+// ---- operand preparation for the 3M products --------------------------------------
+// WT[G][k] = W[k][G] for k < K_pad, 0 for K_pad <= k < Kt; 32 x 32 tiles through LDS.
+__global__ void __launch_bounds__(256) k_transpose(const d2* __restrict__ W, int K_pad, int n_pad, int Kt,
+                                                   d2* __restrict__ WT) {
+  __shared__ d2 t[32][33];
+  const int k0 = blockIdx.x * 32, g0 = blockIdx.y * 32;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) {
+    const int k = k0 + r;
+    t[r][tx] = k < K_pad ? W[(int64_t)k * n_pad + g0 + tx] : d2{0.0, 0.0};
+  }
+  __syncthreads();
+#pragma unroll
+  for (int r = ty; r < 32; r += 8) WT[(int64_t)(g0 + r) * Kt + k0 + tx] = t[tx][r];
+}
+
+// gp[r][c] = g[r][c] for r, c < n, 0 elsewhere (r, c < n_pad).
+__global__ void __launch_bounds__(256) k_pad_square(const d2* __restrict__ g, int n, int n_pad, d2* __restrict__ gp) {
+  const int c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= n_pad) return;
+  for (int r = blockIdx.y; r < n_pad; r += gridDim.y)
+    gp[(int64_t)r * n_pad + c] = (r < n && c < n) ? g[(int64_t)r * n + c] : d2{0.0, 0.0};
+}
+
 }  // namespace
 
 int gradtau_blocks(int n) { return (n + TB - 1) / TB; }
 
-hipError_t launch_pgemm(const double2* W, const double2* gH, const double2* gS, int K_pad, int n, int n_pad,
-                        double2* PH, double2* PS, hipStream_t s) {
-  dim3 grid(n_pad / PN, (K_pad + PM - 1) / PM);
-  hipLaunchKernelGGL(k_pgemm, grid, dim3(PT), 0, s, (const d2*)W, (const d2*)gH, (const d2*)gS, K_pad, n, n_pad,
-                     (d2*)PH, (d2*)PS);
+hipError_t launch_transpose(const double2* W, int K_pad, int n_pad, int Kt, double2* WT, hipStream_t s) {
+  if (Kt % 32 || n_pad % 32 || Kt < K_pad) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_transpose, dim3(Kt / 32, n_pad / 32), dim3(256), 0, s, (const d2*)W, K_pad, n_pad, Kt,
+                     (d2*)WT);
+  return hipGetLastError();
+}
+
+hipError_t launch_pad_square(const double2* g, int n, int n_pad, double2* gp, hipStream_t s) {
+  hipLaunchKernelGGL(k_pad_square, dim3((n_pad + 255) / 256, n_pad < 4096 ? n_pad : 4096), dim3(256), 0, s,
+                     (const d2*)g, n, n_pad, (d2*)gp);
   return hipGetLastError();
 }
 

@@ -195,46 +195,53 @@ __device__ __forceinline__ void hs_tile(Smem& sm, const d2* __restrict__ W, cons
 }
 
 // The complex contraction with three real products per complex multiply-add
-// (the Gauss/3M form): for Re + i Im = conj(a) b,
+// (the Gauss/3M form).  CONJ: S = sum_k conj(L) R and H = sum_k conj(L) Y, for
+// Re + i Im = conj(a) b
 //   P1 = a_r b_r,  P2 = a_i b_i,  P3 = (a_r - a_i)(b_r + b_i),
-//   Re = P1 + P2,  Im = P3 - P1 + P2,
-// each P summed over k in its own accumulator and combined in the epilogue:
+//   Re = P1 + P2,  Im = P3 - P1 + P2;
+// otherwise the plain products S = sum_k L R, H = sum_k L Y, for a b
+//   P3 = (a_r + a_i)(b_r + b_i),  Re = P1 - P2,  Im = P3 - P1 - P2.
+// Each P is summed over k in its own accumulator and combined in the epilogue:
 // 3 MFMAs where the plain form issues 4, for the same sums up to rounding.  The
 // operand sums are formed in registers after the LDS reads.  The three K-chunk
-// operands (W at the G' rows, lam W and Y at the G columns; lam W prepared in HBM)
-// are copied straight into double-buffered LDS with global_load_lds_dwordx4, one
-// barrier per chunk, so no staging registers are held across the MFMAs.
+// operands (L at the tile rows, R and Y at the tile columns: for the forward W,
+// lam W prepared in HBM, and Y) are copied straight into double-buffered LDS with
+// global_load_lds_dwordx4, one barrier per chunk, so no staging registers are held
+// across the MFMAs.  L rows are ldL long, R and Y rows ldR; Kc (a multiple of 16)
+// rows are contracted.  Stored: row < n_row, col < n_col and, with upper, col >= row.
 typedef __attribute__((address_space(3))) void* lds_ptr;
 
-template <int WR>
-__device__ __forceinline__ void hs_tile3m(Smem& sm, const d2* __restrict__ W, const d2* __restrict__ WL,
-                                          const d2* __restrict__ Y, int K_pad, int n, int n_pad, int row0, int col0,
-                                          d2* __restrict__ H, d2* __restrict__ S, int64_t ldh) {
+template <int WR, bool CONJ>
+__device__ __forceinline__ void hs_tile3m(Smem& sm, const d2* __restrict__ L, const d2* __restrict__ R,
+                                          const d2* __restrict__ Y, int Kc, int ldL, int ldR, int row0, int col0,
+                                          int n_row, int n_col, bool upper, d2* __restrict__ H, d2* __restrict__ S,
+                                          int64_t ldh) {
   constexpr int NWV = 2 * WR;              // waves
   constexpr int MI = BM / WR / 16;         // row blocks per wave
   constexpr int NCP = BK * 2 + BK + BK;    // 1 KB copies per chunk: L rows are two copies, R and Y one
   constexpr int CPW = NCP / NWV;           // copies per wave
-  static_assert(NCP % NWV == 0, "copy map");
+  constexpr int CPL = 2 * BK / NWV;        // the first CPL copies of every wave are L rows
+  static_assert(NCP % NWV == 0 && (2 * BK) % NWV == 0, "copy map");
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;
 
-  // copy j: j < 2 BK: L row j/2, half j%2; then BK rows of lam W (R); then BK rows of Y
+  // copy j: j < 2 BK: L row j/2, half j%2; then BK rows of R; then BK rows of Y
   const d2* src0[CPW];
   int dst[CPW];  // d2 offset inside one buffer of sm (L, R, Y are consecutive members)
 #pragma unroll
   for (int i = 0; i < CPW; ++i) {
     const int j = wave + NWV * i;
-    if (j < 2 * BK) {
-      src0[i] = W + (int64_t)(j >> 1) * n_pad + row0 + (j & 1) * 64;
+    if (i < CPL) {
+      src0[i] = L + (int64_t)(j >> 1) * ldL + row0 + (j & 1) * 64;
       dst[i] = (j >> 1) * BM + (j & 1) * 64;
     } else if (j < 3 * BK) {
       const int r = j - 2 * BK;
-      src0[i] = WL + (int64_t)r * n_pad + col0;
+      src0[i] = R + (int64_t)r * ldR + col0;
       dst[i] = 2 * BK * BM + r * BN;  // after L[2][BK][BM]
     } else {
       const int r = j - 3 * BK;
-      src0[i] = Y + (int64_t)r * n_pad + col0;
+      src0[i] = Y + (int64_t)r * ldR + col0;
       dst[i] = 2 * BK * BM + 2 * BK * BN + r * BN;  // after R[2][BK][BN]
     }
   }
@@ -242,11 +249,10 @@ __device__ __forceinline__ void hs_tile3m(Smem& sm, const d2* __restrict__ W, co
   auto issue = [&](int c, int buf) {
 #pragma unroll
     for (int i = 0; i < CPW; ++i) {
-      const int j = wave + NWV * i;
       // the buffer index moves L by BK*BM and R, Y by BK*BN elements
-      const int off = dst[i] + buf * (j < 2 * BK ? BK * BM : BK * BN);
-      __builtin_amdgcn_global_load_lds((const void*)(src0[i] + (int64_t)c * BK * n_pad + lane),
-                                       (lds_ptr)(base + off), 16, 0, 0);
+      const int off = dst[i] + buf * (i < CPL ? BK * BM : BK * BN);
+      const int64_t adv = (int64_t)c * BK * (i < CPL ? ldL : ldR);
+      __builtin_amdgcn_global_load_lds((const void*)(src0[i] + adv + lane), (lds_ptr)(base + off), 16, 0, 0);
     }
   };
 
@@ -257,7 +263,7 @@ __device__ __forceinline__ void hs_tile3m(Smem& sm, const d2* __restrict__ W, co
     for (int j = 0; j < 2; ++j)
       h1[i][j] = h2[i][j] = h3[i][j] = s1[i][j] = s2[i][j] = s3[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
-  const int nchunks = K_pad / BK;
+  const int nchunks = Kc / BK;
   issue(0, 0);
   for (int c = 0; c < nchunks; ++c) {
     const int b = c & 1;
@@ -271,7 +277,7 @@ __device__ __forceinline__ void hs_tile3m(Smem& sm, const d2* __restrict__ W, co
 #pragma unroll
       for (int i = 0; i < MI; ++i) {
         const d2 a = sm.L[b][kk][wr * (BM / WR) + i * 16 + (lane & 15)];
-        ar[i] = a.x; ai[i] = a.y; ad[i] = a.x - a.y;
+        ar[i] = a.x; ai[i] = a.y; ad[i] = CONJ ? a.x - a.y : a.x + a.y;
       }
 #pragma unroll
       for (int j = 0; j < 2; ++j) {
@@ -313,11 +319,16 @@ __device__ __forceinline__ void hs_tile3m(Smem& sm, const d2* __restrict__ W, co
       for (int q = 0; q < 4; ++q) {
         const int row = row0 + wr * (BM / WR) + i * 16 + (lane >> 4) + 4 * q;
         const int col = col0 + wc * 32 + j * 16 + (lane & 15);
-        if (row < n && col < n && col >= row) {
+        if (row < n_row && col < n_col && (!upper || col >= row)) {
           const int64_t o = (int64_t)row * ldh + col;
           const double p1 = h1[i][j][q], p2 = h2[i][j][q], q1 = s1[i][j][q], q2 = s2[i][j][q];
-          H[o] = d2{p1 + p2, h3[i][j][q] - p1 + p2};
-          S[o] = d2{q1 + q2, s3[i][j][q] - q1 + q2};
+          if constexpr (CONJ) {
+            H[o] = d2{p1 + p2, h3[i][j][q] - p1 + p2};
+            S[o] = d2{q1 + q2, s3[i][j][q] - q1 + q2};
+          } else {
+            H[o] = d2{p1 - p2, h3[i][j][q] - p1 - p2};
+            S[o] = d2{q1 - q2, s3[i][j][q] - q1 - q2};
+          }
         }
       }
 }
@@ -337,7 +348,8 @@ __global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64(const d2* __restrict__ 
   tile_origin(w, nbr, gr, row0, col0);
   if (col0 >= n) return;
   if constexpr (REAL) hs_tile<WR, true>(sm, W, Y, lam, K_pad, n, n_pad, row0, col0, H, S, ldh);
-  else if constexpr (WR == 4) hs_tile3m<WR>(sm, W, WL, Y, K_pad, n, n_pad, row0, col0, (d2*)H, (d2*)S, ldh);
+  else if constexpr (WR == 4)
+    hs_tile3m<WR, true>(sm, W, WL, Y, K_pad, n_pad, n_pad, row0, col0, n, n, true, (d2*)H, (d2*)S, ldh);
   else hs_tile<WR, false>(sm, W, Y, lam, K_pad, n, n_pad, row0, col0, H, S, ldh);  // 64 x 32 per wave: plain form
 }
 
@@ -364,12 +376,30 @@ __global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64_batch(const d2* __restr
     tile_origin(t - m.tile_start, m.nbr, gr, row0, col0);
     if (col0 >= m.n) continue;  // uniform across the workgroup
     if constexpr (WR == 4)
-      hs_tile3m<WR>(sm, ws + m.w_off, ws + m.wl_off, ws + m.y_off, K_pad, m.n, m.n_pad, row0, col0, H + m.out_off,
-                    S + m.out_off, m.n);
+      hs_tile3m<WR, true>(sm, ws + m.w_off, ws + m.wl_off, ws + m.y_off, K_pad, m.n_pad, m.n_pad, row0, col0, m.n,
+                          m.n, true, H + m.out_off, S + m.out_off, m.n);
     else
       hs_tile<WR, false>(sm, ws + m.w_off, ws + m.y_off, lam, K_pad, m.n, m.n_pad, row0, col0, H + m.out_off,
                          S + m.out_off, m.n);
   }
+}
+
+// Adjoint products P_H = W gH and P_S = W gS ([K_pad][n_pad]) with the same tile
+// routine: tile rows k (128), columns G (64), contraction over G'.  The left operand
+// is W^T (rows G', k contiguous, Kt = K_pad rounded to 128, zeros past K_pad), the
+// right ones gS and gH zero-padded to n_pad x n_pad, so every copy is in bounds and
+// the pads add nothing.  Full tiles, row-major tile order dealt to the XCDs in
+// contiguous ranges (the tiles an XCD runs together share their W^T strip).
+__global__ void __launch_bounds__(512, 1) k_pgemm3m(const d2* __restrict__ WT, const d2* __restrict__ gSp,
+                                                  const d2* __restrict__ gHp, int Kt, int K_pad, int n_pad, int ncb,
+                                                  int num_wg, d2* __restrict__ PH, d2* __restrict__ PS) {
+  __shared__ Smem sm;
+  const int x = blockIdx.x % kXcds;
+  int start, len;
+  xcd_range(x, num_wg, start, len);
+  const int w = start + blockIdx.x / kXcds;
+  const int rb = w / ncb, cb = w % ncb;
+  hs_tile3m<4, false>(sm, WT, gSp, gHp, n_pad, Kt, n_pad, rb * BM, cb * BN, K_pad, n_pad, false, PH, PS, n_pad);
 }
 
 // Real-symmetric contraction on whole 128 x 128 super-tiles: Re(W^H Y) and
@@ -500,6 +530,15 @@ __global__ void __launch_bounds__(512, 1) k_hs_real(const d2* __restrict__ W, co
 int hs_tiles(int n_pad) {
   const int nbr = n_pad / BM;
   return nbr * (nbr + 1);
+}
+
+hipError_t launch_pgemm3m(const double2* WT, const double2* gSp, const double2* gHp, int Kt, int K_pad, int n_pad,
+                          double2* PH, double2* PS, hipStream_t s) {
+  if (Kt % BM || n_pad % BN) return hipErrorInvalidValue;
+  const int ncb = n_pad / BN, num_wg = ncb * (Kt / BM);
+  hipLaunchKernelGGL(k_pgemm3m, dim3(num_wg), dim3(512), 0, s, (const d2*)WT, (const d2*)gSp, (const d2*)gHp, Kt,
+                     K_pad, n_pad, ncb, num_wg, (d2*)PH, (d2*)PS);
+  return hipGetLastError();
 }
 
 hipError_t launch_hs_fp64(const double2* W, const double2* WL, const double2* Y, const double* lam, int K_pad, int n,
