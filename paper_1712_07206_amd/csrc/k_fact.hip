@@ -111,6 +111,9 @@ typedef __attribute__((address_space(3))) void* lds_ptr;
 // is the number of 4-row steps of the chunk that hold data rows, minus one.
 // XL = lam X (lam = 1 on phase rows, ||udot_l||^2 on B rows) and Yx is zero on
 // phase rows, so a phase chunk adds E^H E to the S slot and nothing to the H slot.
+// The slots sum conj(a) b in the three-product (3M) form, P1 = a_r b_r, P2 = a_i b_i,
+// P3 = (a_r - a_i)(b_r + b_i), and are turned into Re = P1 + P2, Im = P3 - P1 + P2
+// where a slot is captured (P_t) or folded: 3 MFMAs per complex multiply-add.
 __global__ void __launch_bounds__(FNT, 1) k_hs_fact(const d2* __restrict__ X, const d2* __restrict__ XL,
                                                     const d2* __restrict__ Yx, const int* __restrict__ kind,
                                                     int nch, int n, int n_pad, int nb, int num_wg, int gr,
@@ -148,10 +151,11 @@ __global__ void __launch_bounds__(FNT, 1) k_hs_fact(const d2* __restrict__ X, co
                                        (lds_ptr)(&lds[buf][(wave + 8 * i) * FM]), 16, 0, 0);
   };
 
-  d4 pR[2], pI[2], mhR[2], mhI[2], msR[2], msI[2], hR[2], hI[2], sR[2], sI[2];
+  d4 pR[2], pI[2], mh1[2], mh2[2], mh3[2], ms1[2], ms2[2], ms3[2], hR[2], hI[2], sR[2], sI[2];
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
-    pR[i] = pI[i] = mhR[i] = mhI[i] = msR[i] = msI[i] = d4{0.0, 0.0, 0.0, 0.0};
+    pR[i] = pI[i] = d4{0.0, 0.0, 0.0, 0.0};
+    mh1[i] = mh2[i] = mh3[i] = ms1[i] = ms2[i] = ms3[i] = d4{0.0, 0.0, 0.0, 0.0};
     hR[i] = hI[i] = sR[i] = sI[i] = d4{0.0, 0.0, 0.0, 0.0};
   }
 
@@ -173,50 +177,51 @@ __global__ void __launch_bounds__(FNT, 1) k_hs_fact(const d2* __restrict__ X, co
     for (int ks = 0; ks < FK / 4; ++ks) {
       if (ks >= nks) break;
       const int kk = ks * 4 + (lane >> 4);
-      double ar[2], ai[2], an[2];
+      double ar[2], ai[2], ad[2];
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
         const d2 a = L[kk * FM + wr * 32 + i * 16 + (lane & 15)];
-        ar[i] = a.x; ai[i] = a.y; an[i] = -a.y;
+        ar[i] = a.x; ai[i] = a.y; ad[i] = a.x - a.y;
       }
       const d2 yv = Yl[kk * FM + wc * 16 + (lane & 15)];
       const d2 wv = R[kk * FM + wc * 16 + (lane & 15)];
+      const double ws = wv.x + wv.y, ys = yv.x + yv.y;
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        msR[i] = MFMA(ar[i], wv.x, msR[i]);
-        msI[i] = MFMA(ar[i], wv.y, msI[i]);
-        msR[i] = MFMA(ai[i], wv.y, msR[i]);
-        msI[i] = MFMA(an[i], wv.x, msI[i]);
+        ms1[i] = MFMA(ar[i], wv.x, ms1[i]);
+        ms2[i] = MFMA(ai[i], wv.y, ms2[i]);
+        ms3[i] = MFMA(ad[i], ws, ms3[i]);
       }
       if (hslot) {
 #pragma unroll
         for (int i = 0; i < 2; ++i) {
-          mhR[i] = MFMA(ar[i], yv.x, mhR[i]);
-          mhI[i] = MFMA(ar[i], yv.y, mhI[i]);
-          mhR[i] = MFMA(ai[i], yv.y, mhR[i]);
-          mhI[i] = MFMA(an[i], yv.x, mhI[i]);
+          mh1[i] = MFMA(ar[i], yv.x, mh1[i]);
+          mh2[i] = MFMA(ai[i], yv.y, mh2[i]);
+          mh3[i] = MFMA(ad[i], ys, mh3[i]);
         }
       }
     }
     if (kd == 3) {  // the type's last phase chunk: the S slot holds P_t
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
-        pR[i] = msR[i];
-        pI[i] = msI[i];
-        msR[i] = msI[i] = d4{0.0, 0.0, 0.0, 0.0};
+        pR[i] = ms1[i] + ms2[i];
+        pI[i] = ms3[i] - ms1[i] + ms2[i];
+        ms1[i] = ms2[i] = ms3[i] = d4{0.0, 0.0, 0.0, 0.0};
       }
     } else if (kd == 2) {  // the type's last W0 chunk: fold M * P into H and S
 #pragma unroll
       for (int i = 0; i < 2; ++i) {
+        const d4 mhR = mh1[i] + mh2[i], mhI = mh3[i] - mh1[i] + mh2[i];
+        const d4 msR = ms1[i] + ms2[i], msI = ms3[i] - ms1[i] + ms2[i];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const double p_r = pR[i][q], p_i = pI[i][q];
-          hR[i][q] += mhR[i][q] * p_r - mhI[i][q] * p_i;
-          hI[i][q] += mhR[i][q] * p_i + mhI[i][q] * p_r;
-          sR[i][q] += msR[i][q] * p_r - msI[i][q] * p_i;
-          sI[i][q] += msR[i][q] * p_i + msI[i][q] * p_r;
+          hR[i][q] += mhR[q] * p_r - mhI[q] * p_i;
+          hI[i][q] += mhR[q] * p_i + mhI[q] * p_r;
+          sR[i][q] += msR[q] * p_r - msI[q] * p_i;
+          sI[i][q] += msR[q] * p_i + msI[q] * p_r;
         }
-        mhR[i] = mhI[i] = msR[i] = msI[i] = d4{0.0, 0.0, 0.0, 0.0};
+        mh1[i] = mh2[i] = mh3[i] = ms1[i] = ms2[i] = ms3[i] = d4{0.0, 0.0, 0.0, 0.0};
       }
     }
   }
