@@ -13,6 +13,14 @@ namespace hsb {
 constexpr int kTileN = 128;  // basis sizes are padded to a multiple of this
 constexpr int kTileK = 16;   // the stacked contraction index is padded to a multiple of this
 
+// Rows of the stacked operands: K plus at least kTileK - 1 zero rows, so the per-atom T
+// products, which read an atom's rows in kTileK-row chunks, stay inside the array for
+// the last atom.
+inline int stacked_pad(int K) { return (K + 2 * kTileK - 2) / kTileK * kTileK; }
+// Shape of the zero-padded transposed T of one type (2N_L = M): [tprod_kc(M)][tprod_mp(M)].
+inline int tprod_kc(int M) { return (M + 15) / 16 * 16; }
+inline int tprod_mp(int M) { return (M + 127) / 128 * 128; }
+
 inline int64_t round_up(int64_t v, int64_t m) { return (v + m - 1) / m * m; }
 
 // Cell description passed by value to the coefficient kernels.
@@ -45,6 +53,7 @@ struct Layout {
   size_t WL = 0;  // lam W (the FP64 contraction's S operand), forward in FP64 only
   size_t PH = 0, PS = 0, partT = 0, partTau = 0;  // backward only
   size_t WT = 0, gHp = 0, gSp = 0;                // backward: operands of the 3M products
+  size_t TT = 0;                                  // T^T per type, zero-padded (T products)
   int Kt = 0;                                     // backward: K_pad rounded up to 128
   int K_pad2 = 0;                                  // split only: stacked rows padded to 32
   size_t mx = 0, scale = 0, slL = 0, slS = 0, slY = 0;  // split only
@@ -91,8 +100,13 @@ hipError_t launch_pack_rows(const double2* src, int ng, int rows, double2* dst, 
 // rows [row0, row1) of a [*][ld] complex array set to zero.
 hipError_t launch_zero_rows(double2* a, int64_t ld, int row0, int row1, hipStream_t s);
 // Y_atom = T_type(atom) W_atom for every atom (rows of W/Y per atom: 2N_L).
-hipError_t launch_tprod(const CellArgs& c, const double2* T, const double2* W, double2* Y, int n_pad,
+hipError_t launch_tprod(const CellArgs& c, const double2* TT, const double2* W, double2* Y, int n_pad,
                         hipStream_t s);
+// TT[t] = T[t]^T zero-padded to [tprod_kc(M)][tprod_mp(M)] for each of n_types types (M = 2 N_L).
+hipError_t launch_tpad(const double2* T, int n_types, int M, double2* TT, hipStream_t s);
+// Y_a = T_t(a) W_a for every atom of c from TT, in the 3M form (k_hs.hip).
+hipError_t launch_tprod3m(const CellArgs& c, const double2* TT, const double2* W, double2* Y, int n_pad,
+                          hipStream_t s);
 // Upper triangles of H = W^H Y and S = W^H WL over K_pad rows (WL = diag(lam) W, prepared).
 // gr: tile order (0 row-major, > 0 super-rows taken in groups of gr).
 // waves: 4 (64 x 32 per wave) or 8 (32 x 32 per wave).

@@ -89,7 +89,7 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
   L.n = ng;
   L.n_pad = (int)round_up(ng, kTileN);
   L.K = 2 * h.n_atoms * h.n_l;
-  L.K_pad = (int)round_up(L.K, kTileK);
+  L.K_pad = stacked_pad(L.K);
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -126,10 +126,12 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
     L.X = take((size_t)L.R_f * np * sizeof(double2));
     L.XL = take((size_t)L.R_f * np * sizeof(double2));
     L.Yx = take((size_t)L.R_f * np * sizeof(double2));
+    L.TT = take((size_t)h.n_types * tprod_kc(2 * h.n_l) * tprod_mp(2 * h.n_l) * sizeof(double2));
     L.end = off;
     return L;
   }
   if (mode != HSB_MODE_COEFFICIENTS) {
+    L.TT = take((size_t)h.n_types * tprod_kc(2 * h.n_l) * tprod_mp(2 * h.n_l) * sizeof(double2));
     L.lam = take((size_t)L.K_pad * sizeof(double));
     L.W = take((size_t)L.K_pad * np * sizeof(double2));
     L.Y = take((size_t)L.K_pad * np * sizeof(double2));
@@ -230,9 +232,11 @@ int enqueue_operands(hsbuild_t h, const Layout& L, const double k_frac[3], const
   if (rc) return rc;
   double2* W = (double2*)(ws + L.W);
   double2* Y = (double2*)(ws + L.Y);
-  if (!shared) {
+  if (!shared) {  // (the batch prepares lam and T^T once for all k-points)
     rc = launched(h, launch_lambda(c, (const TypeConsts*)(ws + L.consts), L.K_pad, (double*)(ws + L.lam), s),
                   "k_lambda");
+    if (!rc) rc = launched(h, launch_tpad((const double2*)T, h->n_types, 2 * h->n_l, (double2*)(ws + L.TT), s),
+                           "k_tpad");
     if (rc) return rc;
   }
   rc = launched(h, launch_assemble(c, L.n_pad, (const double2*)(ws + L.ang), (const double2*)(ws + L.ab),
@@ -244,7 +248,7 @@ int enqueue_operands(hsbuild_t h, const Layout& L, const double k_frac[3], const
   rc = launched(h, launch_zero_rows(Y, L.n_pad, L.K, L.K_pad, s), "k_zero_rows");
   if (rc) return rc;
   mark(h, 1, s);
-  rc = launched(h, launch_tprod(c, (const double2*)T, W, Y, L.n_pad, s), "k_tprod");
+  rc = launched(h, launch_tprod(c, (const double2*)(ws + L.TT), W, Y, L.n_pad, s), "k_tprod3m");
   if (!rc && L.WL)  // the FP64 contraction's S operand, lam W
     rc = launched(h, launch_scale_rows(W, (const double*)(ws + L.lam), L.K_pad, L.n_pad, (double2*)(ws + L.WL), s),
                   "k_scale_rows");
@@ -287,7 +291,7 @@ constexpr int kBranches = 4;
 
 struct BatchLayout {
   int K = 0, K_pad = 0, max_n_pad = 0;
-  size_t consts = 0, lam = 0, meta = 0, end = 0;
+  size_t consts = 0, lam = 0, meta = 0, TT = 0, end = 0;
   size_t kv[kBranches] = {}, ang[kBranches] = {}, ab[kBranches] = {};
   std::vector<size_t> W, WL, Y;
   std::vector<int> n_pad;
@@ -296,7 +300,7 @@ struct BatchLayout {
 BatchLayout make_batch_layout(const hsbuild_s& h, int n_k, const int32_t* ng) {
   BatchLayout B;
   B.K = 2 * h.n_atoms * h.n_l;
-  B.K_pad = (int)round_up(B.K, kTileK);
+  B.K_pad = stacked_pad(B.K);
   for (int k = 0; k < n_k; ++k) {
     B.n_pad.push_back((int)round_up(ng[k], kTileN));
     B.max_n_pad = std::max(B.max_n_pad, B.n_pad.back());
@@ -310,6 +314,7 @@ BatchLayout make_batch_layout(const hsbuild_s& h, int n_k, const int32_t* ng) {
   const size_t np = (size_t)B.max_n_pad;
   B.consts = take(sizeof(TypeConsts));
   B.lam = take((size_t)B.K_pad * sizeof(double));
+  B.TT = take((size_t)h.n_types * tprod_kc(2 * h.n_l) * tprod_mp(2 * h.n_l) * sizeof(double2));
   for (int b = 0; b < kBranches; ++b) {
     B.kv[b] = take(np * 4 * sizeof(double));
     B.ang[b] = take((size_t)h.n_l * np * sizeof(double2));
@@ -635,6 +640,8 @@ int hsbuild_forward_factored(hsbuild_t h, const double k_frac[3], int32_t ng, co
     base = rw + Mp;
   }
   mark(h, 1, s);
+  rc = launched(h, launch_tpad((const double2*)T, h->n_types, M, (double2*)(w + L.TT), s), "k_tpad");
+  if (rc) return rc;
   base = 0;
   for (int t = 0; t < h->n_types; ++t) {
     const int nt = c.type_start[t + 1] - c.type_start[t];
@@ -645,9 +652,9 @@ int hsbuild_forward_factored(hsbuild_t h, const double k_frac[3], int32_t ng, co
     c1.n_atoms = 1;
     c1.type_start[0] = 0;
     c1.type_start[1] = 1;
-    rc = launched(h, launch_tprod(c1, (const double2*)T + (int64_t)t * M * M, X + (int64_t)rw * np,
-                                  Yx + (int64_t)rw * np, L.n_pad, s),
-                  "k_tprod");
+    rc = launched(h, launch_tprod(c1, (const double2*)(w + L.TT) + (int64_t)t * tprod_kc(M) * tprod_mp(M),
+                                  X + (int64_t)rw * np, Yx + (int64_t)rw * np, L.n_pad, s),
+                  "k_tprod3m");
     if (rc) return rc;
     base = rw + Mp;
   }
@@ -701,7 +708,7 @@ int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const 
   if ((rc = check_device(h))) return rc;
   Layout Lr = L;  // the stacked rows of the representatives only
   Lr.K = 2 * n_rep * h->n_l;
-  Lr.K_pad = (int)round_up(Lr.K, kTileK);
+  Lr.K_pad = stacked_pad(Lr.K);
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
   // upload the representatives from pinned memory (after the previous upload has been consumed)
@@ -837,7 +844,9 @@ int hsbuild_forward_coefficients(hsbuild_t h, int32_t ng, const void* coef, cons
   }
   if ((rc = launched(h, launch_zero_rows(W, L.n_pad, L.K, L.K_pad, s), "k_zero_rows"))) return rc;
   if ((rc = launched(h, launch_zero_rows(Y, L.n_pad, L.K, L.K_pad, s), "k_zero_rows"))) return rc;
-  if ((rc = launched(h, launch_tprod(c, (const double2*)T, W, Y, L.n_pad, s), "k_tprod"))) return rc;
+  if ((rc = launched(h, launch_tpad((const double2*)T, h->n_types, 2 * h->n_l, (double2*)(w + L.TT), s), "k_tpad")))
+    return rc;
+  if ((rc = launched(h, launch_tprod(c, (const double2*)(w + L.TT), W, Y, L.n_pad, s), "k_tprod3m"))) return rc;
   if (h->precision == HSB_FP64) {
     double2* WL = (double2*)(w + L.WL);
     if ((rc = launched(h, launch_scale_rows(W, (const double*)(w + L.lam), L.K_pad, L.n_pad, WL, s), "k_scale_rows")))
@@ -969,6 +978,7 @@ int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t*
     // shared inputs once: type constants and lam; then the k-points' operands in parallel branches
     hipError_t ef = hipMemcpyAsync(w + B.consts, h->consts, sizeof(TypeConsts), hipMemcpyHostToDevice, cs);
     if (ef == hipSuccess) ef = launch_lambda(h->cell, (const TypeConsts*)(w + B.consts), B.K_pad, (double*)(w + B.lam), cs);
+    if (ef == hipSuccess) ef = launch_tpad((const double2*)T, h->n_types, 2 * h->n_l, (double2*)(w + B.TT), cs);
     if (ef == hipSuccess) ef = hipEventRecord(h->fork, cs);
     for (int b = 0; b < kBranches && ef == hipSuccess; ++b) ef = hipStreamWaitEvent(h->aux[b], h->fork, 0);
     if (ef != hipSuccess) rc = launched(h, ef, "batch graph fork");
@@ -983,6 +993,7 @@ int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t*
       L.K_pad = B.K_pad;
       L.consts = B.consts;
       L.lam = B.lam;
+      L.TT = B.TT;
       L.kv = B.kv[b];
       L.ang = B.ang[b];
       L.ab = B.ab[b];

@@ -402,6 +402,26 @@ __global__ void __launch_bounds__(512, 1) k_pgemm3m(const d2* __restrict__ WT, c
   hs_tile3m<4, false>(sm, WT, gSp, gHp, n_pad, Kt, n_pad, rb * BM, cb * BN, K_pad, n_pad, false, PH, PS, n_pad);
 }
 
+// Per-atom T products Y_a = T_t W_a on the same tile routine (plain products): tile
+// rows r of Y_a (128), the routine's two outputs are two adjacent 64-column halves of
+// a 128-column block (both share the staged T), contraction over the atom's rows k in
+// 16-row chunks.  TT: per type T^T zero-padded to [Kc][MP] (Kc = round16(2N_L),
+// MP = round128(2N_L)); rows of a chunk past 2N_L read the next atom's rows of W (or
+// the zero rows past K, at least 15 of them) against zero rows of TT.
+__global__ void __launch_bounds__(512, 1) k_tprod3m(CellArgs c, const d2* __restrict__ TT, const d2* __restrict__ W,
+                                                  d2* __restrict__ Y, int n_pad, int Kc, int MP) {
+  __shared__ Smem sm;
+  const int atom = blockIdx.z;
+  int t = 0;
+  while (t + 1 < c.n_types && atom >= c.type_start[t + 1]) ++t;
+  const int M = 2 * c.n_l;
+  const d2* Wa = W + (int64_t)atom * M * n_pad;
+  d2* Ya = Y + (int64_t)atom * M * n_pad;
+  const int row0 = blockIdx.y * BM, col0 = blockIdx.x * 2 * BN;
+  hs_tile3m<4, false>(sm, TT + (int64_t)t * Kc * MP, Wa, Wa + BN, Kc, MP, n_pad, row0, col0, M, n_pad, false, Ya + BN,
+                      Ya, n_pad);
+}
+
 // Real-symmetric contraction on whole 128 x 128 super-tiles: Re(W^H Y) and
 // Re(W^H lam W) keep two of the four real MFMAs per complex multiply-add, so
 // with the 128 x 64 tile above a wave would read twice the LDS per MFMA.
@@ -530,6 +550,16 @@ __global__ void __launch_bounds__(512, 1) k_hs_real(const d2* __restrict__ W, co
 int hs_tiles(int n_pad) {
   const int nbr = n_pad / BM;
   return nbr * (nbr + 1);
+}
+
+hipError_t launch_tprod3m(const CellArgs& c, const double2* TT, const double2* W, double2* Y, int n_pad,
+                          hipStream_t s) {
+  const int M = 2 * c.n_l;
+  if (n_pad % (2 * BN)) return hipErrorInvalidValue;
+  dim3 grid(n_pad / (2 * BN), tprod_mp(M) / BM, c.n_atoms);
+  hipLaunchKernelGGL(k_tprod3m, grid, dim3(512), 0, s, c, (const d2*)TT, (const d2*)W, (d2*)Y, n_pad, tprod_kc(M),
+                     tprod_mp(M));
+  return hipGetLastError();
 }
 
 hipError_t launch_pgemm3m(const double2* WT, const double2* gSp, const double2* gHp, int Kt, int K_pad, int n_pad,
