@@ -116,8 +116,8 @@ hipError_t launch_hs_fp64(const double2* W, const double2* WL, const double2* Y,
                           int n_pad, int gr, int waves, double2* H, double2* S, int64_t ldh, hipStream_t s);
 
 // The same contraction keeping only the real parts, Re(W^H Y) and Re(W^H lam W), as doubles.
-hipError_t launch_hs_fp64_real(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
-                               int gr, int waves, double* H, double* S, int64_t ldh, hipStream_t s);
+hipError_t launch_hs_fp64_real(const double2* W, const double2* WL, const double2* Y, const double* lam, int K_pad,
+                               int n, int n_pad, int gr, int waves, double* H, double* S, int64_t ldh, hipStream_t s);
 
 // Number of 128 x 64 tiles the contraction covers for a padded basis size.
 int hs_tiles(int n_pad);

@@ -136,7 +136,8 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
     L.W = take((size_t)L.K_pad * np * sizeof(double2));
     L.Y = take((size_t)L.K_pad * np * sizeof(double2));
   }
-  if (mode == HSB_MODE_FORWARD && h.precision == HSB_FP64) L.WL = take((size_t)L.K_pad * np * sizeof(double2));
+  if ((mode == HSB_MODE_FORWARD && h.precision == HSB_FP64) || mode == HSB_MODE_REAL)
+    L.WL = take((size_t)L.K_pad * np * sizeof(double2));
   if (mode == HSB_MODE_FORWARD && h.precision != HSB_FP64) {
     L.K_pad2 = (int)round_up(L.K, 32);
     const size_t planes = (size_t)2 * h.n_slices * np * L.K_pad2 * 2;  // bytes per sliced operand
@@ -709,6 +710,7 @@ int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const 
   Layout Lr = L;  // the stacked rows of the representatives only
   Lr.K = 2 * n_rep * h->n_l;
   Lr.K_pad = stacked_pad(Lr.K);
+  Lr.WL = 0;  // lam W is formed below, after the pair weights are folded into lam
   hipStream_t s = (hipStream_t)stream;
   char* w = (char*)ws;
   // upload the representatives from pinned memory (after the previous upload has been consumed)
@@ -744,8 +746,10 @@ int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const 
                                     tau_rep, wrow, lam, s),
                 "k_rep_setup");
   if (!rc) rc = launched(h, launch_scale_rows(Y, wrow, Lr.K_pad, L.n_pad, Y, s), "k_scale_rows");
+  double2* WL = (double2*)(w + L.WL);  // S's right operand, lam W (lam with the pair weights)
+  if (!rc) rc = launched(h, launch_scale_rows((const double2*)(w + L.W), lam, Lr.K_pad, L.n_pad, WL, s), "k_scale_rows");
   if (!rc)
-    rc = launched(h, launch_hs_fp64_real((const double2*)(w + L.W), Y, lam, Lr.K_pad, ng, L.n_pad, h->tile_group,
+    rc = launched(h, launch_hs_fp64_real((const double2*)(w + L.W), WL, Y, lam, Lr.K_pad, ng, L.n_pad, h->tile_group,
                                          h->hs_waves, H, S, ng, s),
                   "k_hs_fp64 (real)");
   mark(h, 3, s);

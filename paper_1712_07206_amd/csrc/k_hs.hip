@@ -425,9 +425,9 @@ __global__ void __launch_bounds__(512, 1) k_tprod3m(CellArgs c, const d2* __rest
 // Real-symmetric contraction on whole 128 x 128 super-tiles: Re(W^H Y) and
 // Re(W^H lam W) keep two of the four real MFMAs per complex multiply-add, so
 // with the 128 x 64 tile above a wave would read twice the LDS per MFMA.
-// Here the tile is 128 x 128 and 8 rows are staged per chunk: 8 waves of
-// 32 x 64 (2 x 4 MFMA blocks), the same MFMA work and LDS reads per chunk
-// as the complex kernel.
+// Here the tile is 128 x 128 and 8 rows are staged per chunk, copied straight
+// into double-buffered LDS: 8 waves of 32 x 64 (2 x 4 MFMA blocks), the same
+// MFMA work and LDS reads per chunk as the complex kernel.
 constexpr int RN = 128, RK = 8;
 
 struct RSmem {
@@ -436,9 +436,9 @@ struct RSmem {
   d2 Y[2][RK][RN];
 };
 
-__global__ void __launch_bounds__(512, 1) k_hs_real(const d2* __restrict__ W, const d2* __restrict__ Y,
-                                                    const double* __restrict__ lam, int K_pad, int n, int n_pad,
-                                                    int nbr, int num_wg, int gr, double* __restrict__ H,
+__global__ void __launch_bounds__(512, 1) k_hs_real(const d2* __restrict__ W, const d2* __restrict__ WL,
+                                                    const d2* __restrict__ Y, int K_pad, int n, int n_pad, int nbr,
+                                                    int num_wg, int gr, double* __restrict__ H,
                                                     double* __restrict__ S, int64_t ldh) {
   __shared__ RSmem sm;
   const int x = blockIdx.x % kXcds;
@@ -450,32 +450,38 @@ __global__ void __launch_bounds__(512, 1) k_hs_real(const d2* __restrict__ W, co
   else tri_decode(w, nbr, bi, bj);
   const int row0 = bi * BM, col0 = bj * RN;
   if (col0 >= n) return;
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int wr = wave >> 1, wc = wave & 1;  // rows wr*32, columns wc*64
 
-  // staging: 8 x 128 per array, two elements per thread (row e/128, column e%128)
-  d2 pl[2], pr[2], py[2];
-  double pm[2];
-#define HR_GLOAD(kc)                                                       \
-  do {                                                                     \
-    _Pragma("unroll") for (int i = 0; i < 2; ++i) {                        \
-      const int e = tid + 512 * i;                                         \
-      const int64_t r = (int64_t)((kc) + (e >> 7)) * n_pad;                \
-      pl[i] = W[r + row0 + (e & 127)];                                     \
-      pr[i] = W[r + col0 + (e & 127)];                                     \
-      py[i] = Y[r + col0 + (e & 127)];                                     \
-      pm[i] = lam[(kc) + (e >> 7)];                                        \
-    }                                                                      \
-  } while (0)
-#define HR_LSTORE(b)                                   \
-  do {                                                 \
-    _Pragma("unroll") for (int i = 0; i < 2; ++i) {    \
-      const int e = tid + 512 * i;                     \
-      sm.L[b][e >> 7][e & 127] = pl[i];                \
-      sm.R[b][e >> 7][e & 127] = pm[i] * pr[i];        \
-      sm.Y[b][e >> 7][e & 127] = py[i];                \
-    }                                                  \
-  } while (0)
+  // Staging straight into LDS: 48 copies of 1 KB (64 elements) per 8-row chunk, wave w
+  // takes j = w + 8 i: copies 0..15 are W at the tile rows, 16..31 lam W (prepared in
+  // HBM) and 32..47 Y at the tile columns; copy j covers row (j % 16) / 2, half j % 2.
+  const d2* src0[6];
+  int dst[6];  // d2 offset in buffer 0 of sm (L, R, Y are consecutive members)
+#pragma unroll
+  for (int i = 0; i < 6; ++i) {
+    const int j = wave + 8 * i, r = (j & 15) >> 1, half = j & 1;
+    if (i < 2) {
+      src0[i] = W + (int64_t)r * n_pad + row0 + half * 64;
+      dst[i] = r * BM + half * 64;
+    } else if (i < 4) {
+      src0[i] = WL + (int64_t)r * n_pad + col0 + half * 64;
+      dst[i] = 2 * RK * BM + r * RN + half * 64;
+    } else {
+      src0[i] = Y + (int64_t)r * n_pad + col0 + half * 64;
+      dst[i] = 2 * RK * BM + 2 * RK * RN + r * RN + half * 64;
+    }
+  }
+  d2* base = &sm.L[0][0][0];
+  auto issue = [&](int c, int buf) {
+#pragma unroll
+    for (int i = 0; i < 6; ++i) {
+      const int off = dst[i] + buf * (i < 2 ? RK * BM : RK * RN);
+      __builtin_amdgcn_global_load_lds((const void*)(src0[i] + (int64_t)c * RK * n_pad + lane),
+                                       (lds_ptr)(base + off), 16, 0, 0);
+    }
+  };
 
   d4 hr[2][4], sr[2][4];
 #pragma unroll
@@ -484,15 +490,14 @@ __global__ void __launch_bounds__(512, 1) k_hs_real(const d2* __restrict__ W, co
     for (int j = 0; j < 4; ++j) hr[i][j] = sr[i][j] = d4{0.0, 0.0, 0.0, 0.0};
 
   const int nchunks = K_pad / RK;
-  HR_GLOAD(0);
-  HR_LSTORE(0);
-  __syncthreads();
+  issue(0, 0);
   for (int c = 0; c < nchunks; ++c) {
     const int b = c & 1;
-    if (c + 1 < nchunks) HR_GLOAD((c + 1) * RK);
+    __builtin_amdgcn_s_waitcnt(0);  // this wave's copies of chunk c have landed
+    __syncthreads();                // everyone's have, and buffer b^1 is free
+    if (c + 1 < nchunks) issue(c + 1, b ^ 1);
 #pragma unroll
     for (int ks = 0; ks < RK / 4; ++ks) {
-      if (ks == RK / 8 && c + 1 < nchunks) HR_LSTORE(b ^ 1);  // as in hs_tile
       const int kk = ks * 4 + (lane >> 4);
       double ar[2], ai[2], yre[4], yim[4], wre[4], wim[4];
 #pragma unroll
@@ -523,10 +528,7 @@ __global__ void __launch_bounds__(512, 1) k_hs_real(const d2* __restrict__ W, co
 #pragma unroll
         for (int j = 0; j < 4; ++j) sr[i][j] = MFMA(ai[i], wim[j], sr[i][j]);
     }
-    __syncthreads();
   }
-#undef HR_GLOAD
-#undef HR_LSTORE
 
   // D layout of the 16x16 f64 MFMA: lane l, element q -> row l/16 + 4q, column l%16
 #pragma unroll
@@ -585,13 +587,14 @@ hipError_t launch_hs_fp64(const double2* W, const double2* WL, const double2* Y,
   return hipGetLastError();
 }
 
-hipError_t launch_hs_fp64_real(const double2* W, const double2* Y, const double* lam, int K_pad, int n, int n_pad,
-                               int gr, int waves, double* H, double* S, int64_t ldh, hipStream_t s) {
+hipError_t launch_hs_fp64_real(const double2* W, const double2* WL, const double2* Y, const double* lam, int K_pad,
+                               int n, int n_pad, int gr, int waves, double* H, double* S, int64_t ldh, hipStream_t s) {
   const int nbr = n_pad / BM;
   const int num_wg = hs_tiles(n_pad);
+  if (K_pad % RK) return hipErrorInvalidValue;
   if (waves == 8)  // whole 128 x 128 super-tiles
-    hipLaunchKernelGGL(k_hs_real, dim3(num_wg / 2), dim3(512), 0, s, (const d2*)W, (const d2*)Y, lam, K_pad, n,
-                       n_pad, nbr, num_wg / 2, gr, H, S, ldh);
+    hipLaunchKernelGGL(k_hs_real, dim3(num_wg / 2), dim3(512), 0, s, (const d2*)W, (const d2*)WL, (const d2*)Y, K_pad,
+                       n, n_pad, nbr, num_wg / 2, gr, H, S, ldh);
   else
     hipLaunchKernelGGL((k_hs_fp64<2, true>), dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)nullptr,
                        (const d2*)Y, lam, K_pad, n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
