@@ -408,7 +408,9 @@ def adjoint_leg(args) -> dict:
     del gH, gS, gT, gtau
     torch.cuda.empty_cache()
     return {"workload": case["name"], "n_g": n, "ms_per_backward": round(ms, 4), "flops": flops,
-            "fp64_tflops": round(flops / (ms * 1e-3) / 1e12, 4)}
+            "fp64_equiv_tflops": round(flops / (ms * 1e-3) / 1e12, 4),
+            "note": "conventional flop count; the products P_H, P_S run in the 3M form (6 flops per complex "
+                    "multiply-add)"}
 
 
 def oracle_table() -> list:
