@@ -9,17 +9,20 @@
 // formed per atom, one herkx over the full stacked width gives the same H in
 // 8 N_A N_L N_G^2, and S shares its left operand W.
 //
-// Complex FP64 on v_mfma_f64_16x16x4f64 (four real MFMAs per complex MAC):
-//   Re += Wr^T Yr + Wi^T Yi,  Im += Wr^T Yi - Wi^T Yr.
-// Workgroup: output tile 128 (G') x 64 (G) for both H and S, either 4 waves
-// of 64 x 32 (4 x 2 MFMA blocks per matrix, accumulators in AGPRs, one wave per
-// SIMD) or 8 waves of 32 x 32 (two waves per SIMD, which hides the chunk
-// barriers); both issue the same MFMA sequence per output block, so they give
-// bitwise the same result.  K is staged 16 rows at a time through
-// double-buffered LDS with a register prefetch of the next chunk.  Only tiles
-// that touch the upper triangle are computed; they are numbered row-major
-// over 128 x 128 super-tiles and the numbering is dealt to the eight XCDs in
-// contiguous ranges so tiles sharing a row strip share an L2.
+// Complex FP64 on v_mfma_f64_16x16x4f64.  Workgroup: output tile 128 (G') x 64
+// (G) for both H and S.  Two variants:
+//   8 waves of 32 x 32 (two waves per SIMD, which hides the chunk barriers):
+//     three real MFMAs per complex multiply-add (the 3M form, hs_tile3m below),
+//     operand strips copied straight into double-buffered LDS;
+//   4 waves of 64 x 32 (accumulators in AGPRs, one wave per SIMD): four real
+//     MFMAs per complex multiply-add, Re += Wr^T Yr + Wi^T Yi,
+//     Im += Wr^T Yi - Wi^T Yr, with a register prefetch of the next chunk.
+// The two agree to FP64 rounding.  K is staged 16 rows at a time.  Only tiles
+// that touch the upper triangle are computed; they are numbered over 128 x 128
+// super-tiles (grouped order, tiles.h) and the numbering is dealt to the eight
+// XCDs in contiguous ranges so tiles sharing a row strip share an L2.  The 3M
+// tile routine also serves the per-atom T products (k_tprod3m) and the
+// adjoint's products (k_pgemm3m), with the plain complex product.
 //
 // k_hs_fp64 computes one k-point, one workgroup per tile.  k_hs_fp64_batch is
 // the persistent form for many k-points: a fixed grid (one workgroup per CU)
