@@ -1,8 +1,10 @@
 """Autotuner for the performance options of the H/S build.
 
-The options change only the order in which work is dealt to the compute
-units, never the arithmetic, so every candidate gives bitwise the same H and
-S.  `tune` times the candidates on the caller's inputs with HIP events and
+The tile order changes only the order in which work is dealt to the compute
+units, never the arithmetic (bitwise the same H and S); the wave count of the
+FP64 contraction also selects its complex form (three real products per
+complex one with 8 waves, four with 4), whose results agree to FP64 rounding.
+`tune` times the candidates on the caller's inputs with HIP events and
 returns the fastest; `cached_options` / `apply` keep the choice in a JSON
 cache keyed by device, precision and problem size so later runs reuse it.
 """
