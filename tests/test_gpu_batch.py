@@ -132,7 +132,9 @@ def test_batch_error_paths():
 
 def test_batch_autotuner_picks_a_candidate_and_keeps_results():
     """tune_batch times the candidates on the batch call itself and leaves the
-    fastest set; every candidate gives bitwise the same blocks."""
+    fastest set.  Candidates with the default 8 waves give bitwise the same
+    blocks; the 4-wave form (four real products per complex one) agrees to
+    FP64 rounding."""
     from paper_1712_07206_amd import _native as N
     from paper_1712_07206_amd import autotune
     from paper_1712_07206_amd.hsbuild import HSBuilder
@@ -155,4 +157,7 @@ def test_batch_autotuner_picks_a_candidate_and_keeps_results():
     H1, S1, off1 = b.batch(case["k_frac"], gl, tau, T)
     torch.cuda.synchronize()
     got = upper_blocks(H1, off1) + upper_blocks(S1, off1)
-    assert all(torch.equal(a, c) for a, c in zip(ref, got))
+    if res["waves"] == 8:
+        assert all(torch.equal(a, c) for a, c in zip(ref, got))
+    else:
+        assert all(float(torch.linalg.norm(c - a) / torch.linalg.norm(a)) <= 1e-12 for a, c in zip(ref, got))
