@@ -637,6 +637,13 @@ def main() -> int:
                      "complex_form": "3M" if options["waves"] == 8 else "4M",
                      "fp64_equiv_tflops": round(hs_equiv, 4)},
         "split_speedup": None,
+        "paper_context": {
+            "note": "the paper's figures on its own hardware and inputs: context, not a target",
+            "abstract": "over 70% of peak on CPU+coprocessor nodes; 5x over CPU-only on a JURECA node",
+            "sec6_rwth_gpu": "about 2 of 3 TFLOP/s (66%); TiO2 at K_max 4.0 about 2.5 TFLOP/s (83%)",
+            "sec6_jureca_gpu": "4 GK210 + 2 Haswell, 6.7 TFLOP/s peak: up to 3.2 TFLOP/s AuAg (47%), 4.3 TFLOP/s "
+                               "TiO2 (61%), whole H/S build",
+        },
     }
     if not args.no_factored:
         result["factored"] = factored_leg(args, case, g, tau, T, H, S, ms_step)
