@@ -161,3 +161,30 @@ def test_batch_autotuner_picks_a_candidate_and_keeps_results():
         assert all(torch.equal(a, c) for a, c in zip(ref, got))
     else:
         assert all(float(torch.linalg.norm(c - a) / torch.linalg.norm(a)) <= 1e-12 for a, c in zip(ref, got))
+
+
+def test_batch_small_uneven_bases_against_oracle():
+    """k-points with 37, 128, 129 and 300 basis functions (bases truncated in
+    their |k+G| order): one to three tile rows per k-point, ragged edges, in one
+    persistent launch; each block against the oracle and bitwise against the
+    single-k forward."""
+    from paper_1712_07206_amd.hsbuild import HSBuilder
+    case = make_batch_case(3, n_k=4)
+    sizes = [37, 128, 129, 300]
+    case["g"] = [np.ascontiguousarray(case["g"][k][:sizes[k]]) for k in range(4)]
+    case["n_g"] = np.array(sizes, dtype=np.int32)
+    b, tau, T, gl = _setup(case)
+    H, S, off = b.batch(case["k_frac"], gl, tau, T)
+    torch.cuda.synchronize()
+    Hc, Sc = H.cpu().numpy(), S.cpu().numpy()
+    for k, n in enumerate(sizes):
+        sub = sub_case(case, k)
+        Hr, Sr = o.hs(sub)
+        hb, sb = _block(Hc, off[k], n), _block(Sc, off[k], n)
+        eh = np.linalg.norm(_full(hb) - Hr) / np.linalg.norm(Hr)
+        es = np.linalg.norm(_full(sb) - Sr) / np.linalg.norm(Sr)
+        print("k %d N_G %d: H %.3e S %.3e" % (k, n, eh, es))
+        assert eh <= 1e-12 and es <= 1e-12, (k, eh, es)
+        h1, s1 = b.forward(case["k_frac"][k], gl[k], tau, T)
+        iu = np.triu_indices(n)
+        assert np.array_equal(hb[iu], h1.cpu().numpy()[iu]) and np.array_equal(sb[iu], s1.cpu().numpy()[iu]), k
