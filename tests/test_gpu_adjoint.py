@@ -39,8 +39,11 @@ def _loss(b, case, g, tau, T, Wm, Vm):
     return float((torch.sum(Wm * H.transpose(0, 1)).real + torch.sum(Vm * S.transpose(0, 1)).real).item())
 
 
-def test_backward_matches_oracle_gradient():
-    case = make_case(4, n_g=800)
+@pytest.mark.parametrize("n_g", [37, 129, 800])
+def test_backward_matches_oracle_gradient(n_g):
+    """One, two and seven 128-wide blocks of G (the padded W^T and gradients of
+    the adjoint products are ragged at the first two)."""
+    case = make_case(4, n_g=n_g)
     b, g, tau, T, Wm, Vm = _setup(case)
     gT, gtau = b.backward(case["k_frac"], g, tau, T, Wm, Vm)
     torch.cuda.synchronize()
