@@ -52,7 +52,7 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("prec_name", ["bf16", "fp16"])
-@pytest.mark.parametrize("idx,n_g", [(0, None), (1, 1000), (2, 3000)])
+@pytest.mark.parametrize("idx,n_g", [(0, None), (1, 7), (1, 129), (1, 1000), (2, 3000)])
 def test_split_matches_oracle(prec_name, idx, n_g):
     from paper_1712_07206_amd import HSB_SPLIT_BF16, HSB_SPLIT_FP16
     prec = HSB_SPLIT_BF16 if prec_name == "bf16" else HSB_SPLIT_FP16
