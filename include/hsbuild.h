@@ -64,8 +64,11 @@ enum {
   HSB_ERR_NUMERIC = -6      /* singular radial Wronskian at create */
 };
 
-/* Contraction precision. */
-enum { HSB_FP64 = 0, HSB_SPLIT_FP16 = 1, HSB_SPLIT_BF16 = 2 };
+/* Contraction precision.  The split forms cut every operand column, scaled by a
+ * power of two, into n_slices integer slices and run the slice products on the
+ * matrix cores: 8-bit slices as BF16 or FP16 values with FP32 sums, or 7-bit
+ * slices as signed bytes with exact int32 sums (HSB_SPLIT_INT8). */
+enum { HSB_FP64 = 0, HSB_SPLIT_FP16 = 1, HSB_SPLIT_BF16 = 2, HSB_SPLIT_INT8 = 3 };
 
 /* Workspace modes for hsbuild_workspace_bytes. */
 enum { HSB_MODE_FORWARD = 0, HSB_MODE_BACKWARD = 1, HSB_MODE_BATCH = 2, HSB_MODE_COEFFICIENTS = 3, HSB_MODE_FACTORED = 4,
@@ -86,8 +89,9 @@ typedef struct {
   const double* r_mt;         /* [n_types] muffin-tin radii (bohr), > 0 */
   const double* radial;       /* [n_types][l_max+1][4]: u, u', udot, udot' at R_MT */
   const double* udot_norm2;   /* [n_types][l_max+1]: ||udot_l||^2 >= 0 */
-  int32_t precision;          /* HSB_FP64, HSB_SPLIT_FP16 or HSB_SPLIT_BF16 */
-  int32_t n_slices;           /* split path only: 8-bit slices per operand, 3..6 */
+  int32_t precision;          /* HSB_FP64, HSB_SPLIT_FP16, HSB_SPLIT_BF16 or HSB_SPLIT_INT8 */
+  int32_t n_slices;           /* split path only: slices per operand, 3..6 (8 bits each
+                                 for BF16/FP16, 7 for INT8) */
 } hsb_config;
 
 /* Create a handle.  Returns HSB_ERR_NUMERIC if some radial Wronskian

@@ -24,6 +24,7 @@ STATUS_NAMES = {0: "HSB_OK", -1: "HSB_ERR_ARG", -2: "HSB_ERR_SHAPE", -3: "HSB_ER
 HSB_FP64 = 0
 HSB_SPLIT_FP16 = 1
 HSB_SPLIT_BF16 = 2
+HSB_SPLIT_INT8 = 3
 
 HSB_MODE_FORWARD = 0
 HSB_MODE_BACKWARD = 1

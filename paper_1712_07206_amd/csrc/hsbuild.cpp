@@ -140,7 +140,8 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
     L.WL = take((size_t)L.K_pad * np * sizeof(double2));
   if (mode == HSB_MODE_FORWARD && h.precision != HSB_FP64) {
     L.K_pad2 = (int)round_up(L.K, 32);
-    const size_t planes = (size_t)2 * h.n_slices * np * L.K_pad2 * 2;  // bytes per sliced operand
+    const size_t elem = h.precision == HSB_SPLIT_INT8 ? 1 : 2;       // bytes per slice value
+    const size_t planes = (size_t)2 * h.n_slices * np * L.K_pad2 * elem;  // bytes per sliced operand
     L.mx = take(3 * np * sizeof(unsigned long long));
     L.scale = take(3 * np * sizeof(double));
     L.slL = take(planes);
@@ -263,7 +264,7 @@ int enqueue_split(hsbuild_t h, const Layout& L, char* w, double2* H, double2* S,
   const double2* Y = (const double2*)(w + L.Y);
   const double* lam = (const double*)(w + L.lam);
   const double* sc = (const double*)(w + L.scale);
-  const int QK = L.K_pad2 / 8;
+  const int QK = L.K_pad2 / (h->precision == HSB_SPLIT_INT8 ? 16 : 8);  // 16-byte units per column
   int rc = launched(h, launch_split_scales(W, Y, lam, L.K, L.n_pad, (unsigned long long*)(w + L.mx), (double*)sc, s),
                     "split scales");
   if (rc) return rc;
@@ -398,7 +399,8 @@ int hsbuild_create(const hsb_config* cfg, hsbuild_t* out) {
   if (cfg->max_ng < 1) return fail(nullptr, HSB_ERR_ARG, "max_ng=%d must be >= 1", cfg->max_ng);
   if (!cfg->atom_type || !cfg->r_mt || !cfg->radial || !cfg->udot_norm2)
     return fail(nullptr, HSB_ERR_ARG, "null atom_type, r_mt, radial or udot_norm2");
-  if (cfg->precision != HSB_FP64 && cfg->precision != HSB_SPLIT_FP16 && cfg->precision != HSB_SPLIT_BF16)
+  if (cfg->precision != HSB_FP64 && cfg->precision != HSB_SPLIT_FP16 && cfg->precision != HSB_SPLIT_BF16 &&
+      cfg->precision != HSB_SPLIT_INT8)
     return fail(nullptr, HSB_ERR_ARG, "unknown precision %d", cfg->precision);
   if (cfg->precision != HSB_FP64 && (cfg->n_slices < 3 || cfg->n_slices > 6))
     return fail(nullptr, HSB_ERR_ARG, "n_slices=%d outside [3, 6]", cfg->n_slices);

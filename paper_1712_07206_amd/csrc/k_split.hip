@@ -437,6 +437,253 @@ __global__ void __launch_bounds__(512, 1) k_hs_split2(const u4* __restrict__ Ls,
   }
 }
 
+// ---- int8 slices ------------------------------------------------------------------------
+// Seven-bit slices in signed bytes:
+//     x / 2^e = sum_{s=0}^{S-1} q_s 2^{-6-7s} + r,   q_0 = rint(64 x), q_s = rint(128 r_{s-1}),
+// so |q_s| <= 64 and |r| <= 2^{-7S}, every step exact in FP64.  Unit ((p * NB + b) * QK + q)
+// * 64 + g holds plane p (= 2 s + {0: Re, 1: Im}), G = 64 b + g, k = 16 q .. 16 q + 15, one
+// byte each, so a 32-row chunk of a 64-column block is 2 KB contiguous per plane.
+typedef int i4v __attribute__((ext_vector_type(4)));
+typedef int i16v __attribute__((ext_vector_type(16)));
+
+template <int S>
+__global__ void __launch_bounds__(256) k_slice8(const d2* __restrict__ X, const double* __restrict__ lam,
+                                                int use_lam, int K, int n_pad, int QK,
+                                                const double* __restrict__ scale, u4* __restrict__ out) {
+  const int g = threadIdx.x & 63;
+  const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int b = blockIdx.x;
+  const int G = b * 64 + g;
+  if (q >= QK) return;
+  const double inv = 64.0 / scale[G];  // a power of two: exact
+  double re[16], im[16];
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    const int k = q * 16 + j;
+    d2 v = d2{0.0, 0.0};
+    if (k < K) {
+      v = X[(int64_t)k * n_pad + G];
+      if (use_lam) v *= lam[k];
+    }
+    re[j] = v.x * inv;
+    im[j] = v.y * inv;
+  }
+  const int NB = n_pad / 64;
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    u4 ur = u4{0u, 0u, 0u, 0u}, ui = u4{0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+      const double qr = rint(re[j]), qi = rint(im[j]);
+      re[j] = (re[j] - qr) * 128.0;
+      im[j] = (im[j] - qi) * 128.0;
+      ur[j >> 2] |= ((unsigned)(int)qr & 0xffu) << (8 * (j & 3));
+      ui[j >> 2] |= ((unsigned)(int)qi & 0xffu) << (8 * (j & 3));
+    }
+    out[((int64_t)((2 * s) * NB + b) * QK + q) * 64 + g] = ur;
+    out[((int64_t)((2 * s + 1) * NB + b) * QK + q) * 64 + g] = ui;
+  }
+}
+
+// Bytewise negation of four signed bytes per word (no borrow crosses a byte).
+__device__ __forceinline__ u4 neg_bytes(u4 x) {
+  u4 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) r[i] = (0x80808080u - (x[i] & 0x7f7f7f7fu)) ^ (~x[i] & 0x80808080u);
+  return r;
+}
+
+__device__ __forceinline__ i16v mfma_i8(u4 a, u4 b, i16v c) {
+  return __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(i4v, a), __builtin_bit_cast(i4v, b), c, 0, 0, 0);
+}
+
+// int8 contraction.  Tile, waves and staging as in k_hs_split2 (128 x 64 tile, 8 waves of
+// 32 x 32, direct-to-LDS copies into double-buffered LDS), with 32-row chunks: a 16-byte
+// unit holds 16 rows of one slice plane.  Pair (s, t) runs on v_mfma_i32_32x32x32_i8 into
+// the int32 sum of its level d = s + t, which is exact: per row a channel adds two
+// products of at most 64 * 64, and a level takes at most S pairs, so 8192 rows stay below
+// 2^{13+13} S < 2^31 for S <= 6.  Every 8192 rows (and at the end) the levels are combined
+// in FP64 with weights 2^{-12-7d} and the column scales, and added into C, which the same
+// lane wrote at the previous flush.
+constexpr int kFlush8 = 256;  // chunks of 32 rows between flushes
+
+// LDS reads that pair j (loop order: left slice si, then right slice ti < S - si) issues:
+// its right slice, plus the left slice when it is the first pair of that left slice.
+template <int S>
+constexpr int split8_reads(int j) {
+  int idx = 0;
+  for (int si = 0; si < S; ++si)
+    for (int ti = 0; ti < S - si; ++ti, ++idx)
+      if (idx == j) return ti == 0 ? 4 : 2;
+  return 0;
+}
+
+// scheduling groups (DS read = 0x100, MFMA = 0x008): the reads of pair j + 1, then the
+// four MFMAs of pair j, so that only two pairs' operands are live at a time
+template <int S, int J>
+__device__ __forceinline__ void split8_schedule() {
+  constexpr int NP = S * (S + 1) / 2;
+  if constexpr (J < NP) {
+    if constexpr (J + 1 < NP) __builtin_amdgcn_sched_group_barrier(0x100, split8_reads<S>(J + 1), 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
+    split8_schedule<S, J + 1>();
+  }
+}
+
+template <int S>
+__global__ void __launch_bounds__(512, 1) k_hs_split8(const u4* __restrict__ Ls, const u4* __restrict__ Rs,
+                                                      const double* __restrict__ scL, const double* __restrict__ scR,
+                                                      int QK, int n, int n_pad, int nbr, int num_wg, int gr,
+                                                      d2* __restrict__ C) {
+  constexpr int P = 2 * S;        // planes per operand
+  constexpr int CU = 384 * P;     // units per chunk: left P*2*2*64, right P*2*64
+  constexpr int NI = 6 * P;       // 64-unit copies per chunk
+  __shared__ u4 lds[2][CU];
+
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int x = blockIdx.x % kXcds;
+  int start, len;
+  xcd_range(x, num_wg, start, len);
+  const int w = start + blockIdx.x / kXcds;
+  int row0, col0;
+  tile_origin(w, nbr, gr, row0, col0);
+  if (col0 >= n) return;
+  const int NB = n_pad / 64;
+  const int bL = row0 / 64, bR = col0 / 64;
+  const int nchunks = QK / 2;
+
+  constexpr int NPW = (NI + 7) / 8;
+  const u4* src0[NPW];
+  int dst[NPW];
+#pragma unroll
+  for (int i = 0; i < NPW; ++i) {
+    const int j = wave + 8 * i;
+    src0[i] = Ls;
+    dst[i] = 0;
+    if (j >= NI) continue;
+    if (j < 4 * P) {
+      const int p = j >> 2, b = (j >> 1) & 1, qq = j & 1;
+      src0[i] = Ls + ((int64_t)(p * NB + bL + b) * QK + qq) * 64;
+      dst[i] = ((p * 2 + b) * 2 + qq) * 64;
+    } else {
+      const int jj = j - 4 * P;
+      const int p = jj >> 1, qq = jj & 1;
+      src0[i] = Rs + ((int64_t)(p * NB + bR) * QK + qq) * 64;
+      dst[i] = 256 * P + (p * 2 + qq) * 64;
+    }
+  }
+  auto issue = [&](int c, int buf) {
+#pragma unroll
+    for (int i = 0; i < NPW; ++i)
+      if (wave + 8 * i < NI)
+        __builtin_amdgcn_global_load_lds((const void*)(src0[i] + (int64_t)c * 128 + lane),
+                                         (lds_ptr)(&lds[buf][dst[i]]), 16, 0, 0);
+  };
+
+  i16v acc[S][2];
+#pragma unroll
+  for (int d = 0; d < S; ++d)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[d][0][r] = acc[d][1][r] = 0;
+
+  const int q = lane >> 5, g32 = lane & 31;
+  const int lrow = ((wr >> 1) * 2 + q) * 64 + (wr & 1) * 32 + g32;
+  const int rcol = 256 * P + q * 64 + wc * 32 + g32;
+  // output element r of this lane: D layout of the 32 x 32 MFMA
+  auto flush = [&](bool first) {
+    // the tile origin is loop-invariant: an opaque copy keeps the output addresses and
+    // scales from being hoisted out of the chunk loop (and held in registers through it)
+    int rb = row0 + wr * 32 + 4 * q, cb = col0 + wc * 32 + g32;
+    asm volatile("" : "+v"(rb), "+v"(cb));
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      double vre = 0.0, vim = 0.0;
+#pragma unroll
+      for (int d = 0; d < S; ++d) {
+        vre += __builtin_ldexp((double)acc[d][0][r], -7 * d);
+        vim += __builtin_ldexp((double)acc[d][1][r], -7 * d);
+        acc[d][0][r] = 0;
+        acc[d][1][r] = 0;
+      }
+      const int row = rb + 8 * (r >> 2) + (r & 3);
+      const int col = cb;
+      if (row < n && col < n && col >= row) {
+        const double sc = 0x1p-12 * scL[row] * scR[col];
+        d2 v = d2{vre * sc, vim * sc};
+        if (!first) v += C[(int64_t)row * n + col];
+        C[(int64_t)row * n + col] = v;
+      }
+    }
+  };
+
+  if (nchunks == 0) {
+    flush(true);
+    return;
+  }
+  issue(0, 0);
+  for (int c = 0; c < nchunks; ++c) {
+    const int buf = c & 1;
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    if (c + 1 < nchunks) issue(c + 1, buf ^ 1);
+    const u4* B = lds[buf];
+#pragma unroll
+    for (int si = 0; si < S; ++si) {
+      const u4 lr = B[lrow + (2 * si) * 256];
+      const u4 li = B[lrow + (2 * si + 1) * 256];
+      const u4 ln = neg_bytes(li);
+      // re-read the right slices for every left slice (an opaque index keeps the reads
+      // from being merged, which would hold all 2S right operands live through the chunk)
+      int rc = rcol;
+      asm volatile("" : "+v"(rc));
+      const u4* BR = B + rc;
+#pragma unroll
+      for (int ti = 0; ti < S - si; ++ti) {
+        const u4 rr = BR[(2 * ti) * 128];
+        const u4 ri = BR[(2 * ti + 1) * 128];
+        const int d = si + ti;
+        acc[d][0] = mfma_i8(lr, rr, acc[d][0]);
+        acc[d][1] = mfma_i8(lr, ri, acc[d][1]);
+        acc[d][0] = mfma_i8(li, ri, acc[d][0]);
+        acc[d][1] = mfma_i8(ln, rr, acc[d][1]);
+      }
+    }
+    __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+    split8_schedule<S, 0>();
+    if ((c + 1) % kFlush8 == 0 || c + 1 == nchunks) flush(c < kFlush8);
+  }
+}
+
+hipError_t launch_hs_split8(int S, const void* L, const void* R, const double* scL, const double* scR, int QK, int n,
+                            int n_pad, int gr, double2* C, hipStream_t s) {
+  const int nbr = n_pad / SBM;
+  const int num_wg = nbr * (nbr + 1);
+  dim3 grid(num_wg), block(512);
+  switch (S) {
+    case 3: hipLaunchKernelGGL((k_hs_split8<3>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, (d2*)C); break;
+    case 4: hipLaunchKernelGGL((k_hs_split8<4>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, (d2*)C); break;
+    case 5: hipLaunchKernelGGL((k_hs_split8<5>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, (d2*)C); break;
+    case 6: hipLaunchKernelGGL((k_hs_split8<6>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, (d2*)C); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_slices8(int S, const double2* X, const double* lam, int use_lam, int K, int n_pad, int QK,
+                          const double* scale, void* out, hipStream_t s) {
+  dim3 grid(n_pad / 64, (QK + 3) / 4);
+  switch (S) {
+    case 3: hipLaunchKernelGGL((k_slice8<3>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, (u4*)out); break;
+    case 4: hipLaunchKernelGGL((k_slice8<4>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, (u4*)out); break;
+    case 5: hipLaunchKernelGGL((k_slice8<5>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, (u4*)out); break;
+    case 6: hipLaunchKernelGGL((k_slice8<6>), grid, dim3(256), 0, s, (const d2*)X, lam, use_lam, K, n_pad, QK, scale, (u4*)out); break;
+    default: return hipErrorInvalidValue;
+  }
+  return hipGetLastError();
+}
+
 hipError_t launch_hs_split2(int S, const void* L, const void* R, const double* scL, const double* scR, int QK, int n,
                             int n_pad, int gr, double2* C, hipStream_t s) {
   const int nbr = n_pad / SBM;
@@ -501,6 +748,7 @@ hipError_t launch_split_scales(const double2* W, const double2* Y, const double*
 
 hipError_t launch_split_slices(int precision, int S, const double2* X, const double* lam, int use_lam, int K,
                                int n_pad, int QK, const double* scale, void* out, hipStream_t s) {
+  if (precision == HSB_SPLIT_INT8) return launch_slices8(S, X, lam, use_lam, K, n_pad, QK, scale, out, s);
   // BF16 slices are stored pre-scaled for the level-folding contraction
   if (precision == HSB_SPLIT_BF16) return launch_slices_t<__bf16>(S, X, lam, use_lam, K, n_pad, QK, scale, 1, out, s);
   return launch_slices_t<_Float16>(S, X, lam, use_lam, K, n_pad, QK, scale, 0, out, s);
@@ -508,6 +756,7 @@ hipError_t launch_split_slices(int precision, int S, const double2* X, const dou
 
 hipError_t launch_hs_split(int precision, int S, const void* L, const void* R, const double* scL, const double* scR,
                            int QK, int n, int n_pad, int gr, double2* C, hipStream_t s) {
+  if (precision == HSB_SPLIT_INT8) return launch_hs_split8(S, L, R, scL, scR, QK, n, n_pad, gr, C, s);
   if (precision == HSB_SPLIT_BF16) return launch_hs_split2(S, L, R, scL, scR, QK, n, n_pad, gr, C, s);
   return launch_hs_split_t<_Float16>(S, L, R, scL, scR, QK, n, n_pad, C, s);
 }

@@ -84,9 +84,18 @@ def test_create_rejects_out_of_range(field, value):
     assert N.last_error(None)
 
 
-def test_create_rejects_split_without_slices():
-    cfg, keep = _config(precision=N.HSB_SPLIT_BF16, n_slices=2)
+@pytest.mark.parametrize("precision", [N.HSB_SPLIT_FP16, N.HSB_SPLIT_BF16, N.HSB_SPLIT_INT8])
+@pytest.mark.parametrize("n_slices", [0, 2, 7])
+def test_create_rejects_split_slice_count(precision, n_slices):
+    cfg, keep = _config(precision=precision, n_slices=n_slices)
     assert _create(cfg)[0] == N.HSB_ERR_ARG
+    assert "n_slices" in N.last_error(None)
+
+
+def test_create_rejects_unknown_precision():
+    cfg, keep = _config(precision=N.HSB_SPLIT_INT8 + 1, n_slices=5)
+    assert _create(cfg)[0] == N.HSB_ERR_ARG
+    assert "precision" in N.last_error(None)
 
 
 def test_create_rejects_unsorted_types():

@@ -1,6 +1,7 @@
 """Split-precision (Ozaki slice) forward: BF16 and FP16 slices on MFMA with
-FP32 accumulation, FP64 recombination.  Bar: relative Frobenius error
-<= 1e-10 for H and for S against the oracle (5 slices of 8 bits)."""
+FP32 accumulation, or int8 slices with exact int32 accumulation, FP64
+recombination.  Bar: relative Frobenius error <= 1e-10 for H and for S against
+the oracle (5 slices of 8 bits for BF16/FP16, 6 slices of 7 bits for int8)."""
 import numpy as np
 import pytest
 import torch
@@ -51,13 +52,17 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-@pytest.mark.parametrize("prec_name", ["bf16", "fp16"])
+def _prec(name):
+    from paper_1712_07206_amd import HSB_SPLIT_BF16, HSB_SPLIT_FP16, HSB_SPLIT_INT8
+    return {"bf16": (HSB_SPLIT_BF16, 5), "fp16": (HSB_SPLIT_FP16, 5), "int8": (HSB_SPLIT_INT8, 6)}[name]
+
+
+@pytest.mark.parametrize("prec_name", ["bf16", "fp16", "int8"])
 @pytest.mark.parametrize("idx,n_g", [(0, None), (1, 7), (1, 129), (1, 1000), (2, 3000)])
 def test_split_matches_oracle(prec_name, idx, n_g):
-    from paper_1712_07206_amd import HSB_SPLIT_BF16, HSB_SPLIT_FP16
-    prec = HSB_SPLIT_BF16 if prec_name == "bf16" else HSB_SPLIT_FP16
+    prec, slices = _prec(prec_name)
     case, (Hr, Sr) = oracle(idx, n_g)
-    H, S = _split(case, prec, 5)
+    H, S = _split(case, prec, slices)
     n = case["n_g"]
     il = np.tril_indices(n, -1)
     assert np.all(np.isnan(H[il])) and np.all(np.isnan(S[il])), "strict lower triangle was written"
@@ -66,22 +71,29 @@ def test_split_matches_oracle(prec_name, idx, n_g):
     assert eh <= TOL_SPLIT and es <= TOL_SPLIT
 
 
-def test_split_error_falls_with_slices():
-    from paper_1712_07206_amd import HSB_SPLIT_BF16
+@pytest.mark.parametrize("prec_name", ["bf16", "int8"])
+def test_split_error_falls_with_slices(prec_name):
+    prec, _ = _prec(prec_name)
     case, (Hr, Sr) = oracle(1, 1000)
     errs = []
     for s in (3, 4, 5, 6):
-        H, S = _split(case, HSB_SPLIT_BF16, s, poison=False)
+        H, S = _split(case, prec, s, poison=False)
         errs.append(max(rel(_full(H), Hr), rel(_full(S), Sr)))
-    print("bf16 error by slice count 3..6:", errs)
+    print("%s error by slice count 3..6:" % prec_name, errs)
     assert errs[0] > errs[1] > errs[2] > errs[3]
-    assert errs[0] < 1e-4 and errs[3] < 1e-12
+    if prec_name == "bf16":  # 8-bit slices
+        assert errs[0] < 1e-4 and errs[3] < 1e-12
+    else:  # 7-bit slices: about 2^7 per added slice
+        assert all(a / b > 30 for a, b in zip(errs, errs[1:])), errs
+        assert errs[0] < 1e-4 and errs[3] < TOL_SPLIT
 
 
-def test_split_full_size_against_fp64_path():
+@pytest.mark.parametrize("prec_name", ["bf16", "int8"])
+def test_split_full_size_against_fp64_path(prec_name):
     """Full-size workload (N_G = 12000, stacked width 30976) in the benchmark's
-    launch configuration: BF16, 5 slices, against the FP64 MFMA path."""
-    from paper_1712_07206_amd import HSB_SPLIT_BF16
+    launch configuration (BF16 with 5 slices, int8 with 6) against the FP64 MFMA
+    path."""
+    prec, slices = _prec(prec_name)
     from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors, hermitian_full
     case = make_case(2)
     g, tau, T = case_tensors(case)
@@ -91,10 +103,10 @@ def test_split_full_size_against_fp64_path():
     b64.close()
     del b64
     torch.cuda.empty_cache()
-    bs = HSBuilder.from_case(case, precision=HSB_SPLIT_BF16, n_slices=5)
+    bs = HSBuilder.from_case(case, precision=prec, n_slices=slices)
     Hs, Ss = bs.forward(case["k_frac"], g, tau, T)
     Hs, Ss = hermitian_full(Hs), hermitian_full(Ss)
     eh = (torch.linalg.norm(Hs - H64) / torch.linalg.norm(H64)).item()
     es = (torch.linalg.norm(Ss - S64) / torch.linalg.norm(S64)).item()
-    print("full-size split bf16 vs fp64: H %.3e S %.3e" % (eh, es))
+    print("full-size split %s vs fp64: H %.3e S %.3e" % (prec_name, eh, es))
     assert eh <= TOL_SPLIT and es <= TOL_SPLIT
