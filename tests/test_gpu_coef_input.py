@@ -41,18 +41,23 @@ def test_fp64_from_random_coefficients():
     assert rel(_full(S.cpu().numpy()), Sr) <= 1e-13
 
 
-@pytest.mark.parametrize("prec_name", ["bf16", "fp16"])
-@pytest.mark.parametrize("bits,tol", [(24, 1e-14), (40, 2 ** -37)])
+@pytest.mark.parametrize("prec_name,bits,tol", [("bf16", 24, 1e-14), ("bf16", 40, 2 ** -37),
+                                                ("fp16", 24, 1e-14), ("fp16", 40, 2 ** -37),
+                                                ("int8", 19, 1e-14), ("int8", 40, 2 ** -37)])
 def test_split_on_few_bit_inputs(prec_name, bits, tol):
     """Coefficients with `bits` significant bits per column scale, lambda = 1,
     T = 1 (so H = S = W^H W).  With 5 slices of 8 bits the kept slice pairs are
     those with s + t < 5: 24-bit inputs have only slices 0..2, every nonzero
     pair is kept and the result is the FP64 product to FP64 summation rounding;
     40-bit inputs lose the pairs with s + t >= 5, each below 2^-40 of the
-    leading term."""
-    from paper_1712_07206_amd import HSB_SPLIT_BF16, HSB_SPLIT_FP16
+    leading term.  With 6 int8 slices of 7 bits (6 in the first) the kept pairs
+    are s + t < 6: 19-bit inputs fill only slices 0..2 (20 bits below the
+    scale), every nonzero pair is kept and the result is again the FP64
+    product; 40-bit inputs fill slices 0..5 and lose the pairs with s + t >= 6,
+    each below 2^-42 of the leading term."""
+    from paper_1712_07206_amd import HSB_SPLIT_BF16, HSB_SPLIT_FP16, HSB_SPLIT_INT8
     from paper_1712_07206_amd.hsbuild import HSBuilder
-    prec = HSB_SPLIT_BF16 if prec_name == "bf16" else HSB_SPLIT_FP16
+    prec, slices = {"bf16": (HSB_SPLIT_BF16, 5), "fp16": (HSB_SPLIT_FP16, 5), "int8": (HSB_SPLIT_INT8, 6)}[prec_name]
     case = dict(make_case(1, n_g=640))
     n, n_at, n_l = 640, case["n_atoms"], case["n_l"]
     case["udot_norm2"] = np.ones_like(case["udot_norm2"])  # lambda = 1
@@ -62,7 +67,7 @@ def test_split_on_few_bit_inputs(prec_name, bits, tol):
     e = rng.integers(-3, 4, n)  # per-column binary exponent
     mant = rng.integers(-(2 ** bits) + 1, 2 ** bits, size=(n_at, 2, n_l, n, 2)).astype(np.float64)
     coef = (mant[..., 0] + 1j * mant[..., 1]) * np.ldexp(1.0, e - bits)[None, None, None, :]
-    b = HSBuilder.from_case(case, precision=prec, n_slices=5)
+    b = HSBuilder.from_case(case, precision=prec, n_slices=slices)
     H, S = b.forward_from_coefficients(torch.as_tensor(coef, device="cuda"), torch.as_tensor(case["T"], device="cuda"))
     Sr = o.overlap(case, coef)
     Hs, Ss = _full(H.cpu().numpy()), _full(S.cpu().numpy())

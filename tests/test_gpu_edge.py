@@ -74,14 +74,16 @@ def test_edge_real_with_empty_type():
     assert eh <= 1e-12 and es <= 1e-12
 
 
-def test_edge_split_lmax12():
-    from paper_1712_07206_amd import HSB_SPLIT_BF16
+@pytest.mark.parametrize("prec_name", ["bf16", "int8"])
+def test_edge_split_lmax12(prec_name):
+    from paper_1712_07206_amd import HSB_SPLIT_BF16, HSB_SPLIT_INT8
     from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    prec, slices = {"bf16": (HSB_SPLIT_BF16, 5), "int8": (HSB_SPLIT_INT8, 6)}[prec_name]
     case, (Hr, Sr) = _oracle(7)
-    b = HSBuilder.from_case(case, precision=HSB_SPLIT_BF16, n_slices=5)
+    b = HSBuilder.from_case(case, precision=prec, n_slices=slices)
     g, tau, T = case_tensors(case)
     H, S = b.forward(case["k_frac"], g, tau, T)
-    _check("split bf16 x5", H.cpu().numpy(), S.cpu().numpy(), Hr, Sr, 1e-10)
+    _check("split %s x%d" % (prec_name, slices), H.cpu().numpy(), S.cpu().numpy(), Hr, Sr, 1e-10)
 
 
 @pytest.mark.parametrize("idx", [7, 8])
