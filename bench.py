@@ -429,6 +429,44 @@ def adjoint_leg(args) -> dict:
                     "multiply-add)"}
 
 
+def device_leg() -> dict:
+    """CU count, and the sustained matrix-core rates of the two instructions the
+    contractions run on (FP64 16x16x4 and int8 32x32x32), measured by the
+    library's probe; each rate divided by the per-CU rate per clock gives the
+    clock the matrix cores hold under that load."""
+    import torch
+
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import mfma_probe
+    props = torch.cuda.get_device_properties(0)
+    cus = int(props.multi_processor_count)
+    out = {"name": props.name, "arch": getattr(props, "gcnArchName", ""), "cus": cus}
+    # per CU per clock: 4 SIMDs x (2048 FP64 operations per 64 cycles | 65536 int8 operations per 32 cycles)
+    for key, kind, iters, per_clk, peak in (("fp64", N.HSB_PROBE_FP64, 50000, 128.0, 78.6),
+                                            ("int8", N.HSB_PROBE_INT8, 100000, 8192.0, 5000.0)):
+        blocks = 8 * cus
+        ops, buf = mfma_probe(kind, blocks, 160)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(3):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            ops, buf = mfma_probe(kind, blocks, iters, buf)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None or ms < best else best
+        rate = ops / (best * 1e-3) / 1e12
+        out[key + "_mfma_probe"] = {"achieved": round(rate, 2), "unit": "TFLOP/s" if key == "fp64" else "TOP/s",
+                                    "peak": peak, "frac": round(rate / peak, 4), "ms": round(best, 3),
+                                    "clock_ghz": round(rate * 1e12 / (cus * per_clk) / 1e9, 3)}
+        log("%s MFMA probe: %.1f %s (%.1f %% of %.1f), %.3f GHz" % (key, rate, out[key + "_mfma_probe"]["unit"],
+                                                                    100 * rate / peak, peak,
+                                                                    out[key + "_mfma_probe"]["clock_ghz"]))
+        del buf
+    return out
+
+
 def oracle_table() -> list:
     """The oracle on the host next to the GPU path at the same sizes: forward at
     cfg0, cfg1 (N_G 3000, also single-threaded) and cfg2 at N_G 3000, and the
@@ -530,6 +568,7 @@ def main() -> int:
     ap.add_argument("--no-hsdla", action="store_true", help="skip the rocBLAS HSDLA baseline leg")
     ap.add_argument("--no-real", action="store_true", help="skip the real-symmetric (inversion) leg")
     ap.add_argument("--no-eigen", action="store_true", help="skip the generalized eigensolve leg")
+    ap.add_argument("--no-device-probe", action="store_true", help="skip the matrix-core rate probe")
     ap.add_argument("--split-slices", type=int, default=5,
                     help="also time the BF16 split-precision path with this many slices (0: skip)")
     ap.add_argument("--int8-slices", type=int, default=6,
@@ -682,6 +721,8 @@ def main() -> int:
     if not args.no_batch:
         result["batch"] = batch_leg(args)
         result["batch_speedup"] = result["batch"]["speedup"]
+    if not args.no_device_probe:
+        result["device"] = device_leg()
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host (N_G=%d)" % args.cpu_ng)
         result["cpu_baseline"] = cpu_baseline(args.config, args.cpu_ng)

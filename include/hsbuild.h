@@ -249,6 +249,21 @@ const char* hsbuild_last_error(hsbuild_t h);
 int hsbuild_host_bessel(int32_t lmax, double x, double* jl, double* djl);
 int hsbuild_host_angular(int32_t lmax, const double kvec[3], double pre, void* out);
 
+/* Matrix-core rate probe, to confirm the peak figures the contraction kernels
+ * are measured against: `blocks` workgroups of 4 waves, each wave running 4
+ * independent chains of `iters` (a multiple of 16) MFMAs on register operands
+ * (HSB_PROBE_FP64: v_mfma_f64_16x16x4f64, the instruction of the FP64
+ * contraction; HSB_PROBE_INT8: v_mfma_i32_32x32x32_i8, the instruction of the
+ * int8 split contraction).  out: device buffer of at least blocks * 256 * 8
+ * bytes (FP64) or blocks * 256 * 4 bytes (INT8) that receives one value per
+ * thread; *ops (host) receives the arithmetic operations the launch executes
+ * (2 per multiply-add).  Enqueued on `stream`; the caller times it.  Returns
+ * HSB_ERR_ARG or HSB_ERR_WORKSPACE (checked before any device call), or
+ * HSB_ERR_DEVICE if the launch fails. */
+enum { HSB_PROBE_FP64 = 0, HSB_PROBE_INT8 = 1 };
+int hsbuild_mfma_probe(int32_t kind, int32_t blocks, int32_t iters, void* out, size_t out_bytes, void* stream,
+                       double* ops);
+
 #ifdef __cplusplus
 }
 #endif

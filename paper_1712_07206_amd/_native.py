@@ -25,6 +25,8 @@ HSB_FP64 = 0
 HSB_SPLIT_FP16 = 1
 HSB_SPLIT_BF16 = 2
 HSB_SPLIT_INT8 = 3
+HSB_PROBE_FP64 = 0
+HSB_PROBE_INT8 = 1
 
 HSB_MODE_FORWARD = 0
 HSB_MODE_BACKWARD = 1
@@ -41,7 +43,7 @@ EXPORTS = ("hsbuild_create", "hsbuild_destroy", "hsbuild_workspace_bytes", "hsbu
            "hsbuild_backward",
            "hsbuild_batch", "hsbuild_last_error",
            "hsbuild_host_bessel", "hsbuild_host_angular", "hsbuild_set_timing", "hsbuild_stage_times",
-           "hsbuild_set_option", "hsbuild_get_option")
+           "hsbuild_set_option", "hsbuild_get_option", "hsbuild_mfma_probe")
 
 HSB_OPT_TILE_GROUP = 1
 HSB_OPT_HS_WAVES = 2
@@ -119,6 +121,8 @@ def lib():
     L.hsbuild_set_timing.restype = c_int
     L.hsbuild_stage_times.argtypes = [c_void_p, POINTER(c_double), POINTER(c_int32)]
     L.hsbuild_stage_times.restype = c_int
+    L.hsbuild_mfma_probe.argtypes = [c_int32, c_int32, c_int32, c_void_p, c_size_t, c_void_p, POINTER(c_double)]
+    L.hsbuild_mfma_probe.restype = c_int
     L.hsbuild_set_option.argtypes = [c_void_p, c_int32, c_int32]
     L.hsbuild_set_option.restype = c_int
     L.hsbuild_get_option.argtypes = [c_void_p, c_int32, POINTER(c_int32)]

@@ -125,6 +125,11 @@ int hs_tiles(int n_pad);
 hipError_t launch_hs_fp64_batch(const double2* ws, const double* lam, int K_pad, const BatchMeta* meta, int n_k,
                                 int total, int grid, int gr, int waves, double2* H, double2* S, hipStream_t s);
 
+// ---- matrix-core rate probe (kind 0: FP64 16x16x4, 1: int8 32x32x32) ----
+constexpr int kProbeUnroll = 16;  // iterations per loop pass: the probe's iters must be a multiple
+double probe_ops_per_mfma(int kind);
+hipError_t launch_mfma_probe(int kind, int blocks, int iters, void* out, hipStream_t s);
+
 // ---- split precision ----
 // Column scales 2^e (max_k |Re|, |Im| < 2^e) of W, lam W and Y: scale[0..3 n_pad); mx: 3 n_pad scratch.
 hipError_t launch_split_scales(const double2* W, const double2* Y, const double* lam, int K, int n_pad,

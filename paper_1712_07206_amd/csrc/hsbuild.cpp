@@ -1133,4 +1133,20 @@ int hsbuild_host_angular(int32_t lmax, const double kvec[3], double pre, void* o
   return HSB_OK;
 }
 
+int hsbuild_mfma_probe(int32_t kind, int32_t blocks, int32_t iters, void* out, size_t out_bytes, void* stream,
+                       double* ops) {
+  if (kind != HSB_PROBE_FP64 && kind != HSB_PROBE_INT8) return fail(nullptr, HSB_ERR_ARG, "unknown probe kind %d", kind);
+  if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 26) || iters % kProbeUnroll)
+    return fail(nullptr, HSB_ERR_ARG, "blocks=%d or iters=%d out of range (iters: a multiple of %d)", blocks, iters,
+                kProbeUnroll);
+  if (!out || !ops) return fail(nullptr, HSB_ERR_ARG, "null out or ops");
+  const size_t need = (size_t)blocks * 256 * (kind == HSB_PROBE_FP64 ? sizeof(double) : sizeof(unsigned));
+  if (out_bytes < need) return fail(nullptr, HSB_ERR_WORKSPACE, "out holds %zu bytes, the probe writes %zu", out_bytes, need);
+  // 4 waves per workgroup, 4 independent MFMA chains per wave
+  *ops = (double)blocks * 4.0 * 4.0 * (double)iters * probe_ops_per_mfma(kind);
+  const hipError_t e = launch_mfma_probe(kind, blocks, iters, out, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(nullptr, HSB_ERR_DEVICE, "probe launch: %s", hipGetErrorString(e));
+  return HSB_OK;
+}
+
 }  // extern "C"

@@ -334,6 +334,19 @@ class HSBuilder:
                                        _ptr(ws), ws_bytes, _stream())
 
 
+def mfma_probe(kind: int, blocks: int, iters: int, out: Optional[torch.Tensor] = None):
+    """Enqueue the matrix-core rate probe on the current stream; returns the
+    operations it executes and the per-thread output buffer."""
+    per = 8 if kind == N.HSB_PROBE_FP64 else 4
+    if out is None:
+        out = torch.empty(blocks * 256 * per, dtype=torch.uint8, device="cuda")
+    ops = ctypes.c_double(0.0)
+    code = N.lib().hsbuild_mfma_probe(int(kind), int(blocks), int(iters), _ptr(out), out.numel() * out.element_size(),
+                                      _stream(), ctypes.byref(ops))
+    N.check(code, None)
+    return ops.value, out
+
+
 def hermitian_full(upper: torch.Tensor) -> torch.Tensor:
     """Full Hermitian matrix from its upper triangle (test and reporting helper)."""
     up = torch.triu(upper)

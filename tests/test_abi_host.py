@@ -236,3 +236,27 @@ def test_header_is_plain_c(tmp_path):
     if gxx is not None:
         subprocess.run([gxx, "-std=c++17", "-Wall", "-Werror", "-x", "c++", "-fsyntax-only", "-I", inc,
                         str(src)], check=True)
+
+
+@pytest.mark.parametrize("kind,blocks,iters,nbytes,code", [
+    (2, 8, 16, 1 << 20, N.HSB_ERR_ARG),                    # unknown kind
+    (N.HSB_PROBE_FP64, 0, 16, 1 << 20, N.HSB_ERR_ARG),     # no workgroups
+    (N.HSB_PROBE_INT8, 8, 0, 1 << 20, N.HSB_ERR_ARG),      # no iterations
+    (N.HSB_PROBE_INT8, 8, 24, 1 << 20, N.HSB_ERR_ARG),     # not a multiple of 16
+    (N.HSB_PROBE_FP64, 8, 16, 8 * 256 * 8 - 1, N.HSB_ERR_WORKSPACE),
+    (N.HSB_PROBE_INT8, 8, 16, 8 * 256 * 4 - 1, N.HSB_ERR_WORKSPACE),
+])
+def test_mfma_probe_rejects_bad_arguments(kind, blocks, iters, nbytes, code):
+    """Checked on the host before any device call (no GPU is touched)."""
+    ops = ctypes.c_double(-1.0)
+    fake = ctypes.c_void_p(4096)  # never dereferenced: every case fails validation
+    assert N.lib().hsbuild_mfma_probe(kind, blocks, iters, fake, nbytes, None, ctypes.byref(ops)) == code
+    assert N.last_error(None)
+    assert ops.value == -1.0
+
+
+def test_mfma_probe_rejects_null_buffers():
+    ops = ctypes.c_double(0.0)
+    assert N.lib().hsbuild_mfma_probe(N.HSB_PROBE_FP64, 8, 16, None, 1 << 20, None, ctypes.byref(ops)) == N.HSB_ERR_ARG
+    assert N.lib().hsbuild_mfma_probe(N.HSB_PROBE_FP64, 8, 16, ctypes.c_void_p(4096), 1 << 20, None,
+                                      None) == N.HSB_ERR_ARG
