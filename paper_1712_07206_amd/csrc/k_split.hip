@@ -501,11 +501,11 @@ __device__ __forceinline__ i16v mfma_i8(u4 a, u4 b, i16v c) {
 // 32 x 32, direct-to-LDS copies into double-buffered LDS), with 32-row chunks: a 16-byte
 // unit holds 16 rows of one slice plane.  Pair (s, t) runs on v_mfma_i32_32x32x32_i8 into
 // the int32 sum of its level d = s + t, which is exact: per row a channel adds two
-// products of at most 64 * 64, and a level takes at most S pairs, so 8192 rows stay below
-// 2^{13+13} S < 2^31 for S <= 6.  Every 8192 rows (and at the end) the levels are combined
-// in FP64 with weights 2^{-12-7d} and the column scales, and added into C, which the same
-// lane wrote at the previous flush.
-constexpr int kFlush8 = 256;  // chunks of 32 rows between flushes
+// products of at most 64 * 64, and a level takes at most S pairs, so 32768 rows stay
+// below 2^{13+15} S < 2^31 for S <= 6.  Every 32768 rows (and at the end) the levels are
+// combined in FP64 with weights 2^{-12-7d} and the column scales, and added into C, which
+// the same lane wrote at the previous flush.
+constexpr int kFlush8 = 1024;  // chunks of 32 rows between flushes
 
 // LDS reads that pair j (loop order: left slice si, then right slice ti < S - si) issues:
 // its right slice, plus the left slice when it is the first pair of that left slice.

@@ -110,3 +110,35 @@ def test_split_full_size_against_fp64_path(prec_name):
     es = (torch.linalg.norm(Ss - S64) / torch.linalg.norm(S64)).item()
     print("full-size split %s vs fp64: H %.3e S %.3e" % (prec_name, eh, es))
     assert eh <= TOL_SPLIT and es <= TOL_SPLIT
+
+
+def _wide_case(n_g, extra_per_type):
+    """The bench cell with `extra_per_type` more atoms of every type (seeded
+    positions in the cell): 160 atoms give 38720 stacked rows, past the int8
+    kernel's 32768-row window between flushes of its int32 level sums."""
+    case = dict(make_case(2, n_g=n_g))
+    rng = np.random.default_rng(20171209)
+    types, taus = [], []
+    for t in range(case["n_types"]):
+        old = case["tau"][case["atom_type"] == t]
+        new = rng.uniform(0.0, 1.0, size=(extra_per_type, 3)) @ case["lattice"]
+        types.append(np.full(len(old) + extra_per_type, t, dtype=case["atom_type"].dtype))
+        taus.append(np.concatenate([old, new]))
+    case["atom_type"] = np.concatenate(types)
+    case["tau"] = np.concatenate(taus)
+    case["n_atoms"] = len(case["atom_type"])
+    return case
+
+
+@pytest.mark.parametrize("prec_name", ["int8", "bf16"])
+def test_split_past_the_int8_flush_window(prec_name):
+    """Stacked width 38720 (two int8 flush windows, the second ragged) against the oracle."""
+    prec, slices = _prec(prec_name)
+    case = _wide_case(96, 8)
+    assert 2 * case["n_atoms"] * case["n_l"] > 32768
+    Hr, Sr = o.hs(case)
+    H, S = _split(case, prec, slices)
+    eh, es = rel(_full(H), Hr), rel(_full(S), Sr)
+    print("split %s at stacked width %d: rel err H %.3e S %.3e" % (prec_name, 2 * case["n_atoms"] * case["n_l"], eh, es))
+    assert eh <= TOL_SPLIT and es <= TOL_SPLIT
+
