@@ -723,6 +723,12 @@ def main() -> int:
         result["batch_speedup"] = result["batch"]["speedup"]
     if not args.no_device_probe:
         result["device"] = device_leg()
+        # each kernel's rate against what the matrix cores sustain on this device (the probe)
+        dev = result["device"]
+        result["roofline"]["probe_frac"] = round(result["roofline"]["achieved"] / dev["fp64_mfma_probe"]["achieved"], 4)
+        if result.get("split") and result["split"]["precision"] == "int8":
+            sm = result["split"]["slice_mfma"]
+            sm["probe_frac"] = round(sm["achieved"] / dev["int8_mfma_probe"]["achieved"], 4)
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host (N_G=%d)" % args.cpu_ng)
         result["cpu_baseline"] = cpu_baseline(args.config, args.cpu_ng)
