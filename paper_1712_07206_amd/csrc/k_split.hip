@@ -518,13 +518,13 @@ constexpr int split8_reads(int j) {
   return 0;
 }
 
-// scheduling groups (DS read = 0x100, MFMA = 0x008): the reads of pair j + 1, then the
-// four MFMAs of pair j, so that only two pairs' operands are live at a time
+// scheduling groups (DS read = 0x100, MFMA = 0x008): the reads of pair j + 2, then the
+// four MFMAs of pair j, so that three pairs' operands are live at a time
 template <int S, int J>
 __device__ __forceinline__ void split8_schedule() {
   constexpr int NP = S * (S + 1) / 2;
   if constexpr (J < NP) {
-    if constexpr (J + 1 < NP) __builtin_amdgcn_sched_group_barrier(0x100, split8_reads<S>(J + 1), 0);
+    if constexpr (J + 2 < NP) __builtin_amdgcn_sched_group_barrier(0x100, split8_reads<S>(J + 2), 0);
     __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
     split8_schedule<S, J + 1>();
   }
@@ -650,7 +650,7 @@ __global__ void __launch_bounds__(512, 1) k_hs_split8(const u4* __restrict__ Ls,
         acc[d][1] = mfma_i8(ln, rr, acc[d][1]);
       }
     }
-    __builtin_amdgcn_sched_group_barrier(0x100, 4, 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, 4 + split8_reads<S>(1), 0);
     split8_schedule<S, 0>();
     if ((c + 1) % kFlush8 == 0 || c + 1 == nchunks) flush(c < kFlush8);
   }
