@@ -188,3 +188,25 @@ def test_batch_small_uneven_bases_against_oracle():
         h1, s1 = b.forward(case["k_frac"][k], gl[k], tau, T)
         iu = np.triu_indices(n)
         assert np.array_equal(hb[iu], h1.cpu().numpy()[iu]) and np.array_equal(sb[iu], s1.cpu().numpy()[iu]), k
+
+
+@pytest.mark.parametrize("prec_name", ["int8", "bf16"])
+def test_batch_rejects_split_precision(prec_name):
+    """The batch entry point runs the FP64 contraction only: a handle created
+    with a split precision gets HSB_ERR_UNSUPPORTED, checked on the host before
+    anything is enqueued, and the outputs stay untouched."""
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import HSBuilder
+    prec, slices = (N.HSB_SPLIT_INT8, 6) if prec_name == "int8" else (N.HSB_SPLIT_BF16, 5)
+    case = make_batch_case(3, n_k=2)
+    sizes = [37, 64]
+    case["g"] = [np.ascontiguousarray(case["g"][k][:sizes[k]]) for k in range(2)]
+    case["n_g"] = np.array(sizes, dtype=np.int32)
+    b = HSBuilder.from_case(case, precision=prec, n_slices=slices)
+    tau = torch.as_tensor(case["tau"], device="cuda")
+    T = torch.as_tensor(case["T"], device="cuda")
+    gl = [torch.as_tensor(g, device="cuda") for g in case["g"]]
+    with pytest.raises(N.HSBuildError) as err:
+        b.batch(case["k_frac"], gl, tau, T)
+    assert err.value.code == N.HSB_ERR_UNSUPPORTED
+    assert "FP64" in str(err.value)
