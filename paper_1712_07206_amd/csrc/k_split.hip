@@ -507,24 +507,25 @@ __device__ __forceinline__ i16v mfma_i8(u4 a, u4 b, i16v c) {
 // the same lane wrote at the previous flush.
 constexpr int kFlush8 = 1024;  // chunks of 32 rows between flushes
 
-// LDS reads that pair j (loop order: left slice si, then right slice ti < S - si) issues:
-// its right slice, plus the left slice when it is the first pair of that left slice.
+// LDS reads that pair j (loop order: left slice si, then right slice ti < S - si) issues.
+// Right slices 0 and 1 are read once per chunk, by the pairs (0, 0) and (0, 1), and kept;
+// every other right slice is read by its pair; each left slice is read by its first pair.
 template <int S>
 constexpr int split8_reads(int j) {
   int idx = 0;
   for (int si = 0; si < S; ++si)
     for (int ti = 0; ti < S - si; ++ti, ++idx)
-      if (idx == j) return ti == 0 ? 4 : 2;
+      if (idx == j) return (ti == 0 ? 2 : 0) + (ti >= 2 || si == 0 ? 2 : 0);
   return 0;
 }
 
-// scheduling groups (DS read = 0x100, MFMA = 0x008): the reads of pair j + 2, then the
-// four MFMAs of pair j, so that three pairs' operands are live at a time
+// scheduling groups (DS read = 0x100, MFMA = 0x008): the reads of pair j + 1, then the
+// four MFMAs of pair j, so that two pairs' operands are live at a time
 template <int S, int J>
 __device__ __forceinline__ void split8_schedule() {
   constexpr int NP = S * (S + 1) / 2;
   if constexpr (J < NP) {
-    if constexpr (J + 2 < NP) __builtin_amdgcn_sched_group_barrier(0x100, split8_reads<S>(J + 2), 0);
+    if constexpr (J + 1 < NP) __builtin_amdgcn_sched_group_barrier(0x100, split8_reads<S>(J + 1), 0);
     __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
     split8_schedule<S, J + 1>();
   }
@@ -629,20 +630,23 @@ __global__ void __launch_bounds__(512, 1) k_hs_split8(const u4* __restrict__ Ls,
     __syncthreads();
     if (c + 1 < nchunks) issue(c + 1, buf ^ 1);
     const u4* B = lds[buf];
+    // right slices 0 and 1 pair with all but one left slice: read once per chunk and kept
+    const u4 rr0 = B[rcol], ri0 = B[rcol + 128];
+    const u4 rr1 = B[rcol + 256], ri1 = B[rcol + 384];
 #pragma unroll
     for (int si = 0; si < S; ++si) {
       const u4 lr = B[lrow + (2 * si) * 256];
       const u4 li = B[lrow + (2 * si + 1) * 256];
       const u4 ln = neg_bytes(li);
-      // re-read the right slices for every left slice (an opaque index keeps the reads
-      // from being merged, which would hold all 2S right operands live through the chunk)
+      // the other right slices are re-read for every left slice (an opaque index keeps the
+      // reads from being merged, which would hold all 2S right operands live through the chunk)
       int rc = rcol;
       asm volatile("" : "+v"(rc));
       const u4* BR = B + rc;
 #pragma unroll
       for (int ti = 0; ti < S - si; ++ti) {
-        const u4 rr = BR[(2 * ti) * 128];
-        const u4 ri = BR[(2 * ti + 1) * 128];
+        const u4 rr = ti == 0 ? rr0 : ti == 1 ? rr1 : BR[(2 * ti) * 128];
+        const u4 ri = ti == 0 ? ri0 : ti == 1 ? ri1 : BR[(2 * ti + 1) * 128];
         const int d = si + ti;
         acc[d][0] = mfma_i8(lr, rr, acc[d][0]);
         acc[d][1] = mfma_i8(lr, ri, acc[d][1]);
@@ -650,7 +654,7 @@ __global__ void __launch_bounds__(512, 1) k_hs_split8(const u4* __restrict__ Ls,
         acc[d][1] = mfma_i8(ln, rr, acc[d][1]);
       }
     }
-    __builtin_amdgcn_sched_group_barrier(0x100, 4 + split8_reads<S>(1), 0);
+    __builtin_amdgcn_sched_group_barrier(0x100, split8_reads<S>(0), 0);
     split8_schedule<S, 0>();
     if ((c + 1) % kFlush8 == 0 || c + 1 == nchunks) flush(c < kFlush8);
   }
