@@ -58,7 +58,7 @@ def _prec(name):
 
 
 @pytest.mark.parametrize("prec_name", ["bf16", "fp16", "int8"])
-@pytest.mark.parametrize("idx,n_g", [(0, None), (1, 7), (1, 129), (1, 1000), (2, 3000)])
+@pytest.mark.parametrize("idx,n_g", [(0, None), (1, 1), (1, 7), (1, 129), (1, 1000), (2, 3000), (4, 800)])
 def test_split_matches_oracle(prec_name, idx, n_g):
     prec, slices = _prec(prec_name)
     case, (Hr, Sr) = oracle(idx, n_g)
