@@ -429,6 +429,41 @@ def adjoint_leg(args) -> dict:
                     "multiply-add)"}
 
 
+def coefficient_leg(case, ms_coef: float) -> dict:
+    """The coefficient build (a1-a5, ending in the W write) as an HBM-bound
+    stage: algorithmic bytes 2 k_c N_G x 16 (the coefficients written once)
+    over the forward's coefficient stage time, against 8 TB/s and against a
+    timed 2 GiB device-to-device copy (its read and its write both counted)."""
+    import torch
+    k_c = case["n_atoms"] * case["n_l"]
+    alg = 2.0 * k_c * case["n_g"] * 16
+    size = 2 << 30
+    src = torch.empty(size, dtype=torch.uint8, device="cuda")
+    src.fill_(1)
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    best = None
+    for _ in range(5):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        best = ms if best is None or ms < best else best
+    del src, dst
+    torch.cuda.empty_cache()
+    copy_gbs = 2.0 * size / (best * 1e-3) / 1e9
+    ach = alg / (ms_coef * 1e-3) / 1e9
+    log("coefficient build: %.3f ms, %.0f GB/s (%.1f %% of 8 TB/s, %.1f %% of a %.0f GB/s copy)"
+        % (ms_coef, ach, 100 * ach / 8000.0, 100 * ach / copy_gbs, copy_gbs))
+    return {"stage": "a1-a5: tables, lambda and k_assemble (the W write)", "ms": round(ms_coef, 4),
+            "algorithmic_bytes": alg, "achieved_gbs": round(ach, 1), "peak_gbs": 8000.0,
+            "frac": round(ach / 8000.0, 4), "copy_gbs": round(copy_gbs, 1), "frac_of_copy": round(ach / copy_gbs, 4),
+            "copy": "2 GiB device-to-device, read and write both counted"}
+
+
 def device_leg() -> dict:
     """CU count, and the sustained matrix-core rates of the two instructions the
     contractions run on (FP64 16x16x4 and int8 32x32x32), measured by the
@@ -702,6 +737,7 @@ def main() -> int:
                                "TiO2 (61%), whole H/S build",
         },
     }
+    result["coefficient_build"] = coefficient_leg(case, stage_ms[0])
     if not args.no_factored:
         result["factored"] = factored_leg(args, case, g, tau, T, H, S, ms_step)
     if not args.no_hsdla:
