@@ -286,8 +286,26 @@ def real_leg(args) -> dict:
     imag = (torch.linalg.norm(Hcu.imag) / torch.linalg.norm(Hcu)).item()
     eh = (torch.linalg.norm(torch.triu(Hr) - Hcu.real) / torch.linalg.norm(Hcu.real)).item()
     es = (torch.linalg.norm(torch.triu(Sr) - Scu.real) / torch.linalg.norm(Scu.real)).item()
-    del Hc, Sc, Hr, Sr, Hcu, Scu, ws
+    Hr64, Sr64 = torch.triu(Hr), torch.triu(Sr)
+    del Hc, Sc, Hcu, Scu, ws
     b.close()
+    torch.cuda.empty_cache()
+    # the int8 split form of the real path, against the FP64 real path's outputs
+    int8 = None
+    if args.int8_slices > 0:
+        from paper_1712_07206_amd import HSB_SPLIT_INT8
+        bi = HSBuilder.from_case(case, precision=HSB_SPLIT_INT8, n_slices=args.int8_slices)
+        wsi = bi.workspace(N.HSB_MODE_REAL, [n])
+        ms_i = timed(lambda: bi.forward_real(kf, g, tau, case["partner"], T, Hr, Sr, ws=wsi), reps)
+        ehi = (torch.linalg.norm(torch.triu(Hr) - Hr64) / torch.linalg.norm(Hr64)).item()
+        esi = (torch.linalg.norm(torch.triu(Sr) - Sr64) / torch.linalg.norm(Sr64)).item()
+        log("real-symmetric int8 x%d: %.3f ms (%.2fx the FP64 real path); rel err vs it H %.2e S %.2e"
+            % (args.int8_slices, ms_i, ms_r / ms_i, ehi, esi))
+        int8 = {"slices": args.int8_slices, "ms": round(ms_i, 4), "speedup_vs_fp64_real": round(ms_r / ms_i, 4),
+                "rel_err_vs_fp64_real": {"H": ehi, "S": esi}, "meets_1e-10": bool(ehi <= 1e-10 and esi <= 1e-10)}
+        del wsi
+        bi.close()
+    del Hr, Sr, Hr64, Sr64
     torch.cuda.empty_cache()
     log("real-symmetric %s: complex path %.3f ms, real path %.3f ms (%.2fx), %.2f TFLOP/s on its own %.4g TFLOP; "
         "rel err vs complex H %.2e S %.2e, |Im H|/|H| %.1e" % (case["name"], ms_c, ms_r, ms_c / ms_r,
@@ -296,7 +314,7 @@ def real_leg(args) -> dict:
     return {"workload": case["name"], "n_g": n, "representatives": n_rep, "ms_complex": round(ms_c, 4),
             "ms_real": round(ms_r, 4), "speedup": round(ms_c / ms_r, 4), "flops_real": flops_r,
             "flops_complex": flops_c, "real_tflops": round(flops_r / (ms_r * 1e-3) / 1e12, 4),
-            "complex_imag_rel": imag, "rel_err_vs_complex": {"H": eh, "S": es}}
+            "complex_imag_rel": imag, "rel_err_vs_complex": {"H": eh, "S": es}, "int8_split": int8}
 
 
 def eigen_leg(args) -> dict:

@@ -149,7 +149,11 @@ int hsbuild_forward_factored(hsbuild_t h, const double k_frac[3], int32_t ng, co
  * quarter of the work of hsbuild_forward.  H, S: device double [ng][ng],
  * upper triangle written; equal to the real parts of hsbuild_forward's
  * outputs up to FP64 rounding (undefined if the symmetry does not hold).
- * Other arguments as hsbuild_forward (FP64 whatever the precision).
+ * Other arguments as hsbuild_forward.  A handle created with HSB_FP64 runs
+ * the FP64 contraction; one created with HSB_SPLIT_INT8 runs the int8 split
+ * contraction (the real parts of the split products, to the split path's
+ * error); HSB_SPLIT_BF16 and HSB_SPLIT_FP16 handles get HSB_ERR_UNSUPPORTED
+ * before anything is enqueued.
  * Workspace: hsbuild_workspace_bytes(h, HSB_MODE_REAL, 1, &ng). */
 int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
                          const int32_t* partner, const void* T, double* H, double* S, void* ws, size_t ws_bytes,

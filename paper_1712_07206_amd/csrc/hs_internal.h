@@ -138,6 +138,9 @@ hipError_t launch_split_scales(const double2* W, const double2* Y, const double*
 hipError_t launch_split_slices(int precision, int S, const double2* X, const double* lam, int use_lam, int K,
                                int n_pad, int QK, const double* scale, void* out, hipStream_t s);
 // Upper triangle of C = conj(L)^T R from the slices (C: [n][n]).
+// int8 slices only: C = Re(conj(L)^T R) into a real [n][n] array, upper triangle
+hipError_t launch_hs_split8_real(int S, const void* L, const void* R, const double* scL, const double* scR, int QK,
+                                 int n, int n_pad, int gr, double* C, hipStream_t s);
 hipError_t launch_hs_split(int precision, int S, const void* L, const void* R, const double* scL, const double* scR,
                            int QK, int n, int n_pad, int gr, double2* C, hipStream_t s);
 

@@ -136,9 +136,9 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
     L.W = take((size_t)L.K_pad * np * sizeof(double2));
     L.Y = take((size_t)L.K_pad * np * sizeof(double2));
   }
-  if ((mode == HSB_MODE_FORWARD && h.precision == HSB_FP64) || mode == HSB_MODE_REAL)
+  if ((mode == HSB_MODE_FORWARD || mode == HSB_MODE_REAL) && h.precision == HSB_FP64)
     L.WL = take((size_t)L.K_pad * np * sizeof(double2));
-  if (mode == HSB_MODE_FORWARD && h.precision != HSB_FP64) {
+  if ((mode == HSB_MODE_FORWARD && h.precision != HSB_FP64) || (mode == HSB_MODE_REAL && h.precision == HSB_SPLIT_INT8)) {
     L.K_pad2 = (int)round_up(L.K, 32);
     const size_t elem = h.precision == HSB_SPLIT_INT8 ? 1 : 2;       // bytes per slice value
     const size_t planes = (size_t)2 * h.n_slices * np * L.K_pad2 * elem;  // bytes per sliced operand
@@ -286,6 +286,37 @@ int enqueue_split(hsbuild_t h, const Layout& L, char* w, double2* H, double2* S,
   return launched(h, launch_hs_split(h->precision, h->n_slices, w + L.slL, w + L.slY, sc, sc + 2 * L.n_pad, QK, L.n,
                                      L.n_pad, h->tile_group, H, s),
                   "split contraction (H)");
+}
+
+// Real-symmetric int8 split contraction on the representatives' rows (L.K): column scales and
+// slices as in the complex form, then S = Re(W^H lam W) and H = Re(W^H Y) into real arrays.
+int enqueue_split_real(hsbuild_t h, const Layout& L, char* w, double* H, double* S, hipStream_t s) {
+  const double2* W = (const double2*)(w + L.W);
+  const double2* Y = (const double2*)(w + L.Y);
+  const double* lam = (const double*)(w + L.lam);
+  const double* sc = (const double*)(w + L.scale);
+  const int QK = (int)round_up(L.K, 32) / 16;  // 16-byte units (16 rows of int8) per column
+  int rc = launched(h, launch_split_scales(W, Y, lam, L.K, L.n_pad, (unsigned long long*)(w + L.mx), (double*)sc, s),
+                    "split scales");
+  if (rc) return rc;
+  rc = launched(h, launch_split_slices(HSB_SPLIT_INT8, h->n_slices, W, lam, 0, L.K, L.n_pad, QK, sc, w + L.slL, s),
+                "split slices");
+  if (rc) return rc;
+  rc = launched(h, launch_split_slices(HSB_SPLIT_INT8, h->n_slices, W, lam, 1, L.K, L.n_pad, QK, sc + L.n_pad,
+                                       w + L.slS, s),
+                "split slices");
+  if (rc) return rc;
+  rc = launched(h, launch_split_slices(HSB_SPLIT_INT8, h->n_slices, Y, lam, 0, L.K, L.n_pad, QK, sc + 2 * L.n_pad,
+                                       w + L.slY, s),
+                "split slices");
+  if (rc) return rc;
+  rc = launched(h, launch_hs_split8_real(h->n_slices, w + L.slL, w + L.slS, sc, sc + L.n_pad, QK, L.n, L.n_pad,
+                                         h->tile_group, S, s),
+                "split contraction (real S)");
+  if (rc) return rc;
+  return launched(h, launch_hs_split8_real(h->n_slices, w + L.slL, w + L.slY, sc, sc + 2 * L.n_pad, QK, L.n, L.n_pad,
+                                           h->tile_group, H, s),
+                  "split contraction (real H)");
 }
 
 // Operand builds of the k-points run in kBranches parallel graph branches, each with its own tables.
@@ -679,6 +710,8 @@ int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const 
   if (!k_frac || !g || !tau || !partner || !T || !H || !S)
     return fail(h, HSB_ERR_ARG, "null k_frac, g, tau, partner, T, H or S");
   if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
+  if (h->precision != HSB_FP64 && h->precision != HSB_SPLIT_INT8)
+    return fail(h, HSB_ERR_UNSUPPORTED, "the real-symmetric build has an FP64 and an int8 split form only");
   int rc = check_ng(h, ng);
   if (rc) return rc;
   // representatives: the lower index of each inversion pair (weight 2), atoms paired with themselves (weight 1)
@@ -748,12 +781,16 @@ int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const 
                                     tau_rep, wrow, lam, s),
                 "k_rep_setup");
   if (!rc) rc = launched(h, launch_scale_rows(Y, wrow, Lr.K_pad, L.n_pad, Y, s), "k_scale_rows");
-  double2* WL = (double2*)(w + L.WL);  // S's right operand, lam W (lam with the pair weights)
-  if (!rc) rc = launched(h, launch_scale_rows((const double2*)(w + L.W), lam, Lr.K_pad, L.n_pad, WL, s), "k_scale_rows");
-  if (!rc)
-    rc = launched(h, launch_hs_fp64_real((const double2*)(w + L.W), WL, Y, lam, Lr.K_pad, ng, L.n_pad, h->tile_group,
-                                         h->hs_waves, H, S, ng, s),
-                  "k_hs_fp64 (real)");
+  if (!rc && h->precision == HSB_SPLIT_INT8) {
+    rc = enqueue_split_real(h, Lr, w, H, S, s);
+  } else if (!rc) {
+    double2* WL = (double2*)(w + L.WL);  // S's right operand, lam W (lam with the pair weights)
+    rc = launched(h, launch_scale_rows((const double2*)(w + L.W), lam, Lr.K_pad, L.n_pad, WL, s), "k_scale_rows");
+    if (!rc)
+      rc = launched(h, launch_hs_fp64_real((const double2*)(w + L.W), WL, Y, lam, Lr.K_pad, ng, L.n_pad,
+                                           h->tile_group, h->hs_waves, H, S, ng, s),
+                    "k_hs_fp64 (real)");
+  }
   mark(h, 3, s);
   return rc;
 }

@@ -521,21 +521,24 @@ constexpr int split8_reads(int j) {
 
 // scheduling groups (DS read = 0x100, MFMA = 0x008): the reads of pair j + 1, then the
 // four MFMAs of pair j, so that two pairs' operands are live at a time
-template <int S, int J>
+template <int S, int J, int M>
 __device__ __forceinline__ void split8_schedule() {
   constexpr int NP = S * (S + 1) / 2;
   if constexpr (J < NP) {
     if constexpr (J + 1 < NP) __builtin_amdgcn_sched_group_barrier(0x100, split8_reads<S>(J + 1), 0);
-    __builtin_amdgcn_sched_group_barrier(0x008, 4, 0);
-    split8_schedule<S, J + 1>();
+    __builtin_amdgcn_sched_group_barrier(0x008, M, 0);
+    split8_schedule<S, J + 1, M>();
   }
 }
 
-template <int S>
+// REAL: C = Re(conj(L)^T R), one int32 channel per level (two MFMAs per pair: Re L Re R
+// and Im L Im R), written to a real [n][n] array.
+template <int S, bool REAL>
 __global__ void __launch_bounds__(512, 1) k_hs_split8(const u4* __restrict__ Ls, const u4* __restrict__ Rs,
                                                       const double* __restrict__ scL, const double* __restrict__ scR,
                                                       int QK, int n, int n_pad, int nbr, int num_wg, int gr,
-                                                      d2* __restrict__ C) {
+                                                      void* __restrict__ Cv) {
+  constexpr int NCH = REAL ? 1 : 2;  // int32 channels per level
   constexpr int P = 2 * S;        // planes per operand
   constexpr int CU = 384 * P;     // units per chunk: left P*2*2*64, right P*2*64
   constexpr int NI = 6 * P;       // 64-unit copies per chunk
@@ -583,11 +586,13 @@ __global__ void __launch_bounds__(512, 1) k_hs_split8(const u4* __restrict__ Ls,
                                          (lds_ptr)(&lds[buf][dst[i]]), 16, 0, 0);
   };
 
-  i16v acc[S][2];
+  i16v acc[S][NCH];
 #pragma unroll
   for (int d = 0; d < S; ++d)
 #pragma unroll
-    for (int r = 0; r < 16; ++r) acc[d][0][r] = acc[d][1][r] = 0;
+    for (int ch = 0; ch < NCH; ++ch)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[d][ch][r] = 0;
 
   const int q = lane >> 5, g32 = lane & 31;
   const int lrow = ((wr >> 1) * 2 + q) * 64 + (wr & 1) * 32 + g32;
@@ -604,17 +609,27 @@ __global__ void __launch_bounds__(512, 1) k_hs_split8(const u4* __restrict__ Ls,
 #pragma unroll
       for (int d = 0; d < S; ++d) {
         vre += __builtin_ldexp((double)acc[d][0][r], -7 * d);
-        vim += __builtin_ldexp((double)acc[d][1][r], -7 * d);
         acc[d][0][r] = 0;
-        acc[d][1][r] = 0;
+        if constexpr (!REAL) {
+          vim += __builtin_ldexp((double)acc[d][1][r], -7 * d);
+          acc[d][1][r] = 0;
+        }
       }
       const int row = rb + 8 * (r >> 2) + (r & 3);
       const int col = cb;
       if (row < n && col < n && col >= row) {
         const double sc = 0x1p-12 * scL[row] * scR[col];
-        d2 v = d2{vre * sc, vim * sc};
-        if (!first) v += C[(int64_t)row * n + col];
-        C[(int64_t)row * n + col] = v;
+        if constexpr (REAL) {
+          double* C = (double*)Cv;
+          double v = vre * sc;
+          if (!first) v += C[(int64_t)row * n + col];
+          C[(int64_t)row * n + col] = v;
+        } else {
+          d2* C = (d2*)Cv;
+          d2 v = d2{vre * sc, vim * sc};
+          if (!first) v += C[(int64_t)row * n + col];
+          C[(int64_t)row * n + col] = v;
+        }
       }
     }
   };
@@ -637,7 +652,8 @@ __global__ void __launch_bounds__(512, 1) k_hs_split8(const u4* __restrict__ Ls,
     for (int si = 0; si < S; ++si) {
       const u4 lr = B[lrow + (2 * si) * 256];
       const u4 li = B[lrow + (2 * si + 1) * 256];
-      const u4 ln = neg_bytes(li);
+      u4 ln;
+      if constexpr (!REAL) ln = neg_bytes(li);
       // the other right slices are re-read for every left slice (an opaque index keeps the
       // reads from being merged, which would hold all 2S right operands live through the chunk)
       int rc = rcol;
@@ -648,28 +664,34 @@ __global__ void __launch_bounds__(512, 1) k_hs_split8(const u4* __restrict__ Ls,
         const u4 rr = ti == 0 ? rr0 : ti == 1 ? rr1 : BR[(2 * ti) * 128];
         const u4 ri = ti == 0 ? ri0 : ti == 1 ? ri1 : BR[(2 * ti + 1) * 128];
         const int d = si + ti;
-        acc[d][0] = mfma_i8(lr, rr, acc[d][0]);
-        acc[d][1] = mfma_i8(lr, ri, acc[d][1]);
-        acc[d][0] = mfma_i8(li, ri, acc[d][0]);
-        acc[d][1] = mfma_i8(ln, rr, acc[d][1]);
+        if constexpr (REAL) {
+          acc[d][0] = mfma_i8(lr, rr, acc[d][0]);
+          acc[d][0] = mfma_i8(li, ri, acc[d][0]);
+        } else {
+          acc[d][0] = mfma_i8(lr, rr, acc[d][0]);
+          acc[d][1] = mfma_i8(lr, ri, acc[d][1]);
+          acc[d][0] = mfma_i8(li, ri, acc[d][0]);
+          acc[d][1] = mfma_i8(ln, rr, acc[d][1]);
+        }
       }
     }
     __builtin_amdgcn_sched_group_barrier(0x100, split8_reads<S>(0), 0);
-    split8_schedule<S, 0>();
+    split8_schedule<S, 0, REAL ? 2 : 4>();
     if ((c + 1) % kFlush8 == 0 || c + 1 == nchunks) flush(c < kFlush8);
   }
 }
 
+template <bool REAL>
 hipError_t launch_hs_split8(int S, const void* L, const void* R, const double* scL, const double* scR, int QK, int n,
-                            int n_pad, int gr, double2* C, hipStream_t s) {
+                            int n_pad, int gr, void* C, hipStream_t s) {
   const int nbr = n_pad / SBM;
   const int num_wg = nbr * (nbr + 1);
   dim3 grid(num_wg), block(512);
   switch (S) {
-    case 3: hipLaunchKernelGGL((k_hs_split8<3>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, (d2*)C); break;
-    case 4: hipLaunchKernelGGL((k_hs_split8<4>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, (d2*)C); break;
-    case 5: hipLaunchKernelGGL((k_hs_split8<5>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, (d2*)C); break;
-    case 6: hipLaunchKernelGGL((k_hs_split8<6>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, (d2*)C); break;
+    case 3: hipLaunchKernelGGL((k_hs_split8<3, REAL>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, C); break;
+    case 4: hipLaunchKernelGGL((k_hs_split8<4, REAL>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, C); break;
+    case 5: hipLaunchKernelGGL((k_hs_split8<5, REAL>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, C); break;
+    case 6: hipLaunchKernelGGL((k_hs_split8<6, REAL>), grid, block, 0, s, (const u4*)L, (const u4*)R, scL, scR, QK, n, n_pad, nbr, num_wg, gr, C); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -760,9 +782,14 @@ hipError_t launch_split_slices(int precision, int S, const double2* X, const dou
 
 hipError_t launch_hs_split(int precision, int S, const void* L, const void* R, const double* scL, const double* scR,
                            int QK, int n, int n_pad, int gr, double2* C, hipStream_t s) {
-  if (precision == HSB_SPLIT_INT8) return launch_hs_split8(S, L, R, scL, scR, QK, n, n_pad, gr, C, s);
+  if (precision == HSB_SPLIT_INT8) return launch_hs_split8<false>(S, L, R, scL, scR, QK, n, n_pad, gr, C, s);
   if (precision == HSB_SPLIT_BF16) return launch_hs_split2(S, L, R, scL, scR, QK, n, n_pad, gr, C, s);
   return launch_hs_split_t<_Float16>(S, L, R, scL, scR, QK, n, n_pad, C, s);
+}
+
+hipError_t launch_hs_split8_real(int S, const void* L, const void* R, const double* scL, const double* scR, int QK,
+                                 int n, int n_pad, int gr, double* C, hipStream_t s) {
+  return launch_hs_split8<true>(S, L, R, scL, scR, QK, n, n_pad, gr, C, s);
 }
 
 }  // namespace hsb

@@ -125,3 +125,47 @@ def test_real_wave_variants_bitwise_equal():
         torch.cuda.synchronize()
         out.append((H.cpu().numpy(), S.cpu().numpy()))
     assert np.array_equal(out[0][0], out[1][0]) and np.array_equal(out[0][1], out[1][1])
+
+
+def _real_int8(case, poison=True):
+    from paper_1712_07206_amd import HSB_SPLIT_INT8
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    n = case["n_g"]
+    b = HSBuilder.from_case(case, precision=HSB_SPLIT_INT8, n_slices=6)
+    g, tau, T = case_tensors(case)
+    H = torch.full((n, n), float("nan") if poison else 0.0, dtype=torch.float64, device="cuda")
+    S = H.clone()
+    b.forward_real(case["k_frac"], g, tau, case["partner"], T, H, S)
+    torch.cuda.synchronize()
+    return H.cpu().numpy(), S.cpu().numpy()
+
+
+@pytest.mark.parametrize("idx,n_g", [(5, None), (5, 1), (5, 7), (5, 300), (6, 3000)])
+def test_real_int8_split_matches_oracle(idx, n_g):
+    """The int8 split form of the real path (6 slices of 7 bits): the split
+    bar, relative Frobenius error <= 1e-10 against the oracle's real parts."""
+    case = make_case(idx, n_g=n_g)
+    print("case", idx, "n_g", case["n_g"], flush=True)
+    H, S = _real_int8(case)
+    n = case["n_g"]
+    il = np.tril_indices(n, -1)
+    assert np.all(np.isnan(H[il])) and np.all(np.isnan(S[il])), "strict lower triangle written"
+    Hr, Sr = o.hs(case)
+    eh, es = rel(_full(H), Hr.real), rel(_full(S), Sr.real)
+    print("real int8 split vs oracle: H %.3e S %.3e" % (eh, es))
+    assert eh <= 1e-10 and es <= 1e-10
+
+
+def test_real_rejects_16bit_split_handles():
+    """The real path has FP64 and int8 forms only: a BF16 handle gets
+    HSB_ERR_UNSUPPORTED before anything is enqueued."""
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    case = make_case(5, n_g=7)
+    b = HSBuilder.from_case(case, precision=N.HSB_SPLIT_BF16, n_slices=5)
+    g, tau, T = case_tensors(case)
+    H = torch.zeros((7, 7), dtype=torch.float64, device="cuda")
+    S = torch.zeros_like(H)
+    with pytest.raises(N.HSBuildError) as err:
+        b.forward_real(case["k_frac"], g, tau, case["partner"], T, H, S)
+    assert err.value.code == N.HSB_ERR_UNSUPPORTED
