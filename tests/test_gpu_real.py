@@ -169,3 +169,31 @@ def test_real_rejects_16bit_split_handles():
     with pytest.raises(N.HSBuildError) as err:
         b.forward_real(case["k_frac"], g, tau, case["partner"], T, H, S)
     assert err.value.code == N.HSB_ERR_UNSUPPORTED
+
+
+def test_real_int8_full_size_vs_fp64_real():
+    """Full size (N_G = 12000, the bench's inversion cell and launch
+    configuration): the int8 form of the real path against the FP64 one, on
+    the device, to the split bar."""
+    from paper_1712_07206_amd import HSB_SPLIT_INT8
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    case = make_case(6)
+    n = case["n_g"]
+    g, tau, T = case_tensors(case)
+    b = HSBuilder.from_case(case)
+    H64 = torch.zeros((n, n), dtype=torch.float64, device="cuda")
+    S64 = torch.zeros_like(H64)
+    b.forward_real(case["k_frac"], g, tau, case["partner"], T, H64, S64)
+    b.close()
+    del b
+    torch.cuda.empty_cache()
+    bi = HSBuilder.from_case(case, precision=HSB_SPLIT_INT8, n_slices=6)
+    H8 = torch.zeros_like(H64)
+    S8 = torch.zeros_like(H64)
+    bi.forward_real(case["k_frac"], g, tau, case["partner"], T, H8, S8)
+    torch.cuda.synchronize()
+    H64, S64, H8, S8 = torch.triu(H64), torch.triu(S64), torch.triu(H8), torch.triu(S8)
+    eh = (torch.linalg.norm(H8 - H64) / torch.linalg.norm(H64)).item()
+    es = (torch.linalg.norm(S8 - S64) / torch.linalg.norm(S64)).item()
+    print("full-size real int8 vs fp64 real: H %.3e S %.3e" % (eh, es))
+    assert eh <= 1e-10 and es <= 1e-10
