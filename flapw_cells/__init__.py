@@ -7,7 +7,8 @@ contains none of the arithmetic that turns those inputs into the matching
 coefficients, H or S; both the oracle and the GPU library consume the arrays
 it returns and recompute everything else on their own.
 """
-from .cells import CONFIGS, CellConfig, make_case, make_batch_case, basis_for_k, sub_case, perturb_positions
+from .cells import CONFIGS, CellConfig, make_case, make_batch_case, basis_for_k, sub_case, perturb_positions, \
+    shell_sizes, at_k
 
 __all__ = ["CONFIGS", "CellConfig", "make_case", "make_batch_case", "basis_for_k", "sub_case",
-           "perturb_positions"]
+           "perturb_positions", "shell_sizes", "at_k"]

@@ -306,6 +306,36 @@ def sub_case(case: dict, k: int) -> dict:
     return out
 
 
+def shell_sizes(lattice: np.ndarray, k_frac, upto: int):
+    """The basis sizes up to `upto` at which the cut-off falls between two
+    shells of |k+G| (the sizes basis_for_k accepts): at a high-symmetry k,
+    such as k = 0, most sizes split a shell of equal norms."""
+    lattice = np.asarray(lattice, dtype=np.float64)
+    bvec = 2.0 * np.pi * np.linalg.inv(lattice).T
+    omega = abs(np.linalg.det(lattice))
+    radius = 1.5 * (6.0 * np.pi ** 2 * (upto + 1) / omega) ** (1.0 / 3.0) + 1.0
+    nmax = np.ceil(radius * np.linalg.norm(lattice, axis=1) / (2.0 * np.pi) + 1.0).astype(int)
+    grid = np.stack(np.meshgrid(*[np.arange(-m, m + 1) for m in nmax], indexing="ij"), axis=-1).reshape(-1, 3)
+    kvec = (grid + np.asarray(k_frac, dtype=np.float64)) @ bvec
+    norm = np.sort(np.sqrt(np.einsum("ij,ij->i", kvec, kvec)))
+    assert norm[upto] < radius
+    # norms of one shell can differ in the last bits (summation order): a gap must be real
+    return [n for n in range(1, upto + 1) if norm[n] > norm[n - 1] * (1.0 + 1e-9)]
+
+
+def at_k(case: dict, k_frac, n_g: Optional[int] = None) -> dict:
+    """A copy of a single-k case moved to the k-point k_frac (reciprocal
+    basis): the same cell, atoms, radial values and T, with the basis of that
+    k chosen by the rule above (n_g must close a shell; see shell_sizes).
+    The loss matrices of the loss workload are dropped."""
+    n = int(case["n_g"] if n_g is None else n_g)
+    kf = np.asarray(k_frac, dtype=np.float64).reshape(3).copy()
+    g, kmax = basis_for_k(case["lattice"], kf, n)
+    out = {key: val for key, val in case.items() if key not in ("W", "V")}
+    out.update(k_frac=kf, g=g, n_g=n, k_max=kmax)
+    return out
+
+
 def perturb_positions(case: dict, delta: np.ndarray) -> dict:
     """A copy of `case` with tau replaced by tau + delta (cartesian)."""
     out = dict(case)

@@ -9,7 +9,7 @@ import numpy as np
 import pytest
 from scipy import special
 
-from flapw_cells import make_case, perturb_positions
+from flapw_cells import at_k, make_case, perturb_positions
 from oracle import hs_oracle as o
 
 
@@ -135,7 +135,31 @@ def pin_tau_fd(mod):
     return worst <= 1e-7 * np.abs(gtau).max()
 
 
-PINS = [pin_plane_wave, pin_matching, pin_overlap_closed_form, pin_hamiltonian_diag_blocks, pin_covariance,
+def pin_gamma(mod):
+    """k = 0: the K = 0 column of the coefficients in closed form from the radial data
+    (only A_00 = sqrt(4 pi/Omega) udot'/W_0 and B_00 = -sqrt(4 pi/Omega) u'/W_0 nonzero),
+    and S_00 = (4 pi/Omega) sum_a (a_0^2 + |udot_0|^2 b_0^2)."""
+    case = at_k(make_case(1, n_g=50), np.zeros(3), 123)
+    coef = mod.coefficients(case)
+    if not np.all(np.isfinite(coef)):
+        return False
+    pre = np.sqrt(4 * np.pi / case["omega"])
+    s00 = 0.0
+    for a in range(case["n_atoms"]):
+        t = int(case["atom_type"][a])
+        u, du, ud, dud = case["radial"][t, 0]
+        w = u * dud - ud * du
+        a0, b0 = pre * dud / w, -pre * du / w
+        if abs(coef[a, 0, 0, 0] - a0) > 1e-14 * abs(a0) or abs(coef[a, 1, 0, 0] - b0) > 1e-14 * abs(b0):
+            return False
+        if np.abs(coef[a, :, 1:, 0]).max() > 0.0:
+            return False
+        s00 += a0 * a0 + case["udot_norm2"][t, 0] * b0 * b0
+    S = mod.overlap(case, coef)
+    return abs(S[0, 0] - s00) <= 1e-13 * s00
+
+
+PINS = [pin_gamma, pin_plane_wave, pin_matching, pin_overlap_closed_form, pin_hamiltonian_diag_blocks, pin_covariance,
         pin_tau_fd]
 
 
@@ -169,6 +193,15 @@ def _mutants():
     def t_transposed(case, coef):
         return orig_ham(dict(case, T=np.transpose(case["T"], (0, 2, 1))), coef)
 
+    def no_zero_guard(kvec, l_max):
+        # K_hat = K / |K| taken without the K = 0 rule: NaN angles at K = 0
+        kn = np.linalg.norm(kvec, axis=1)
+        with np.errstate(invalid="ignore", divide="ignore"):
+            theta = np.arccos(kvec[:, 2] / kn)
+        phi = np.mod(np.arctan2(kvec[:, 1], kvec[:, 0]), 2 * np.pi)
+        return np.stack([(1j ** l) * np.conj(special.sph_harm_y(l, m, theta, phi))
+                         for l in range(l_max + 1) for m in range(-l, l + 1)])
+
     def grad_sign(case, Wm, Vm):
         gT, gtau = orig_grad(case, Wm, Vm)
         return gT, -gtau
@@ -176,7 +209,8 @@ def _mutants():
     return {"angular without conj": ("angular_factor", no_conj), "angular without i^l": ("angular_factor", no_il),
             "a and b swapped": ("matching", swap_ab), "phase sign flipped": ("coefficients", phase_sign),
             "1/sqrt(Omega) squared": ("coefficients", omega_norm), "B term dropped from S": ("overlap", no_b_overlap),
-            "T transposed in H": ("hamiltonian", t_transposed), "tau gradient sign": ("loss_gradients", grad_sign)}
+            "T transposed in H": ("hamiltonian", t_transposed), "tau gradient sign": ("loss_gradients", grad_sign),
+            "no K = 0 rule for the angles": ("angular_factor", no_zero_guard)}
 
 
 def test_unmutated_oracle_passes_every_pin():

@@ -11,7 +11,7 @@ import numpy as np
 import pytest
 from scipy import special
 
-from flapw_cells import make_case, perturb_positions
+from flapw_cells import at_k, make_case, perturb_positions
 from oracle import hs_oracle as o
 
 
@@ -154,6 +154,133 @@ def test_boundary_continuity_plane_wave():
         r = case["tau"][a][None, :] + R * pts
         pw = np.exp(1j * kvec @ r.T) / np.sqrt(case["omega"])
         np.testing.assert_allclose(val, pw, rtol=0, atol=1e-13)
+
+
+# ---- k on a lattice point: the basis holds K = k + G = 0 (Sec. 2.1) ---------------------
+# At K = 0 only l = 0 survives: j_0(0) = 1, j_l(0) = 0 for l >= 1 and |K| j_l'(0) = 0, so
+# a_0 = udot'/W_0, b_0 = -u'/W_0 (W_0 = u udot' - udot u'), every other a_l, b_l is 0, the
+# phase is 1 and Y_00 = 1/sqrt(4 pi) whatever direction K_hat is given.
+
+def gamma_case(index=1, n_g=123):
+    """Workload `index` moved to k = 0 with a closed-shell basis (G = 0 first)."""
+    case = at_k(make_case(index, n_g=50), np.zeros(3), n_g)
+    assert np.all(case["g"][0] == 0)
+    return case
+
+
+def _w0(radial_tl):
+    u, du, ud, dud = radial_tl
+    return u * dud - ud * du
+
+
+def test_matching_at_zero_argument():
+    """x = 0 in the matching: a_0 = udot'/W_0, b_0 = -u'/W_0 and a_l = b_l = 0 for l >= 1
+    (the value and slope of the plane wave at K = 0 are 1 and 0)."""
+    radial = np.random.default_rng(31).uniform(0.5, 1.5, (2, 13, 4))
+    a, b = o.matching(np.zeros(3), np.array([1.2, 2.3]), radial)
+    for t in range(2):
+        u, du, ud, dud = radial[t, 0]
+        np.testing.assert_allclose(a[t, 0], dud / _w0(radial[t, 0]), rtol=1e-15, atol=0)
+        np.testing.assert_allclose(b[t, 0], -du / _w0(radial[t, 0]), rtol=1e-15, atol=0)
+        assert np.all(a[t, 1:] == 0.0) and np.all(b[t, 1:] == 0.0)
+
+
+def test_gamma_coefficients_of_g0_closed_form():
+    """The G = 0 column at k = 0: A_00 = sqrt(4 pi/Omega) a_0 and B_00 = sqrt(4 pi/Omega) b_0
+    for every atom (phase 1, whatever its position), every other (l, m) exactly 0; the
+    values come from the radial data alone."""
+    case = gamma_case(1, 123)
+    coef = o.coefficients(case)
+    pre = np.sqrt(4 * np.pi / case["omega"])
+    for a in range(case["n_atoms"]):
+        r = case["radial"][int(case["atom_type"][a]), 0]
+        u, du, ud, dud = r
+        np.testing.assert_allclose(coef[a, 0, 0, 0], pre * dud / _w0(r), rtol=1e-14, atol=0)
+        np.testing.assert_allclose(coef[a, 1, 0, 0], -pre * du / _w0(r), rtol=1e-14, atol=0)
+        assert np.all(coef[a, :, 1:, 0] == 0.0)
+
+
+def test_gamma_boundary_continuity_plane_wave():
+    """The muffin-tin expansion equals the plane wave on the sphere at k = 0, the K = 0
+    column (constant 1/sqrt(Omega)) included; |K| R <= 1 with l_max 14 as above."""
+    case = gamma_case(0, 123)
+    l_max = 14
+    case = dict(case, l_max=l_max)
+    rng = np.random.default_rng(17)
+    case["radial"] = rng.uniform(0.5, 1.5, (1, l_max + 1, 4))
+    kvec = o.k_plus_g(case["lattice"], case["k_frac"], case["g"])
+    keep = np.linalg.norm(kvec, axis=1) * case["r_mt"][0] <= 1.0
+    assert keep[0] and keep.sum() >= 7
+    coef = o.coefficients(case, g=case["g"][keep])
+    kvec = kvec[keep]
+    R = case["r_mt"][0]
+    pts = rng.normal(size=(25, 3))
+    pts /= np.linalg.norm(pts, axis=1)[:, None]
+    theta = np.arccos(pts[:, 2])
+    phi = np.mod(np.arctan2(pts[:, 1], pts[:, 0]), 2 * np.pi)
+    Ypts = np.stack([special.sph_harm_y(l, m, theta, phi) for l in range(l_max + 1) for m in range(-l, l + 1)])
+    u = np.concatenate([[case["radial"][0, l, 0]] * (2 * l + 1) for l in range(l_max + 1)])
+    ud = np.concatenate([[case["radial"][0, l, 2]] * (2 * l + 1) for l in range(l_max + 1)])
+    for a in range(len(case["tau"])):
+        val = (coef[a, 0] * u[:, None] + coef[a, 1] * ud[:, None]).T @ Ypts
+        pw = np.exp(1j * kvec @ (case["tau"][a][None, :] + R * pts).T) / np.sqrt(case["omega"])
+        np.testing.assert_allclose(val, pw, rtol=0, atol=1e-13)
+        np.testing.assert_allclose(val[0], 1.0 / np.sqrt(case["omega"]), rtol=0, atol=1e-15)
+
+
+def test_gamma_overlap_and_hamiltonian_closed_form():
+    """At k = 0: the whole S by the Legendre closed form (only l = 0 enters the K = 0 row
+    and column, so the K_hat convention cannot matter), the row of S and of H at G' = 0 in
+    closed form from the radial data, the phases and T's (l = 0) entries alone:
+      S_0G = (4 pi/Omega) sum_a e^{iK_G.tau_a} [a_0(0) a_0(K_G) + |udot_0|^2 b_0(0) b_0(K_G)],
+      H_0G = (4 pi/Omega) sum_a e^{iK_G.tau_a} [a_0(0), b_0(0)] T_t[(A|B,00), (A|B,L)] [A|B coefficients],
+    and S_00, H_00 from the radial values only."""
+    case = gamma_case(1, 123)
+    kvec = o.k_plus_g(case["lattice"], case["k_frac"], case["g"])
+    assert np.linalg.norm(kvec[0]) == 0.0
+    coef = o.coefficients(case)
+    H, S = o.hamiltonian(case, coef), o.overlap(case, coef)
+    # Legendre form of S with the matching by an independent Cramer solve at every G
+    kn = np.linalg.norm(kvec, axis=1)
+    a = np.empty((case["n_types"], case["l_max"] + 1, len(kn)))
+    b = np.empty_like(a)
+    for t in range(case["n_types"]):
+        for l in range(case["l_max"] + 1):
+            u, du, ud, dud = case["radial"][t, l]
+            x = kn * case["r_mt"][t]
+            rhs = np.stack([special.spherical_jn(l, x), kn * special.spherical_jn(l, x, derivative=True)])
+            a[t, l], b[t, l] = np.linalg.solve(np.array([[u, ud], [du, dud]]), rhs)
+    nrm = case["udot_norm2"]
+    ref = _legendre_form(case, a, b, kvec, lambda t, l, al, bl: np.outer(al, al) + nrm[t, l] * np.outer(bl, bl))
+    assert rel(S, ref) < 1e-13
+    # row G' = 0 of S and H, and the (0, 0) entries
+    pre2 = 4 * np.pi / case["omega"]
+    n_l = case["n_l"]
+    s_row = np.zeros(case["n_g"], dtype=np.complex128)
+    h_row = np.zeros(case["n_g"], dtype=np.complex128)
+    s00 = h00 = 0.0
+    for at in range(case["n_atoms"]):
+        t = int(case["atom_type"][at])
+        r = case["radial"][t, 0]
+        a0, b0 = r[3] / _w0(r), -r[1] / _w0(r)
+        ph = np.exp(1j * (kvec @ case["tau"][at]))
+        s_row += pre2 * ph * (a0 * a[t, 0] + nrm[t, 0] * b0 * b[t, 0])
+        Tt = case["T"][t]
+        Wa = coef[at].reshape(2 * n_l, -1)
+        h_row += np.sqrt(pre2) * (a0 * Tt[0] + b0 * Tt[n_l]) @ Wa  # conj of a real row
+        s00 += pre2 * (a0 * a0 + nrm[t, 0] * b0 * b0)
+        h00 += pre2 * (a0 * a0 * Tt[0, 0].real + 2 * a0 * b0 * Tt[0, n_l].real + b0 * b0 * Tt[n_l, n_l].real)
+    assert rel(S[0], s_row) < 1e-13 and rel(H[0], h_row) < 1e-13
+    assert abs(S[0, 0] - s00) <= 1e-14 * abs(s00) and abs(H[0, 0] - h00) <= 1e-13 * abs(h00)
+
+
+def test_gamma_hermitian_and_translation_invariant():
+    case = gamma_case(0, 57)
+    H, S = o.hs(case)
+    assert rel(H, H.conj().T) < 1e-15 and rel(S, S.conj().T) < 1e-15
+    shift = np.tile(case["lattice"][0] - 2 * case["lattice"][2], (case["n_atoms"], 1))
+    H2, S2 = o.hs(perturb_positions(case, shift))
+    assert rel(H2, H) < 1e-13 and rel(S2, S) < 1e-13
 
 
 # ---- closed forms of S and H ---------------------------------------------------------
