@@ -208,9 +208,19 @@ int hsbuild_backward(hsbuild_t h, const double k_frac[3], int32_t ng, const int3
                      const void* T, const void* gH, const void* gS, void* gT, double* gtau, void* ws,
                      size_t ws_bytes, void* stream);
 
-/* H and S of n_k k-points sharing tau and T.  k_frac: host double[n_k][3];
- * ng: host int32[n_k]; g: device int32, the n_k G lists concatenated;
- * out_off: host int64[n_k], element offsets of each k's ng x ng block in H and S. */
+/* H and S of n_k k-points sharing tau and T: Sec. 2.1 sets up one basis, and
+ * one pair H(k), S(k), per k-point of the Brillouin-zone sampling, each with
+ * its own basis size N_G(k).  k_frac: host double[n_k][3]; ng: host
+ * int32[n_k]; g: device int32, the n_k G lists concatenated in k order;
+ * out_off: host int64[n_k], element offsets of each k's ng x ng block in H and
+ * S (blocks must not overlap: HSB_ERR_SHAPE).  Each block holds exactly what
+ * hsbuild_forward writes for that k (bitwise, with the same options), upper
+ * triangle only.  FP64 only: a handle with a split precision gets
+ * HSB_ERR_UNSUPPORTED.  The calls are recorded once into a hipGraph, replayed
+ * while n_k, k_frac, ng, out_off and the device pointers stay the same (the
+ * graph reads g, tau and T at each replay, so their contents may change);
+ * any other change, or hsbuild_set_option, records it again.
+ * Workspace: hsbuild_workspace_bytes(h, HSB_MODE_BATCH, n_k, ng). */
 int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t* ng, const int32_t* g,
                   const int64_t* out_off, const double* tau, const void* T, void* H, void* S, void* ws,
                   size_t ws_bytes, void* stream);

@@ -18,9 +18,10 @@
 // rows of E), then W0_t against Y0_t and Lam_t W0_t together (K = 2 N_L, the
 // left operand shared), and folds M_H * P and M_S * P into the running H and S
 // tiles in registers; nothing but the final tile goes back to HBM.  All
-// contractions are complex FP64 on v_mfma_f64_16x16x4f64; rows are staged 16 at
-// a time through double-buffered LDS with a register prefetch of the next
-// chunk, which may belong to the next phase or type.
+// contractions are complex FP64 on v_mfma_f64_16x16x4f64; rows are copied 16 at
+// a time straight into double-buffered LDS (global_load_lds, no staging
+// registers), the next chunk's copies issued while the current one is
+// contracted; the next chunk may belong to the next phase or type.
 #include "hs_internal.h"
 #include "tiles.h"
 

@@ -584,8 +584,7 @@ hipError_t launch_hs_fp64(const double2* W, const double2* WL, const double2* Y,
   const int num_wg = hs_tiles(n_pad);  // two 128 x 64 tiles per upper-triangle 128 x 128 super-tile
   if (waves == 8)
     hipLaunchKernelGGL((k_hs_fp64<4, false>), dim3(num_wg), dim3(512), 0, s, (const d2*)W, (const d2*)WL,
-                       (const d2*)Y, (const double*)nullptr, K_pad, n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S,
-                       ldh);
+                       (const d2*)Y, lam, K_pad, n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
   else
     hipLaunchKernelGGL((k_hs_fp64<2, false>), dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)WL,
                        (const d2*)Y, lam, K_pad, n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
@@ -601,7 +600,7 @@ hipError_t launch_hs_fp64_real(const double2* W, const double2* WL, const double
     hipLaunchKernelGGL(k_hs_real, dim3(num_wg / 2), dim3(512), 0, s, (const d2*)W, (const d2*)WL, (const d2*)Y, K_pad,
                        n, n_pad, nbr, num_wg / 2, gr, H, S, ldh);
   else
-    hipLaunchKernelGGL((k_hs_fp64<2, true>), dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)nullptr,
+    hipLaunchKernelGGL((k_hs_fp64<2, true>), dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)WL,
                        (const d2*)Y, lam, K_pad, n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
   return hipGetLastError();
 }

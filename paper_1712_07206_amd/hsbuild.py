@@ -263,11 +263,15 @@ class HSBuilder:
         if len(g_list) != n_k:
             raise ValueError("one G list per k-point")
         ng = np.array([int(x.shape[0]) for x in g_list], dtype=np.int32)
-        gkey = tuple((int(x.data_ptr()), int(x.shape[0])) for x in g_list)
+        gkey = tuple(int(x.shape[0]) for x in g_list)
+        g_in = [_dev(x, torch.int32, "g", (int(x.shape[0]), 3)) for x in g_list]
         if getattr(self, "_gcat_key", None) == gkey:
-            g_cat = self._batch_keep  # same G lists: keep the buffer the captured graph refers to
+            # same sizes: refresh the buffer the captured graph refers to (its address stays, so
+            # the graph is still replayed, and it reads the lists as they are now)
+            g_cat = self._batch_keep
+            torch.cat(g_in, out=g_cat)
         else:
-            g_cat = _dev(torch.cat([_dev(x, torch.int32, "g") for x in g_list]), torch.int32, "g")
+            g_cat = _dev(torch.cat(g_in), torch.int32, "g")
         tau = _dev(tau, torch.float64, "tau", (self.n_atoms, 3))
         T = _dev(T, torch.complex128, "T", (self.n_types, 2 * self.n_l, 2 * self.n_l))
         if out_off is None:

@@ -96,6 +96,36 @@ def test_batch_graph_reuse_and_recapture():
     assert np.array_equal(H[:n0 * n0].reshape(n0, n0).cpu().numpy()[iu], h0.cpu().numpy()[iu])
 
 
+def test_batch_sees_g_lists_changed_in_place():
+    """The captured graph reads the G lists through the binding's own concatenated copy:
+    a list changed in place (same size, so the same graph is replayed) or replaced by a
+    new tensor of the same size must reach the next call."""
+    case = make_batch_case(3, n_k=3)
+    b, tau, T, gl = _setup(case)
+    b.batch(case["k_frac"], gl, tau, T)
+    # reverse the order of k-point 1's G list in place: its H becomes P^T H P
+    gl[1].copy_(torch.flip(gl[1], dims=[0]))
+    # and give k-point 2 a fresh tensor holding its list in another order
+    perm = np.random.default_rng(4).permutation(int(case["n_g"][2]))
+    gl[2] = torch.as_tensor(np.ascontiguousarray(case["g"][2][perm]), device="cuda")
+    H, S, off = b.batch(case["k_frac"], gl, tau, T)
+    torch.cuda.synchronize()
+    Hc, Sc = H.cpu().numpy(), S.cpu().numpy()
+    for k in range(3):
+        n = int(case["n_g"][k])
+        h1, s1 = b.forward(case["k_frac"][k], gl[k], tau, T)
+        iu = np.triu_indices(n)
+        assert np.array_equal(_block(Hc, off[k], n)[iu], h1.cpu().numpy()[iu]), k
+        assert np.array_equal(_block(Sc, off[k], n)[iu], s1.cpu().numpy()[iu]), k
+    # and the reordered block is the permuted original (a check that the new list was used)
+    n1 = int(case["n_g"][1])
+    sub = sub_case(case, 1)
+    sub["g"] = np.ascontiguousarray(case["g"][1][::-1])
+    Hr, _ = o.hs(sub)
+    e = np.linalg.norm(_full(_block(Hc, off[1], n1)) - Hr) / np.linalg.norm(Hr)
+    assert e <= 1e-12, e
+
+
 def test_batch_full_64k_against_oracle():
     """The full multi-k workload (64 k-points, N_G 2800-3400, 32 atoms, l_max = 8):
     the k-points with the smallest and largest N_G and two others vs the oracle."""
