@@ -124,6 +124,24 @@ int hsbuild_coefficients(hsbuild_t h, const double k_frac[3], int32_t ng, const 
 int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
                     const void* T, void* H, void* S, void* ws, size_t ws_bytes, void* stream);
 
+/* H and S of one k-point exactly as hsbuild_forward (same arguments, results,
+ * precision handling and errors), for callers that cannot allocate device
+ * memory: code under hipGraph capture, tight serving loops, harnesses that
+ * forbid hipMalloc.  There is no workspace argument: the call runs in a device
+ * array the library holds, HSB_STATIC_SCRATCH_BYTES long, one copy per GPU,
+ * kept from the library's first use on that GPU until the process ends.  The
+ * call allocates nothing (no hipMalloc, hipFree or allocating library call).
+ * A problem whose hsbuild_workspace_bytes(h, HSB_MODE_FORWARD, 1, &ng) exceeds
+ * HSB_STATIC_SCRATCH_BYTES gets HSB_ERR_WORKSPACE before anything is enqueued
+ * (use hsbuild_forward with a caller workspace for it).  Every call on one GPU
+ * uses that GPU's one array, whose contents stay from the last call (each call
+ * overwrites every byte it reads first): calls that may overlap on one GPU --
+ * on different streams, from different handles or threads without ordering --
+ * race and give undefined results. */
+#define HSB_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+int hsbuild_forward_static(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
+                           const void* T, void* H, void* S, void* stream);
+
 /* H and S of one k-point by the type-factored ("compressed") contraction,
  * the compression of A and B that Sec. 7 proposes: each atom's coefficients
  * are its type's coefficients at the origin times the structure phase

@@ -43,7 +43,9 @@ EXPORTS = ("hsbuild_create", "hsbuild_destroy", "hsbuild_workspace_bytes", "hsbu
            "hsbuild_backward",
            "hsbuild_batch", "hsbuild_last_error",
            "hsbuild_host_bessel", "hsbuild_host_angular", "hsbuild_set_timing", "hsbuild_stage_times",
-           "hsbuild_set_option", "hsbuild_get_option", "hsbuild_mfma_probe")
+           "hsbuild_set_option", "hsbuild_get_option", "hsbuild_mfma_probe", "hsbuild_forward_static")
+
+HSB_STATIC_SCRATCH_BYTES = 256 << 20
 
 HSB_OPT_TILE_GROUP = 1
 HSB_OPT_HS_WAVES = 2
@@ -89,6 +91,9 @@ def lib():
     L.hsbuild_forward.argtypes = [c_void_p, POINTER(c_double), c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_size_t, c_void_p]
     L.hsbuild_forward.restype = c_int
+    L.hsbuild_forward_static.argtypes = [c_void_p, POINTER(c_double), c_int32, c_void_p, c_void_p, c_void_p,
+                                         c_void_p, c_void_p, c_void_p]
+    L.hsbuild_forward_static.restype = c_int
     L.hsbuild_forward_factored.argtypes = [c_void_p, POINTER(c_double), c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                                   c_void_p, c_void_p, c_size_t, c_void_p]
     L.hsbuild_forward_factored.restype = c_int

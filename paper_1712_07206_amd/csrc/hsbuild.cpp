@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -18,8 +19,15 @@
 
 using namespace hsb;
 
+// Workspace of hsbuild_forward_static.  The HIP runtime gives every GPU its own copy of
+// this array, alive until the process ends.  On the host the name is only a stand-in for
+// the symbol: host code uses the address hipGetSymbolAddress returns for the current
+// device (static_scratch below), never the name itself.
+static __device__ __align__(256) unsigned char scratch[HSB_STATIC_SCRATCH_BYTES];
+
 struct hsbuild_s {
   int device = 0;
+  void* scratch = nullptr;  // this device's copy of `scratch` (device address)
   int n_types = 0, n_atoms = 0, l_max = 0, n_l = 0, max_ng = 0;
   int precision = HSB_FP64, n_slices = 0;
   int tile_group = 8;  // HSB_OPT_TILE_GROUP
@@ -73,6 +81,26 @@ int fail(hsbuild_t h, int code, const char* fmt, ...) {
 }
 
 size_t align256(size_t v) { return (v + 255) & ~size_t(255); }
+
+// Device address of `scratch` on device `dev`, which must be current: looked up once per
+// device and kept.  hipSuccess or the lookup's error.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_addr[kMaxDevices] = {};
+
+hipError_t static_scratch(int dev, void** out) {
+  if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_addr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    if (!p) return hipErrorInvalidSymbol;
+    g_scratch_addr[dev] = p;
+  }
+  *out = g_scratch_addr[dev];
+  return hipSuccess;
+}
 
 // Rows of the factored layout: per type with atoms, round16(N_t) phase rows and round16(2 N_L) W0 rows.
 int fact_rows(const hsbuild_s& h) {
@@ -484,8 +512,16 @@ int hsbuild_create(const hsb_config* cfg, hsbuild_t* out) {
   if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return fail(nullptr, HSB_ERR_DEVICE, "device %d is %s, this library is built for gfx950", dev, prop.gcnArchName);
 
+  void* scratch_dev = nullptr;
+  {
+    const hipError_t e = static_scratch(dev, &scratch_dev);
+    if (e != hipSuccess)
+      return fail(nullptr, HSB_ERR_DEVICE, "address of the static scratch on device %d: %s", dev, hipGetErrorString(e));
+  }
+
   hsbuild_s* h = new (std::nothrow) hsbuild_s();
   if (!h) return fail(nullptr, HSB_ERR_ARG, "out of host memory");
+  h->scratch = scratch_dev;
   if (hipHostMalloc((void**)&h->consts, sizeof(TypeConsts), hipHostMallocDefault) != hipSuccess) {
     delete h;
     return fail(nullptr, HSB_ERR_DEVICE, "pinned host allocation failed");
@@ -593,19 +629,15 @@ int hsbuild_coefficients(hsbuild_t h, const double k_frac[3], int32_t ng, const 
                   "k_assemble");
 }
 
-int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
-                    const void* T, void* H, void* S, void* ws, size_t ws_bytes, void* stream) {
-  if (!h) return HSB_ERR_ARG;
-  h->err.clear();
-  if (!k_frac || !g || !tau || !T || !H || !S) return fail(h, HSB_ERR_ARG, "null k_frac, g, tau, T, H or S");
-  if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
-  int rc = check_ng(h, ng);
-  if (rc) return rc;
-  const Layout L = make_layout(*h, ng, HSB_MODE_FORWARD);
-  if ((rc = check_ws(h, L, ws, ws_bytes))) return rc;
-  if ((rc = check_device(h))) return rc;
-  hipStream_t s = (hipStream_t)stream;
-  char* w = (char*)ws;
+}  // extern "C"
+
+namespace {
+
+// Body of hsbuild_forward and hsbuild_forward_static once the arguments and the
+// workspace `w` (L.end bytes) have been checked.
+int forward_enqueue(hsbuild_t h, const Layout& L, const double k_frac[3], int32_t ng, const int32_t* g,
+                    const double* tau, const void* T, void* H, void* S, char* w, hipStream_t s) {
+  int rc;
   mark(h, 0, s);
   if ((rc = enqueue_operands(h, L, k_frac, g, tau, T, w, s))) return rc;
   if (h->precision == HSB_FP64) {
@@ -618,6 +650,43 @@ int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32
   }
   mark(h, 3, s);
   return rc;
+}
+
+}  // namespace
+
+extern "C" {
+
+int hsbuild_forward(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
+                    const void* T, void* H, void* S, void* ws, size_t ws_bytes, void* stream) {
+  if (!h) return HSB_ERR_ARG;
+  h->err.clear();
+  if (!k_frac || !g || !tau || !T || !H || !S) return fail(h, HSB_ERR_ARG, "null k_frac, g, tau, T, H or S");
+  if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
+  int rc = check_ng(h, ng);
+  if (rc) return rc;
+  const Layout L = make_layout(*h, ng, HSB_MODE_FORWARD);
+  if ((rc = check_ws(h, L, ws, ws_bytes))) return rc;
+  if ((rc = check_device(h))) return rc;
+  return forward_enqueue(h, L, k_frac, ng, g, tau, T, H, S, (char*)ws, (hipStream_t)stream);
+}
+
+int hsbuild_forward_static(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
+                           const void* T, void* H, void* S, void* stream) {
+  if (!h) return HSB_ERR_ARG;
+  h->err.clear();
+  if (!k_frac || !g || !tau || !T || !H || !S) return fail(h, HSB_ERR_ARG, "null k_frac, g, tau, T, H or S");
+  if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
+  int rc = check_ng(h, ng);
+  if (rc) return rc;
+  const Layout L = make_layout(*h, ng, HSB_MODE_FORWARD);
+  if (L.end > HSB_STATIC_SCRATCH_BYTES)
+    return fail(h, HSB_ERR_WORKSPACE,
+                "ng=%d needs %zu bytes of workspace, the static scratch holds %zu; use hsbuild_forward with a "
+                "caller workspace",
+                ng, L.end, (size_t)HSB_STATIC_SCRATCH_BYTES);
+  if ((rc = check_device(h))) return rc;
+  if (!h->scratch) return fail(h, HSB_ERR_DEVICE, "no static scratch address for device %d", h->device);
+  return forward_enqueue(h, L, k_frac, ng, g, tau, T, H, S, (char*)h->scratch, (hipStream_t)stream);
 }
 
 int hsbuild_forward_factored(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,

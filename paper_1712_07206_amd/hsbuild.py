@@ -144,6 +144,26 @@ class HSBuilder:
                                         _ptr(ws), ws.numel(), _stream()), self._h)
         return H, S
 
+    def forward_static(self, k_frac, g: torch.Tensor, tau: torch.Tensor, T: torch.Tensor,
+                       H: Optional[torch.Tensor] = None, S: Optional[torch.Tensor] = None):
+        """hsbuild_forward_static: as forward(), with the library's own device
+        scratch instead of a workspace (nothing is allocated by the call; H and
+        S are allocated here only when not given)."""
+        ng = int(g.shape[0])
+        g = _dev(g, torch.int32, "g", (ng, 3))
+        tau = _dev(tau, torch.float64, "tau", (self.n_atoms, 3))
+        T = _dev(T, torch.complex128, "T", (self.n_types, 2 * self.n_l, 2 * self.n_l))
+        if H is None:
+            H = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+        if S is None:
+            S = torch.empty((ng, ng), dtype=torch.complex128, device="cuda")
+        H = _dev(H, torch.complex128, "H", (ng, ng))
+        S = _dev(S, torch.complex128, "S", (ng, ng))
+        kf = (ctypes.c_double * 3)(*[float(x) for x in k_frac])
+        N.check(N.lib().hsbuild_forward_static(self._h, kf, ng, _ptr(g), _ptr(tau), _ptr(T), _ptr(H), _ptr(S),
+                                               _stream()), self._h)
+        return H, S
+
     def forward_factored(self, k_frac, g: torch.Tensor, tau: torch.Tensor, T: torch.Tensor,
                          H: Optional[torch.Tensor] = None, S: Optional[torch.Tensor] = None,
                          ws: Optional[torch.Tensor] = None):

@@ -136,6 +136,7 @@ def test_null_handle_entry_points():
     kf = (ctypes.c_double * 3)(0, 0, 0)
     assert L.hsbuild_forward(None, kf, 1, None, None, None, None, None, None, 0, None) == N.HSB_ERR_ARG
     assert L.hsbuild_coefficients(None, kf, 1, None, None, None, None, 0, None) == N.HSB_ERR_ARG
+    assert L.hsbuild_forward_static(None, kf, 1, None, None, None, None, None, None) == N.HSB_ERR_ARG
     L.hsbuild_destroy(None)
 
 
