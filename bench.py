@@ -27,9 +27,38 @@ def log(msg: str) -> None:
     sys.stderr.flush()
 
 
-def cpu_baseline(index: int, n_g: int) -> dict:
+def host_cpu() -> dict:
+    """CPU model and physical core count of the host (from /proc/cpuinfo)."""
+    model, cores = None, set()
+    phys = core = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                key, _, val = line.partition(":")
+                key, val = key.strip(), val.strip()
+                if key == "model name" and model is None:
+                    model = val
+                elif key == "physical id":
+                    phys = val
+                elif key == "core id":
+                    core = val
+                elif not key and phys is not None and core is not None:
+                    cores.add((phys, core))
+                    phys = core = None
+        if phys is not None and core is not None:
+            cores.add((phys, core))
+    except OSError:
+        pass
+    return {"cpu_model": model, "physical_cores": len(cores) or None, "logical_cpus": os.cpu_count(),
+            "affinity_cpus": len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None}
+
+
+def cpu_baseline(index: int, n_g: int, split_forms=()) -> dict:
     """The oracle as it stands, on a bounded sample of the same workload: the
-    same cell at a reduced basis size."""
+    same cell at a reduced basis size.  With split_forms ((name, precision,
+    slices) triples), the oracle's H and S of the same cell at N_G = 3000 also
+    serve as the reference for each split form's error, computed on the GPU at
+    that size (the oracle stays on the host)."""
     from threadpoolctl import threadpool_info
 
     from flapw_cells import make_case
@@ -40,9 +69,33 @@ def cpu_baseline(index: int, n_g: int) -> dict:
     dt = time.perf_counter() - t0
     flops = o.flops_forward(case["n_atoms"], case["n_l"], n_g)
     threads = max([p.get("num_threads", 1) for p in threadpool_info() if p.get("user_api") == "blas"] or [1])
-    return {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
-            "sample": "oracle H+S (numpy complex128 over OpenBLAS) on the same cell at N_G=%d "
-                      "(F=%.3g TFLOP, %.1f s)" % (n_g, flops / 1e12, dt)}
+    out = {"value": flops / dt / 1e12, "unit": "TFLOP/s", "cores": int(threads), "kind": "oracle",
+           "threads": int(threads), **host_cpu(),
+           "sample": "oracle H+S (numpy complex128 over OpenBLAS, %d threads) on the same cell at N_G=%d "
+                     "(F=%.3g TFLOP, %.1f s)" % (threads, n_g, flops / 1e12, dt)}
+    if split_forms:
+        import numpy as np
+        import torch
+
+        from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+        c3 = make_case(index, n_g=3000)
+        Hr, Sr = o.hs(c3)
+        g, tau, T = case_tensors(c3)
+        errs = {}
+        for name, precision, slices in split_forms:
+            bs = HSBuilder.from_case(c3, precision=precision, n_slices=slices)
+            H, S = bs.forward(c3["k_frac"], g, tau, T)
+            H, S = H.cpu().numpy(), S.cpu().numpy()
+            bs.close()
+            full = lambda M: np.triu(M) + np.triu(M, 1).conj().T
+            eh = float(np.linalg.norm(full(H) - Hr) / np.linalg.norm(Hr))
+            es = float(np.linalg.norm(full(S) - Sr) / np.linalg.norm(Sr))
+            errs["%s_x%d" % (name, slices)] = {"H": eh, "S": es, "meets_1e-10": bool(max(eh, es) <= 1e-10)}
+            log("split %s x%d vs oracle at N_G=3000: H %.2e S %.2e" % (name, slices, eh, es))
+        del g, tau, T
+        torch.cuda.empty_cache()
+        out["split_vs_oracle_ng3000"] = errs
+    return out
 
 
 def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
@@ -52,7 +105,7 @@ def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
     is the headline split figure."""
     import torch
 
-    from paper_1712_07206_amd import HSB_SPLIT_BF16, HSB_SPLIT_INT8
+    from paper_1712_07206_amd import HSB_SPLIT_BF16, HSB_SPLIT_CRT, HSB_SPLIT_FP16, HSB_SPLIT_INT8
     from paper_1712_07206_amd import _native as N
     from paper_1712_07206_amd.hsbuild import HSBuilder, hermitian_full
     n = case["n_g"]
@@ -72,7 +125,7 @@ def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
     del ws
     torch.cuda.empty_cache()
 
-    def one(name, precision, slices, bits, peak, unit):
+    def one(name, precision, slices, bits, peak, unit, kernel):
         bs = HSBuilder.from_case(case, precision=precision, n_slices=slices)
         wsb = bs.workspace_bytes(N.HSB_MODE_FORWARD, [n])
         wss = torch.empty(wsb, dtype=torch.uint8, device="cuda")
@@ -97,20 +150,28 @@ def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
         stage_ms, _ = bs.stage_times()
         eh = (torch.linalg.norm(hermitian_full(H) - H64) / torch.linalg.norm(H64)).item()
         es = (torch.linalg.norm(hermitian_full(S) - S64) / torch.linalg.norm(S64)).item()
-        # slice-MFMA work executed by the two contraction launches (S and H): every 128 x 64 tile of
-        # the upper triangle, the stacked rows padded to 32, S(S+1)/2 slice pairs x 4 real products
-        # x 2 operations
-        nbr = -(-n // 128)
-        k_pad2 = -(-2 * case["n_atoms"] * case["n_l"] // 32) * 32
-        pairs = slices * (slices + 1) // 2
-        mfma_ops = 2.0 * nbr * (nbr + 1) * 128 * 64 * k_pad2 * pairs * 8
+        if precision == HSB_SPLIT_CRT:
+            # residue-MFMA work of the two contraction launches (S and H): every 256 x 128 tile of the
+            # upper triangle (two per 256 x 256 super-tile), the stacked rows padded to 64, per modulus
+            # two int8 products (P and Q) x 2 operations
+            nbs = -(-n // 256)
+            k64 = -(-2 * case["n_atoms"] * case["n_l"] // 64) * 64
+            mfma_ops = 2.0 * nbs * (nbs + 1) * 256 * 128 * k64 * slices * 2 * 2
+        else:
+            # slice-MFMA work executed by the two contraction launches (S and H): every 128 x 64 tile
+            # of the upper triangle, the stacked rows padded to 32, S(S+1)/2 slice pairs x 4 real
+            # products x 2 operations
+            nbr = -(-n // 128)
+            k_pad2 = -(-2 * case["n_atoms"] * case["n_l"] // 32) * 32
+            pairs = slices * (slices + 1) // 2
+            mfma_ops = 2.0 * nbr * (nbr + 1) * 128 * 64 * k_pad2 * pairs * 8
         rate = mfma_ops / (stage_ms[2] * 1e-3) / 1e12
         log("split %s x%d: %.3f ms/step (contraction stage %.3f ms); FP64 path next to it %.3f ms: speedup %.3f; "
             "rel err vs FP64 H %.2e S %.2e" % (name, slices, ms, stage_ms[2], ms_fp64_adj, ms_fp64_adj / ms, eh, es))
         del wss
         bs.close()
         torch.cuda.empty_cache()
-        return {"precision": name, "slices": slices, "slice_bits": bits, "ms_per_step": round(ms, 4),
+        return {"precision": name, "slices": slices, "slice_bits": bits, "kernel": kernel, "ms_per_step": round(ms, 4),
                 "fp64_equiv_tflops": round(flops / (ms * 1e-3) / 1e12, 4), "speedup": round(ms_fp64_adj / ms, 4),
                 "fp64_ms_adjacent": round(ms_fp64_adj, 4), "speedup_vs_headline_fp64": round(ms_fp64 / ms, 4),
                 "stages_ms": {"coefficients": round(stage_ms[0], 4), "t_products": round(stage_ms[1], 4),
@@ -120,13 +181,19 @@ def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
                                "frac": round(rate / peak, 4)}}
 
     forms = []
+    if args.crt_moduli > 0:  # "slices" of the residue form: its moduli; "slice_bits": bits per residue byte
+        forms.append(one("crt", HSB_SPLIT_CRT, args.crt_moduli, 8, 5000.0, "TOP/s", "k_hs_crt"))
     if args.int8_slices > 0:
-        forms.append(one("int8", HSB_SPLIT_INT8, args.int8_slices, 7, 5000.0, "TOP/s"))
+        forms.append(one("int8", HSB_SPLIT_INT8, args.int8_slices, 7, 5000.0, "TOP/s", "k_hs_split8"))
     if args.split_slices > 0:
-        forms.append(one("bf16", HSB_SPLIT_BF16, args.split_slices, 8, 2500.0, "TFLOP/s"))
+        forms.append(one("bf16", HSB_SPLIT_BF16, args.split_slices, 8, 2500.0, "TFLOP/s", "k_hs_split2"))
+    if args.fp16_slices > 0:
+        forms.append(one("fp16", HSB_SPLIT_FP16, args.fp16_slices, 8, 2500.0, "TFLOP/s", "k_hs_split"))
     del H64, S64
     torch.cuda.empty_cache()
-    best = next((f for f in forms if f["meets_1e-10"]), forms[0])
+    # headline: the fastest form that meets the 1e-10 bar
+    ok = [f for f in forms if f["meets_1e-10"]]
+    best = min(ok, key=lambda f: f["ms_per_step"]) if ok else forms[0]
     out = dict(best)
     out["other_forms"] = [f for f in forms if f is not best]
     return out
@@ -290,21 +357,27 @@ def real_leg(args) -> dict:
     del Hc, Sc, Hcu, Scu, ws
     b.close()
     torch.cuda.empty_cache()
-    # the int8 split form of the real path, against the FP64 real path's outputs
-    int8 = None
-    if args.int8_slices > 0:
-        from paper_1712_07206_amd import HSB_SPLIT_INT8
-        bi = HSBuilder.from_case(case, precision=HSB_SPLIT_INT8, n_slices=args.int8_slices)
+    # the split forms of the real path (int8 slices, residues), against the FP64 real path's outputs
+    def real_split(name, precision, slices):
+        bi = HSBuilder.from_case(case, precision=precision, n_slices=slices)
         wsi = bi.workspace(N.HSB_MODE_REAL, [n])
         ms_i = timed(lambda: bi.forward_real(kf, g, tau, case["partner"], T, Hr, Sr, ws=wsi), reps)
         ehi = (torch.linalg.norm(torch.triu(Hr) - Hr64) / torch.linalg.norm(Hr64)).item()
         esi = (torch.linalg.norm(torch.triu(Sr) - Sr64) / torch.linalg.norm(Sr64)).item()
-        log("real-symmetric int8 x%d: %.3f ms (%.2fx the FP64 real path); rel err vs it H %.2e S %.2e"
-            % (args.int8_slices, ms_i, ms_r / ms_i, ehi, esi))
-        int8 = {"slices": args.int8_slices, "ms": round(ms_i, 4), "speedup_vs_fp64_real": round(ms_r / ms_i, 4),
-                "rel_err_vs_fp64_real": {"H": ehi, "S": esi}, "meets_1e-10": bool(ehi <= 1e-10 and esi <= 1e-10)}
+        log("real-symmetric %s x%d: %.3f ms (%.2fx the FP64 real path); rel err vs it H %.2e S %.2e"
+            % (name, slices, ms_i, ms_r / ms_i, ehi, esi))
         del wsi
         bi.close()
+        return {"slices": slices, "ms": round(ms_i, 4), "speedup_vs_fp64_real": round(ms_r / ms_i, 4),
+                "rel_err_vs_fp64_real": {"H": ehi, "S": esi}, "meets_1e-10": bool(ehi <= 1e-10 and esi <= 1e-10)}
+
+    int8 = crt = None
+    if args.int8_slices > 0:
+        from paper_1712_07206_amd import HSB_SPLIT_INT8
+        int8 = real_split("int8", HSB_SPLIT_INT8, args.int8_slices)
+    if args.crt_moduli > 0:
+        from paper_1712_07206_amd import HSB_SPLIT_CRT
+        crt = real_split("crt", HSB_SPLIT_CRT, args.crt_moduli)
     del Hr, Sr, Hr64, Sr64
     torch.cuda.empty_cache()
     log("real-symmetric %s: complex path %.3f ms, real path %.3f ms (%.2fx), %.2f TFLOP/s on its own %.4g TFLOP; "
@@ -314,7 +387,8 @@ def real_leg(args) -> dict:
     return {"workload": case["name"], "n_g": n, "representatives": n_rep, "ms_complex": round(ms_c, 4),
             "ms_real": round(ms_r, 4), "speedup": round(ms_c / ms_r, 4), "flops_real": flops_r,
             "flops_complex": flops_c, "real_tflops": round(flops_r / (ms_r * 1e-3) / 1e12, 4),
-            "complex_imag_rel": imag, "rel_err_vs_complex": {"H": eh, "S": es}, "int8_split": int8}
+            "complex_imag_rel": imag, "rel_err_vs_complex": {"H": eh, "S": es}, "int8_split": int8,
+            "crt_split": crt}
 
 
 def eigen_leg(args) -> dict:
@@ -626,6 +700,10 @@ def main() -> int:
                     help="also time the BF16 split-precision path with this many slices (0: skip)")
     ap.add_argument("--int8-slices", type=int, default=6,
                     help="also time the int8 split-precision path with this many slices (0: skip)")
+    ap.add_argument("--fp16-slices", type=int, default=5,
+                    help="also time the FP16 split-precision path with this many slices (0: skip)")
+    ap.add_argument("--crt-moduli", type=int, default=11,
+                    help="also time the residue (CRT) split-precision path with this many moduli (0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -760,7 +838,7 @@ def main() -> int:
         result["factored"] = factored_leg(args, case, g, tau, T, H, S, ms_step)
     if not args.no_hsdla:
         result["hsdla_rocblas"] = hsdla_leg(args, case, g, tau, T, H, S, ms_step)
-    if args.split_slices > 0 or args.int8_slices > 0:
+    if args.split_slices > 0 or args.int8_slices > 0 or args.fp16_slices > 0 or args.crt_moduli > 0:
         result["split"] = split_leg(args, case, b, g, tau, T, H, S, ws, ms_step, flops)
         if result["split"]["meets_1e-10"]:
             result["split_speedup"] = result["split"]["speedup"]
@@ -780,12 +858,16 @@ def main() -> int:
         # each kernel's rate against what the matrix cores sustain on this device (the probe)
         dev = result["device"]
         result["roofline"]["probe_frac"] = round(result["roofline"]["achieved"] / dev["fp64_mfma_probe"]["achieved"], 4)
-        if result.get("split") and result["split"]["precision"] == "int8":
-            sm = result["split"]["slice_mfma"]
-            sm["probe_frac"] = round(sm["achieved"] / dev["int8_mfma_probe"]["achieved"], 4)
+        for form in ([result["split"]] + result["split"]["other_forms"]) if result.get("split") else []:
+            if form["precision"] in ("int8", "crt"):
+                sm = form["slice_mfma"]
+                sm["probe_frac"] = round(sm["achieved"] / dev["int8_mfma_probe"]["achieved"], 4)
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host (N_G=%d)" % args.cpu_ng)
-        result["cpu_baseline"] = cpu_baseline(args.config, args.cpu_ng)
+        from paper_1712_07206_amd import HSB_SPLIT_BF16, HSB_SPLIT_CRT, HSB_SPLIT_FP16, HSB_SPLIT_INT8
+        forms = [("crt", HSB_SPLIT_CRT, args.crt_moduli), ("int8", HSB_SPLIT_INT8, args.int8_slices),
+                 ("bf16", HSB_SPLIT_BF16, args.split_slices), ("fp16", HSB_SPLIT_FP16, args.fp16_slices)]
+        result["cpu_baseline"] = cpu_baseline(args.config, args.cpu_ng, [f for f in forms if f[2] > 0])
         log("oracle: %.4f TFLOP/s on %d threads" % (result["cpu_baseline"]["value"], result["cpu_baseline"]["cores"]))
     else:
         result["cpu_baseline"] = None

@@ -64,11 +64,16 @@ enum {
   HSB_ERR_NUMERIC = -6      /* singular radial Wronskian at create */
 };
 
-/* Contraction precision.  The split forms cut every operand column, scaled by a
+/* Contraction precision.  The slice forms cut every operand column, scaled by a
  * power of two, into n_slices integer slices and run the slice products on the
  * matrix cores: 8-bit slices as BF16 or FP16 values with FP32 sums, or 7-bit
- * slices as signed bytes with exact int32 sums (HSB_SPLIT_INT8). */
-enum { HSB_FP64 = 0, HSB_SPLIT_FP16 = 1, HSB_SPLIT_BF16 = 2, HSB_SPLIT_INT8 = 3 };
+ * slices as signed bytes with exact int32 sums (HSB_SPLIT_INT8).  The residue
+ * form (HSB_SPLIT_CRT) rounds every column, scaled by a power of two, to
+ * Gaussian integers, multiplies their residues modulo n_slices coprime moduli
+ * below 256 on the int8 matrix cores (exact int32 sums, two products per
+ * modulus for a complex product) and recovers the integer products by the
+ * Chinese remainder theorem in FP64. */
+enum { HSB_FP64 = 0, HSB_SPLIT_FP16 = 1, HSB_SPLIT_BF16 = 2, HSB_SPLIT_INT8 = 3, HSB_SPLIT_CRT = 4 };
 
 /* Workspace modes for hsbuild_workspace_bytes. */
 enum { HSB_MODE_FORWARD = 0, HSB_MODE_BACKWARD = 1, HSB_MODE_BATCH = 2, HSB_MODE_COEFFICIENTS = 3, HSB_MODE_FACTORED = 4,
@@ -89,9 +94,12 @@ typedef struct {
   const double* r_mt;         /* [n_types] muffin-tin radii (bohr), > 0 */
   const double* radial;       /* [n_types][l_max+1][4]: u, u', udot, udot' at R_MT */
   const double* udot_norm2;   /* [n_types][l_max+1]: ||udot_l||^2 >= 0 */
-  int32_t precision;          /* HSB_FP64, HSB_SPLIT_FP16, HSB_SPLIT_BF16 or HSB_SPLIT_INT8 */
+  int32_t precision;          /* HSB_FP64, HSB_SPLIT_FP16, HSB_SPLIT_BF16, HSB_SPLIT_INT8 or
+                                 HSB_SPLIT_CRT */
   int32_t n_slices;           /* split path only: slices per operand, 3..6 (8 bits each
-                                 for BF16/FP16, 7 for INT8) */
+                                 for BF16/FP16, 7 for INT8); for HSB_SPLIT_CRT the number
+                                 of moduli, 8..14 (each adds about 3.7 bits per operand
+                                 column; 11 keeps the error near 1e-11) */
 } hsb_config;
 
 /* Create a handle.  Returns HSB_ERR_NUMERIC if some radial Wronskian
@@ -168,10 +176,10 @@ int hsbuild_forward_factored(hsbuild_t h, const double k_frac[3], int32_t ng, co
  * upper triangle written; equal to the real parts of hsbuild_forward's
  * outputs up to FP64 rounding (undefined if the symmetry does not hold).
  * Other arguments as hsbuild_forward.  A handle created with HSB_FP64 runs
- * the FP64 contraction; one created with HSB_SPLIT_INT8 runs the int8 split
- * contraction (the real parts of the split products, to the split path's
- * error); HSB_SPLIT_BF16 and HSB_SPLIT_FP16 handles get HSB_ERR_UNSUPPORTED
- * before anything is enqueued.
+ * the FP64 contraction; one created with HSB_SPLIT_INT8 or HSB_SPLIT_CRT runs
+ * that split contraction (the real parts of the split products, to the split
+ * path's error); HSB_SPLIT_BF16 and HSB_SPLIT_FP16 handles get
+ * HSB_ERR_UNSUPPORTED before anything is enqueued.
  * Workspace: hsbuild_workspace_bytes(h, HSB_MODE_REAL, 1, &ng). */
 int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
                          const int32_t* partner, const void* T, double* H, double* S, void* ws, size_t ws_bytes,

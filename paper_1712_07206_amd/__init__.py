@@ -5,6 +5,7 @@ include/hsbuild.h; this package holds its sources (csrc/), the build script
 and a thin ctypes/PyTorch binding.
 """
 from . import _native
-from ._native import HSBuildError, HSB_FP64, HSB_SPLIT_FP16, HSB_SPLIT_BF16, HSB_SPLIT_INT8
+from ._native import HSBuildError, HSB_FP64, HSB_SPLIT_FP16, HSB_SPLIT_BF16, HSB_SPLIT_INT8, HSB_SPLIT_CRT
 
-__all__ = ["_native", "HSBuildError", "HSB_FP64", "HSB_SPLIT_FP16", "HSB_SPLIT_BF16", "HSB_SPLIT_INT8"]
+__all__ = ["_native", "HSBuildError", "HSB_FP64", "HSB_SPLIT_FP16", "HSB_SPLIT_BF16", "HSB_SPLIT_INT8",
+           "HSB_SPLIT_CRT"]

@@ -25,6 +25,7 @@ HSB_FP64 = 0
 HSB_SPLIT_FP16 = 1
 HSB_SPLIT_BF16 = 2
 HSB_SPLIT_INT8 = 3
+HSB_SPLIT_CRT = 4
 HSB_PROBE_FP64 = 0
 HSB_PROBE_INT8 = 1
 

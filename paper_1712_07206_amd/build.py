@@ -18,7 +18,7 @@ BUILD = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libhsbuild.so")
 ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 SOURCES = ["hsbuild.cpp", "k_coef.hip", "k_tprod.hip", "k_hs.hip", "k_adjoint.hip", "k_split.hip", "k_fact.hip",
-           "hsdla_blas.cpp", "k_probe.hip"]
+           "hsdla_blas.cpp", "k_probe.hip", "k_crt.hip"]
 ARCH = "gfx950"
 FLAGS = [
     "-O3", "-std=c++17", "-fPIC", "-x", "hip", "--offload-arch=" + ARCH,

@@ -56,7 +56,9 @@ struct Layout {
   size_t TT = 0;                                  // T^T per type, zero-padded (T products)
   int Kt = 0;                                     // backward: K_pad rounded up to 128
   int K_pad2 = 0;                                  // split only: stacked rows padded to 32
-  size_t mx = 0, scale = 0, slL = 0, slS = 0, slY = 0;  // split only
+  size_t mx = 0, scale = 0, slL = 0, slS = 0, slY = 0;  // split only (slL, slS, slY: residue planes in the CRT form)
+  int K64 = 0, n_res = 0;                              // residue form: rows padded to 64, columns to 256
+  size_t crPart = 0, crRes = 0;                        // residue form: partial column norms, product residues
   // factored only: rows [R_f] of X (E and W0 blocks), XL = lam X, Yx (Y0 on W0 rows, 0 on E rows)
   int R_f = 0;
   size_t X = 0, XL = 0, Yx = 0, lamx = 0, kind = 0, tau0 = 0;
@@ -143,6 +145,42 @@ hipError_t launch_hs_split8_real(int S, const void* L, const void* R, const doub
                                  int n, int n_pad, int gr, double* C, hipStream_t s);
 hipError_t launch_hs_split(int precision, int S, const void* L, const void* R, const double* scL, const double* scR,
                            int QK, int n, int n_pad, int gr, double2* C, hipStream_t s);
+
+// ---- split precision by residues (Chinese remainder) ----
+constexpr int kCrtMinModuli = 8, kCrtMaxModuli = 14;
+constexpr int kCrtRows = 64;  // stacked rows per stage of the residue contraction (K padded to it)
+// Moduli and recombination constants, passed to the kernels by value.
+struct CrtConsts {
+  int n_mod;
+  int m[kCrtMaxModuli];      // coprime moduli, each a power of a prime p = 1 (mod 4), below 256
+  int j[kCrtMaxModuli];      // j^2 = -1 (mod m)
+  int inv2[kCrtMaxModuli];   // 2^{-1} (mod m)
+  int inv2j[kCrtMaxModuli];  // (2 j)^{-1} (mod m)
+  double h[kCrtMaxModuli];   // y_i / m_i = h_i + l_i, y_i = (M / m_i)^{-1} (mod m_i), h_i on a 2^-42 grid
+  double l[kCrtMaxModuli];
+  double M;                  // product of the moduli (rounded)
+  double bound;              // largest 2-norm of a scaled integer column: bound^2 < M/2 (1 - 2^-10)
+};
+// Host: the n_mod largest such moduli and their constants; false if n_mod is out of range.
+bool crt_make_consts(int n_mod, CrtConsts* cc);
+// Residue columns: the basis padded to whole 256-row tiles.
+inline int crt_cols(int n) { return (int)round_up(n, 256); }
+int crt_norm_blocks(int K);
+int crt_tiles(int n_res);
+// Column scales (powers of two) of W, lam W and Y: scale[0..3 n_res); part: 3 crt_norm_blocks(K) n_res doubles.
+hipError_t launch_crt_scales(const double2* W, const double2* Y, const double* lam, int K, int n_pad, int n_res,
+                             const CrtConsts& cc, double* part, double* scale, hipStream_t s);
+// Residue planes of X (times lam if use_lam): 2 n_mod planes of [n_res / 64][QK][64] 16-byte units, QK = K64 / 16.
+hipError_t launch_crt_residues(const CrtConsts& cc, const double2* X, const double* lam, int use_lam, int K, int n_pad,
+                               int n_res, int QK, const double* scale, void* out, hipStream_t s);
+// Residues of the upper triangle of conj(L)^T R per modulus: res [n_mod][n_res][n_res], 2 bytes per
+// entry (1 if real: Re only).
+// waves: 8 (waves of 64 x 64) or 4 (128 x 64).
+hipError_t launch_hs_crt(const CrtConsts& cc, bool real, const void* L, const void* R, int QK, int n, int n_res,
+                         int gr, int waves, void* res, hipStream_t s);
+// C[row][col] (row <= col < n, ld n) from the residues, scaled by 1 / (scL[row] scR[col]); complex or real.
+hipError_t launch_crt_combine(const CrtConsts& cc, bool real, const void* res, int n_res, const double* scL,
+                              const double* scR, int n, void* C, hipStream_t s);
 
 // ---- type-factored form ----
 // Number of 64 x 64 tiles of the factored contraction.

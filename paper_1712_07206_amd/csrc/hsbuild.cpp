@@ -30,6 +30,7 @@ struct hsbuild_s {
   void* scratch = nullptr;  // this device's copy of `scratch` (device address)
   int n_types = 0, n_atoms = 0, l_max = 0, n_l = 0, max_ng = 0;
   int precision = HSB_FP64, n_slices = 0;
+  CrtConsts crt{};  // moduli of the residue form (HSB_SPLIT_CRT)
   int tile_group = 8;  // HSB_OPT_TILE_GROUP
   int hs_waves = 8;    // HSB_OPT_HS_WAVES
   double lattice[9];
@@ -166,7 +167,19 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
   }
   if ((mode == HSB_MODE_FORWARD || mode == HSB_MODE_REAL) && h.precision == HSB_FP64)
     L.WL = take((size_t)L.K_pad * np * sizeof(double2));
-  if ((mode == HSB_MODE_FORWARD && h.precision != HSB_FP64) || (mode == HSB_MODE_REAL && h.precision == HSB_SPLIT_INT8)) {
+  if ((mode == HSB_MODE_FORWARD || mode == HSB_MODE_REAL) && h.precision == HSB_SPLIT_CRT) {
+    L.K64 = (int)round_up(L.K, kCrtRows);
+    L.n_res = crt_cols(ng);
+    const size_t nr = (size_t)L.n_res;
+    const size_t planes = (size_t)2 * h.crt.n_mod * L.K64 * nr;  // bytes of one operand's residue planes
+    L.crPart = take((size_t)3 * crt_norm_blocks(L.K) * nr * sizeof(double));
+    L.scale = take(3 * nr * sizeof(double));
+    L.slL = take(planes);
+    L.slS = take(planes);
+    L.slY = take(planes);
+    L.crRes = take((size_t)h.crt.n_mod * nr * nr * (mode == HSB_MODE_REAL ? 1 : 2));
+  } else if ((mode == HSB_MODE_FORWARD && h.precision != HSB_FP64) ||
+             (mode == HSB_MODE_REAL && h.precision == HSB_SPLIT_INT8)) {
     L.K_pad2 = (int)round_up(L.K, 32);
     const size_t elem = h.precision == HSB_SPLIT_INT8 ? 1 : 2;       // bytes per slice value
     const size_t planes = (size_t)2 * h.n_slices * np * L.K_pad2 * elem;  // bytes per sliced operand
@@ -286,8 +299,39 @@ int enqueue_operands(hsbuild_t h, const Layout& L, const double k_frac[3], const
   return rc;
 }
 
+// Residue form of the split contraction (complex, or real parts only): column scales, the
+// residue planes of W, lam W and Y, then per matrix the residue contraction and the FP64
+// recombination.  L.K is the number of stacked rows used (the representatives' in the real case).
+int enqueue_crt(hsbuild_t h, const Layout& L, char* w, void* H, void* S, bool real, hipStream_t s) {
+  const double2* W = (const double2*)(w + L.W);
+  const double2* Y = (const double2*)(w + L.Y);
+  const double* lam = (const double*)(w + L.lam);
+  double* sc = (double*)(w + L.scale);
+  const int QK = (int)round_up(L.K, kCrtRows) / 16;  // 16-byte units (16 rows of int8) per column
+  const int nr = L.n_res;
+  const CrtConsts& cc = h->crt;
+  int rc = launched(h, launch_crt_scales(W, Y, lam, L.K, L.n_pad, nr, cc, (double*)(w + L.crPart), sc, s),
+                    "residue scales");
+  if (!rc) rc = launched(h, launch_crt_residues(cc, W, lam, 0, L.K, L.n_pad, nr, QK, sc, w + L.slL, s), "residues");
+  if (!rc)
+    rc = launched(h, launch_crt_residues(cc, W, lam, 1, L.K, L.n_pad, nr, QK, sc + nr, w + L.slS, s), "residues");
+  if (!rc)
+    rc = launched(h, launch_crt_residues(cc, Y, lam, 0, L.K, L.n_pad, nr, QK, sc + 2 * nr, w + L.slY, s), "residues");
+  if (!rc)
+    rc = launched(h, launch_hs_crt(cc, real, w + L.slL, w + L.slS, QK, L.n, nr, h->tile_group, h->hs_waves, w + L.crRes, s),
+                  "residue contraction (S)");
+  if (!rc) rc = launched(h, launch_crt_combine(cc, real, w + L.crRes, nr, sc, sc + nr, L.n, S, s), "recombination (S)");
+  if (!rc)
+    rc = launched(h, launch_hs_crt(cc, real, w + L.slL, w + L.slY, QK, L.n, nr, h->tile_group, h->hs_waves, w + L.crRes, s),
+                  "residue contraction (H)");
+  if (!rc)
+    rc = launched(h, launch_crt_combine(cc, real, w + L.crRes, nr, sc, sc + 2 * nr, L.n, H, s), "recombination (H)");
+  return rc;
+}
+
 // Split-precision contraction: column scales, slices of W, lam W and Y, then S and H.
 int enqueue_split(hsbuild_t h, const Layout& L, char* w, double2* H, double2* S, hipStream_t s) {
+  if (h->precision == HSB_SPLIT_CRT) return enqueue_crt(h, L, w, H, S, false, s);
   const double2* W = (const double2*)(w + L.W);
   const double2* Y = (const double2*)(w + L.Y);
   const double* lam = (const double*)(w + L.lam);
@@ -319,6 +363,7 @@ int enqueue_split(hsbuild_t h, const Layout& L, char* w, double2* H, double2* S,
 // Real-symmetric int8 split contraction on the representatives' rows (L.K): column scales and
 // slices as in the complex form, then S = Re(W^H lam W) and H = Re(W^H Y) into real arrays.
 int enqueue_split_real(hsbuild_t h, const Layout& L, char* w, double* H, double* S, hipStream_t s) {
+  if (h->precision == HSB_SPLIT_CRT) return enqueue_crt(h, L, w, H, S, true, s);
   const double2* W = (const double2*)(w + L.W);
   const double2* Y = (const double2*)(w + L.Y);
   const double* lam = (const double*)(w + L.lam);
@@ -459,10 +504,16 @@ int hsbuild_create(const hsb_config* cfg, hsbuild_t* out) {
   if (!cfg->atom_type || !cfg->r_mt || !cfg->radial || !cfg->udot_norm2)
     return fail(nullptr, HSB_ERR_ARG, "null atom_type, r_mt, radial or udot_norm2");
   if (cfg->precision != HSB_FP64 && cfg->precision != HSB_SPLIT_FP16 && cfg->precision != HSB_SPLIT_BF16 &&
-      cfg->precision != HSB_SPLIT_INT8)
+      cfg->precision != HSB_SPLIT_INT8 && cfg->precision != HSB_SPLIT_CRT)
     return fail(nullptr, HSB_ERR_ARG, "unknown precision %d", cfg->precision);
-  if (cfg->precision != HSB_FP64 && (cfg->n_slices < 3 || cfg->n_slices > 6))
+  CrtConsts crt{};
+  if (cfg->precision == HSB_SPLIT_CRT) {
+    if (!crt_make_consts(cfg->n_slices, &crt))
+      return fail(nullptr, HSB_ERR_ARG, "n_slices=%d (moduli of the residue form) outside [%d, %d]", cfg->n_slices,
+                  kCrtMinModuli, kCrtMaxModuli);
+  } else if (cfg->precision != HSB_FP64 && (cfg->n_slices < 3 || cfg->n_slices > 6)) {
     return fail(nullptr, HSB_ERR_ARG, "n_slices=%d outside [3, 6]", cfg->n_slices);
+  }
   const int n_l = (cfg->l_max + 1) * (cfg->l_max + 1);
   const int64_t K = 2LL * cfg->n_atoms * n_l;
   if (K > (1LL << 30) || (int64_t)cfg->max_ng * (int64_t)round_up(cfg->max_ng, kTileN) > (1LL << 40))
@@ -537,6 +588,7 @@ int hsbuild_create(const hsb_config* cfg, hsbuild_t* out) {
   h->precision = cfg->precision;
   if (cfg->precision != HSB_FP64) h->tile_group = 4;  // measured best for the split contraction
   h->n_slices = cfg->n_slices;
+  h->crt = crt;
   std::memcpy(h->lattice, cfg->lattice, sizeof h->lattice);
   for (int t = 0; t < cfg->n_types; ++t)
     for (int l = 0; l <= cfg->l_max; ++l) {
@@ -779,8 +831,9 @@ int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const 
   if (!k_frac || !g || !tau || !partner || !T || !H || !S)
     return fail(h, HSB_ERR_ARG, "null k_frac, g, tau, partner, T, H or S");
   if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
-  if (h->precision != HSB_FP64 && h->precision != HSB_SPLIT_INT8)
-    return fail(h, HSB_ERR_UNSUPPORTED, "the real-symmetric build has an FP64 and an int8 split form only");
+  if (h->precision != HSB_FP64 && h->precision != HSB_SPLIT_INT8 && h->precision != HSB_SPLIT_CRT)
+    return fail(h, HSB_ERR_UNSUPPORTED,
+                "the real-symmetric build has FP64, int8 slice and residue forms only (no BF16/FP16)");
   int rc = check_ng(h, ng);
   if (rc) return rc;
   // representatives: the lower index of each inversion pair (weight 2), atoms paired with themselves (weight 1)
@@ -850,7 +903,7 @@ int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const 
                                     tau_rep, wrow, lam, s),
                 "k_rep_setup");
   if (!rc) rc = launched(h, launch_scale_rows(Y, wrow, Lr.K_pad, L.n_pad, Y, s), "k_scale_rows");
-  if (!rc && h->precision == HSB_SPLIT_INT8) {
+  if (!rc && (h->precision == HSB_SPLIT_INT8 || h->precision == HSB_SPLIT_CRT)) {
     rc = enqueue_split_real(h, Lr, w, H, S, s);
   } else if (!rc) {
     double2* WL = (double2*)(w + L.WL);  // S's right operand, lam W (lam with the pair weights)

@@ -1,0 +1,484 @@
+// Split-precision contraction by residues (Chinese remainder theorem) on the int8
+// matrix cores: the residue form of the split path.
+//
+// Every operand column (one G: the vector over the stacked index k) is scaled by a
+// power of two 2^f_G and rounded to Gaussian integers x' = rint(2^f x) (exact in
+// FP64).  The integer product conj(L')^T R' of two such columns is represented by its
+// residues modulo n pairwise coprime moduli m_i.  Each m_i is a power of a prime
+// p = 1 (mod 4), so -1 has a square root j_i modulo m_i and the Gaussian integers
+// modulo m_i split into two copies of Z/m_i:
+//     z = x + i y  ->  (x + j y, x - j y)  (mod m),
+// a ring isomorphism (its inverse: x = (u + v)/2, y = (u - v)/(2j)).  The conjugated
+// product of two columns then costs two integer inner products per modulus instead of
+// four:
+//     P = sum_k (a_r - j a_i)_k (b_r + j b_i)_k,   Q = sum_k (a_r + j a_i)_k (b_r - j b_i)_k,
+//     Re = (P + Q) / 2,   Im = (P - Q) / (2j)      (mod m),
+// with the residues stored as signed bytes in [-(m-1)/2, (m-1)/2] and P, Q exact int32
+// sums on v_mfma_i32_32x32x32_i8.  The column scaling keeps |Re|, |Im| of the integer
+// product below M/2 (M = prod m_i) by Cauchy-Schwarz, so the residues fix it uniquely;
+// it is recovered in FP64 as M * frac(sum_i r_i y_i / m_i), y_i = (M/m_i)^{-1} mod m_i,
+// with y_i / m_i split into a part on a 2^-42 grid (whose weighted sum is exact) and a
+// small remainder.  The only approximation is the rounding of the scaled operands to
+// integers; at 11 moduli that keeps 40 bits of each column's 2-norm.
+//
+// Residue layout (16-byte units of 16 consecutive k, one byte each): unit
+// ((p * NB + b) * QK + q) * 64 + g holds plane p = 2 i + {0: x_r + j_i x_i, 1: x_r - j_i x_i}
+// of modulus i, column G = 64 b + g, rows k = 16 q .. 16 q + 15; NB = n_res / 64, with
+// the columns padded to n_res (a multiple of 256) and the rows to a multiple of 64, the
+// pads zero.
+#include <cmath>
+
+#include "hs_internal.h"
+#include "tiles.h"
+
+namespace hsb {
+
+namespace {
+
+typedef double d2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef int i4v __attribute__((ext_vector_type(4)));
+typedef int i16v __attribute__((ext_vector_type(16)));
+typedef __attribute__((address_space(3))) void* lds_ptr;
+
+constexpr int kNormRows = 512;  // stacked rows per partial sum of the column norms
+
+// Partial sums of squares over kNormRows rows: part[(op * nkb + kb) * n_res + G] for
+// op 0: W, 1: lam W, 2: Y (columns G >= n_pad are zero).
+__global__ void __launch_bounds__(256) k_crt_norm_part(const d2* __restrict__ W, const d2* __restrict__ Y,
+                                                       const double* __restrict__ lam, int K, int n_pad, int n_res,
+                                                       int nkb, double* __restrict__ part) {
+  const int G = blockIdx.x * 256 + threadIdx.x;
+  if (G >= n_res) return;
+  const int kb = blockIdx.y;
+  const int k0 = kb * kNormRows, k1 = min(k0 + kNormRows, K);
+  double sw = 0.0, sl = 0.0, sy = 0.0;
+  if (G < n_pad) {
+    for (int k = k0; k < k1; ++k) {
+      const d2 w = W[(int64_t)k * n_pad + G];
+      const d2 y = Y[(int64_t)k * n_pad + G];
+      const double a = w.x * w.x + w.y * w.y;
+      const double lk = lam[k];
+      sw += a;
+      sl += lk * lk * a;
+      sy += y.x * y.x + y.y * y.y;
+    }
+  }
+  part[((int64_t)0 * nkb + kb) * n_res + G] = sw;
+  part[((int64_t)1 * nkb + kb) * n_res + G] = sl;
+  part[((int64_t)2 * nkb + kb) * n_res + G] = sy;
+}
+
+// scale[op * n_res + G] = 2^f, the largest power of two with 2^f ||x_G|| + sqrt(2K)/2 <= bound
+// (the second term bounds the 2-norm of the rounding errors); 1 for a zero column.  The
+// partial sums are added in a fixed order, so the scales are reproducible.
+__global__ void __launch_bounds__(256) k_crt_scale(const double* __restrict__ part, int nkb, int n_res, int K,
+                                                   double bound, double* __restrict__ scale) {
+  const int i = blockIdx.x * 256 + threadIdx.x;
+  if (i >= 3 * n_res) return;
+  const int op = i / n_res, G = i - op * n_res;
+  double s = 0.0;
+  for (int kb = 0; kb < nkb; ++kb) s += part[((int64_t)op * nkb + kb) * n_res + G];
+  double sc = 1.0;
+  if (s > 0.0) {
+    const double t = (bound - 0.5 * sqrt(2.0 * (double)K)) / sqrt(s) * (1.0 - 0x1p-30);
+    int e = 0;
+    (void)frexp(t, &e);  // t = mant * 2^e, mant in [0.5, 1): 2^(e-1) <= t
+    sc = ldexp(1.0, e - 1);
+  }
+  scale[i] = sc;
+}
+
+// v - m * round(v / m) for an integer-valued double |v| < 2^52, in [-(m-1)/2, (m-1)/2] (m odd).
+// The quotient may be off by one near a half-integer; one correction step covers that.  The
+// product q m and the difference are exact.
+__device__ __forceinline__ double smod_d(double v, double m, double inv_m, double h) {
+  const double q = rint(v * inv_m);
+  double r = fma(-q, m, v);
+  if (r > h) r -= m;
+  if (r < -h) r += m;
+  return r;
+}
+
+// One thread per (column G, 16-row group q): the 2 n_mod residue planes of 16 rows of X
+// (times lam if use_lam), scaled by scale[G] and rounded.
+__global__ void __launch_bounds__(256) k_crt_residues(CrtConsts cc, const d2* __restrict__ X,
+                                                      const double* __restrict__ lam, int use_lam, int K, int n_pad,
+                                                      int n_res, int QK, const double* __restrict__ scale,
+                                                      u4* __restrict__ out) {
+  const int g = threadIdx.x & 63;
+  const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int b = blockIdx.x;
+  const int G = b * 64 + g;
+  if (q >= QK) return;
+  const double sc = scale[G];
+  double re[16], im[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int k = q * 16 + r;
+    d2 v = d2{0.0, 0.0};
+    if (k < K && G < n_pad) {
+      v = X[(int64_t)k * n_pad + G];
+      if (use_lam) v *= lam[k];
+    }
+    re[r] = rint(v.x * sc);  // the scale is a power of two: the product is exact
+    im[r] = rint(v.y * sc);
+  }
+  const int NB = n_res / 64;
+  const int64_t plane = (int64_t)NB * QK * 64;
+  u4* o = out + ((int64_t)b * QK + q) * 64 + g;
+  for (int i = 0; i < cc.n_mod; ++i) {
+    const double m = (double)cc.m[i], inv_m = 1.0 / m, h = 0.5 * (m - 1.0), jm = (double)cc.j[i];
+    u4 u0 = u4{0u, 0u, 0u, 0u}, u1 = u4{0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const double a = smod_d(re[r], m, inv_m, h), c = smod_d(im[r], m, inv_m, h);
+      const int p0 = (int)smod_d(fma(jm, c, a), m, inv_m, h);   // a + j c, |.| < 2^15: exact
+      const int p1 = (int)smod_d(fma(-jm, c, a), m, inv_m, h);  // a - j c
+      u0[r >> 2] |= ((unsigned)p0 & 0xffu) << (8 * (r & 3));
+      u1[r >> 2] |= ((unsigned)p1 & 0xffu) << (8 * (r & 3));
+    }
+    o[(2 * i) * plane] = u0;
+    o[(2 * i + 1) * plane] = u1;
+  }
+}
+
+__device__ __forceinline__ i16v mfma_i8(u4 a, u4 b, i16v c) {
+  return __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(i4v, a), __builtin_bit_cast(i4v, b), c, 0, 0, 0);
+}
+
+// v mod m in [-(m-1)/2, (m-1)/2] for |v| < 2^30 (the quotient from FP64, one correction).
+__device__ __forceinline__ int smod_i(int v, int m, double inv_m, int h) {
+  const int q = (int)rint((double)v * inv_m);
+  int r = v - q * m;
+  if (r > h) r -= m;
+  if (r < -h) r += m;
+  return r;
+}
+
+// Contraction tile: 256 rows (G') x 128 columns (G) per workgroup, rows of the stacked index
+// in chunks of 64 copied straight into LDS (global_load_lds_dwordx4) through a ring of three
+// stages (48 KB each): a chunk is copied two chunks ahead of its use.  WAVES = 8: waves of
+// 64 x 64 (2 x 2 blocks of 32 x 32, two int32 sums P and Q each, two waves per SIMD);
+// WAVES = 4: waves of 128 x 64 (4 x 2 blocks, one wave per SIMD), which read 3/4 of the LDS
+// bytes per MFMA.
+constexpr int kCrtStages = 3;
+constexpr int kCrtLeftUnits = 2 * 4 * 4 * 64;                     // 2 planes x 4 blocks x 4 row groups x 64
+constexpr int kCrtStageUnits = kCrtLeftUnits + 2 * 2 * 4 * 64;    // + 2 planes x 2 blocks x 4 x 64
+constexpr int kCrtCopies = kCrtStageUnits / 64;                   // 1 KB copies per chunk (48)
+constexpr int kCrtWindow = 1024;  // chunks (65536 rows) between reductions of the int32 sums: 2^16 * 120^2 < 2^30
+// Chunks whose sums stay exact with no reduction at all: 2^17 rows * 120^2 < 2^31.  Reducing
+// 256 accumulators held in AGPRs costs the 4-wave form its registers, so it runs only up to
+// this many chunks and the 8-wave form takes longer stacked widths.
+constexpr int kCrtNoReduce = 2048;
+
+// s_waitcnt immediates (gfx9 encoding): vector-memory count N, the other counters not waited on.
+constexpr int vmcnt_only(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
+
+// Workgroup w: modulus w / num_tiles, tile w % num_tiles (XCD-contiguous numbering, so the
+// tiles an XCD runs together belong to one modulus and a compact patch of the triangle).
+// res: residues of the product per modulus, [n_mod][n_res][n_res] of 16-bit (Re, Im) pairs of
+// signed bytes, Re in the low byte (REAL: Re bytes only), written for row <= col < n.
+template <int WAVES, bool REAL>
+__global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__ L, const u4* __restrict__ R,
+                                                          CrtConsts cc, int QK, int n, int NB, int nbs,
+                                                          int num_tiles, int num_wg, int gr, void* __restrict__ res,
+                                                          int64_t ld) {
+  constexpr int WRN = WAVES / 2;    // wave rows
+  constexpr int RB = 8 / WRN;       // 32-row blocks per wave (2 or 4)
+  constexpr int NPW = kCrtCopies / WAVES;  // copies per wave and chunk
+  __shared__ u4 lds[kCrtStages][kCrtStageUnits];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wr = wave >> 1, wc = wave & 1;
+  const int x = blockIdx.x % kXcds;
+  int start, len;
+  xcd_range(x, num_wg, start, len);
+  const int w = start + blockIdx.x / kXcds;
+  const int mod = w / num_tiles;
+  int row0, col0;
+  tile_origin_256(w - mod * num_tiles, nbs, gr, row0, col0);
+  if (col0 >= n) return;
+  const int bL = row0 >> 6, bR = col0 >> 6;
+  const int64_t plane = (int64_t)NB * QK * 64;
+  const u4* Lm = L + 2 * mod * plane;
+  const u4* Rm = R + 2 * mod * plane;
+
+  const u4* src[NPW];
+  int dst[NPW];
+#pragma unroll
+  for (int i = 0; i < NPW; ++i) {
+    const int j = wave + WAVES * i;
+    if (j < 32) {
+      const int p = j >> 4, b = (j >> 2) & 3, qq = j & 3;
+      src[i] = Lm + p * plane + ((int64_t)(bL + b) * QK + qq) * 64;
+      dst[i] = ((p * 4 + b) * 4 + qq) * 64;
+    } else {
+      const int jj = j - 32, p = jj >> 3, b = (jj >> 2) & 1, qq = jj & 3;
+      src[i] = Rm + p * plane + ((int64_t)(bR + b) * QK + qq) * 64;
+      dst[i] = kCrtLeftUnits + ((p * 2 + b) * 4 + qq) * 64;
+    }
+  }
+  auto issue = [&](int c, int buf) {
+#pragma unroll
+    for (int i = 0; i < NPW; ++i)
+      __builtin_amdgcn_global_load_lds((const void*)(src[i] + (int64_t)c * 256 + lane),
+                                       (lds_ptr)(&lds[buf][dst[i]]), 16, 0, 0);
+  };
+
+  i16v accP[RB][2], accQ[RB][2];
+#pragma unroll
+  for (int a = 0; a < RB; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        accP[a][b][r] = 0;
+        accQ[a][b][r] = 0;
+      }
+
+  const int m = cc.m[mod], hm = (m - 1) / 2;
+  const double inv_m = 1.0 / (double)m;
+  auto reduce = [&]() {
+#pragma unroll
+    for (int a = 0; a < RB; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          accP[a][b][r] = smod_i(accP[a][b][r], m, inv_m, hm);
+          accQ[a][b][r] = smod_i(accQ[a][b][r], m, inv_m, hm);
+        }
+  };
+
+  const int qh = lane >> 5, g32 = lane & 31;
+  // A operand of block rb (rows wr * 32 RB + 32 rb of the tile) for k step s, plane p: unit
+  // la(rb) + p * 1024 + s * 128 with la(rb) = ((wr RB + rb) / 2 * 4 + qh) * 64 + (rb & 1) * 32 + g32;
+  // B operand: ra + p * 512 + s * 128 + cb * 32.
+  const int la = ((wr * RB) / 2 * 4 + qh) * 64 + g32;
+  const int ra = kCrtLeftUnits + (wc * 4 + qh) * 64 + g32;
+  const int nchunks = QK >> 2;
+  if (nchunks > 0) issue(0, 0);
+  if (nchunks > 1) issue(1, 1);
+  for (int c = 0; c < nchunks; ++c) {
+    // this wave's copies of chunk c are done once at most those of chunk c + 1 are pending
+    if (c + 1 < nchunks) __builtin_amdgcn_s_waitcnt(vmcnt_only(NPW));
+    else __builtin_amdgcn_s_waitcnt(vmcnt_only(0));
+    // Every wave's copies of chunk c are in LDS past this barrier, and stage (c + 2) % 3 is
+    // free (its reads, of chunk c - 1, fed MFMAs before the barrier).  A plain s_barrier: the
+    // release fence of __syncthreads would wait for the copies of chunk c + 1 as well.
+    __builtin_amdgcn_s_barrier();
+    asm volatile("" ::: "memory");
+    if (c + 2 < nchunks) issue(c + 2, (c + 2) % kCrtStages);
+    const u4* B = lds[c % kCrtStages];
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
+      u4 a0[RB], a1[RB], b0[2], b1[2];
+#pragma unroll
+      for (int t = 0; t < RB; ++t) {
+        const int off = la + (t >> 1) * 256 + (t & 1) * 32 + s * 128;
+        a0[t] = B[off];
+        a1[t] = B[off + 1024];
+      }
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        b0[t] = B[ra + s * 128 + t * 32];
+        b1[t] = B[ra + 512 + s * 128 + t * 32];
+      }
+#pragma unroll
+      for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+        for (int cb = 0; cb < 2; ++cb) {
+          accP[rb][cb] = mfma_i8(a1[rb], b0[cb], accP[rb][cb]);  // (a_r - j a_i)(b_r + j b_i)
+          accQ[rb][cb] = mfma_i8(a0[rb], b1[cb], accQ[rb][cb]);  // (a_r + j a_i)(b_r - j b_i)
+        }
+    }
+    // the 4-wave form runs only where no reduction is needed (at most kCrtNoReduce chunks)
+    if constexpr (WAVES == 8)
+      if ((c + 1) % kCrtWindow == 0) reduce();
+  }
+
+  // residues of Re and Im; output element r of a 32 x 32 block: row 8 (r / 4) + 4 qh + r % 4, column g32
+  const int inv2 = cc.inv2[mod], inv2j = cc.inv2j[mod];
+  int rbase = row0 + wr * 32 * RB + 4 * qh, cbase = col0 + wc * 64 + g32;
+  asm volatile("" : "+v"(rbase), "+v"(cbase));
+  const int64_t obase = (int64_t)mod * ld * ld;
+#pragma unroll
+  for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+    for (int cb = 0; cb < 2; ++cb)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int row = rbase + rb * 32 + 8 * (r >> 2) + (r & 3);
+        const int col = cbase + cb * 32;
+        if (row < n && col < n && col >= row) {
+          const int p = smod_i(accP[rb][cb][r], m, inv_m, hm);
+          const int q = smod_i(accQ[rb][cb][r], m, inv_m, hm);
+          const int re = smod_i((p + q) * inv2, m, inv_m, hm);
+          if constexpr (REAL) {
+            ((int8_t*)res)[obase + (int64_t)row * ld + col] = (int8_t)re;
+          } else {
+            const int im = smod_i((p - q) * inv2j, m, inv_m, hm);
+            ((uint16_t*)res)[obase + (int64_t)row * ld + col] = (uint16_t)((re & 0xff) | ((im & 0xff) << 8));
+          }
+        }
+      }
+}
+
+// Recovery of each upper-triangle entry from its residues: value = M * frac(sum_i r_i y_i / m_i),
+// times 2^-(f_row + f_col).  sum r_i h_i is exact (h_i on a 2^-42 grid, |r_i| < 2^7, n <= 14
+// terms), so the rounding to the nearest integer is exact and the fraction keeps FP64
+// precision.  One thread per (row, col).
+template <bool REAL>
+__global__ void __launch_bounds__(256) k_crt_combine(CrtConsts cc, const void* __restrict__ res, int64_t ld,
+                                                     const double* __restrict__ scL, const double* __restrict__ scR,
+                                                     int n, void* __restrict__ Cv) {
+  const int row = blockIdx.y;
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= n || col < row) return;
+  const int64_t mstride = ld * ld, e = (int64_t)row * ld + col;
+  double hr = 0.0, lr = 0.0, hi = 0.0, li = 0.0;
+  for (int i = 0; i < cc.n_mod; ++i) {
+    if constexpr (REAL) {
+      const double r = (double)((const int8_t*)res)[i * mstride + e];
+      hr += r * cc.h[i];
+      lr += r * cc.l[i];
+    } else {
+      const unsigned v = ((const uint16_t*)res)[i * mstride + e];
+      const double r = (double)(int8_t)(v & 0xffu), t = (double)(int8_t)(v >> 8);
+      hr += r * cc.h[i];
+      lr += r * cc.l[i];
+      hi += t * cc.h[i];
+      li += t * cc.l[i];
+    }
+  }
+  const double sc = cc.M / (scL[row] * scR[col]);
+  const double fr = (hr - rint(hr)) + lr;
+  if constexpr (REAL) {
+    ((double*)Cv)[(int64_t)row * n + col] = fr * sc;
+  } else {
+    const double fi = (hi - rint(hi)) + li;
+    ((d2*)Cv)[(int64_t)row * n + col] = d2{fr * sc, fi * sc};
+  }
+}
+
+}  // namespace
+
+namespace {
+int inverse_mod(int a, int m) {  // a^{-1} mod m for gcd(a, m) = 1, m < 256
+  a %= m;
+  if (a < 0) a += m;
+  for (int x = 1; x < m; ++x)
+    if ((a * x) % m == 1) return x;
+  return 0;
+}
+}  // namespace
+
+// The n_mod largest moduli below 256 that are powers of distinct primes p = 1 (mod 4):
+// 241, 233, 229, 197, 193, 181, 173, 169 = 13^2, 157, 149, 137, 125 = 5^3, 113, 109, ...
+bool crt_make_consts(int n_mod, CrtConsts* cc) {
+  if (n_mod < kCrtMinModuli || n_mod > kCrtMaxModuli || !cc) return false;
+  *cc = CrtConsts{};
+  cc->n_mod = n_mod;
+  int used[64], n_used = 0, k = 0;
+  for (int m = 255; m >= 5 && k < n_mod; --m) {
+    int p = 2;
+    while (m % p) ++p;  // smallest prime factor
+    int r = m;
+    while (r % p == 0) r /= p;
+    if (r != 1 || p % 4 != 1) continue;
+    bool dup = false;
+    for (int i = 0; i < n_used; ++i) dup = dup || used[i] == p;
+    if (dup) continue;
+    used[n_used++] = p;
+    int j = 1;
+    while ((j * j + 1) % m) ++j;
+    cc->m[k] = m;
+    cc->j[k] = j;
+    cc->inv2[k] = inverse_mod(2, m);
+    cc->inv2j[k] = inverse_mod(2 * j, m);
+    ++k;
+  }
+  if (k < n_mod) return false;
+  double M = 1.0;
+  for (int i = 0; i < n_mod; ++i) M *= (double)cc->m[i];
+  for (int i = 0; i < n_mod; ++i) {
+    const int mi = cc->m[i];
+    int c = 1;  // (M / m_i) mod m_i
+    for (int t = 0; t < n_mod; ++t)
+      if (t != i) c = c * (cc->m[t] % mi) % mi;
+    const int y = inverse_mod(c, mi);
+    const double hh = std::ldexp(std::rint(std::ldexp((double)y / mi, 42)), -42);
+    cc->h[i] = hh;
+    cc->l[i] = ((double)y - hh * mi) / mi;  // y - h m_i is exact: h has 42 fractional bits, m_i 8 bits
+  }
+  cc->M = M;
+  cc->bound = std::sqrt(0.5 * M * (1.0 - 0x1p-10));
+  return true;
+}
+
+int crt_norm_blocks(int K) { return (K + kNormRows - 1) / kNormRows; }
+
+int crt_tiles(int n_res) {
+  const int nbs = n_res / 256;
+  return nbs * (nbs + 1);
+}
+
+hipError_t launch_crt_scales(const double2* W, const double2* Y, const double* lam, int K, int n_pad, int n_res,
+                             const CrtConsts& cc, double* part, double* scale, hipStream_t s) {
+  const int nkb = crt_norm_blocks(K);
+  hipLaunchKernelGGL(k_crt_norm_part, dim3(n_res / 256, nkb), dim3(256), 0, s, (const d2*)W, (const d2*)Y, lam, K,
+                     n_pad, n_res, nkb, part);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(k_crt_scale, dim3((3 * n_res + 255) / 256), dim3(256), 0, s, (const double*)part, nkb, n_res, K,
+                     cc.bound, scale);
+  return hipGetLastError();
+}
+
+hipError_t launch_crt_residues(const CrtConsts& cc, const double2* X, const double* lam, int use_lam, int K, int n_pad,
+                               int n_res, int QK, const double* scale, void* out, hipStream_t s) {
+  dim3 grid(n_res / 64, (QK + 3) / 4);
+  hipLaunchKernelGGL(k_crt_residues, grid, dim3(256), 0, s, cc, (const d2*)X, lam, use_lam, K, n_pad, n_res, QK, scale,
+                     (u4*)out);
+  return hipGetLastError();
+}
+
+hipError_t launch_hs_crt(const CrtConsts& cc, bool real, const void* L, const void* R, int QK, int n, int n_res,
+                         int gr, int waves, void* res, hipStream_t s) {
+  const int nbs = n_res / 256;
+  const int num_tiles = crt_tiles(n_res);
+  const int num_wg = num_tiles * cc.n_mod;
+  const int NB = n_res / 64;
+  const dim3 grid(num_wg);
+  const u4 *l = (const u4*)L, *r = (const u4*)R;
+  const int64_t ld = n_res;
+  if (waves == 4 && QK / 4 <= kCrtNoReduce) {
+    if (real)
+      hipLaunchKernelGGL((k_hs_crt<4, true>), grid, dim3(256), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr,
+                         res, ld);
+    else
+      hipLaunchKernelGGL((k_hs_crt<4, false>), grid, dim3(256), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr,
+                         res, ld);
+  } else {
+    if (real)
+      hipLaunchKernelGGL((k_hs_crt<8, true>), grid, dim3(512), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr,
+                         res, ld);
+    else
+      hipLaunchKernelGGL((k_hs_crt<8, false>), grid, dim3(512), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr,
+                         res, ld);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_crt_combine(const CrtConsts& cc, bool real, const void* res, int n_res, const double* scL,
+                              const double* scR, int n, void* C, hipStream_t s) {
+  dim3 grid((n + 255) / 256, n);
+  if (real)
+    hipLaunchKernelGGL((k_crt_combine<true>), grid, dim3(256), 0, s, cc, res, (int64_t)n_res, scL, scR, n, C);
+  else
+    hipLaunchKernelGGL((k_crt_combine<false>), grid, dim3(256), 0, s, cc, res, (int64_t)n_res, scL, scR, n, C);
+  return hipGetLastError();
+}
+
+}  // namespace hsb
