@@ -254,8 +254,10 @@ int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t*
 /* Stage timing with HIP events recorded on the call's stream, for profiling.
  * hsbuild_set_timing(h, 1) creates an event pool and clears the record;
  * while enabled, each hsbuild_forward records events around its three stages
- * (0: coefficients and tables, 1: per-atom T products, 2: the H/S
- * contraction), for up to HSB_TIMING_CAPACITY calls (later calls are not
+ * (0: coefficients and tables, 1: per-atom T products and, in the split
+ * forms, the column scales and the slices or residues of the operands, 2: the
+ * H/S contraction, with the split forms' recombination), for up to
+ * HSB_TIMING_CAPACITY calls (later calls are not
  * recorded).  hsbuild_stage_times waits for the recorded events and returns
  * the average milliseconds of each stage over the recorded calls (ms_avg[3])
  * and their number.  hsbuild_set_timing(h, 0) destroys the pool. */

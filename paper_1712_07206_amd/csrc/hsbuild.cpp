@@ -317,6 +317,7 @@ int enqueue_crt(hsbuild_t h, const Layout& L, char* w, void* H, void* S, bool re
     rc = launched(h, launch_crt_residues(cc, W, lam, 1, L.K, L.n_pad, nr, QK, sc + nr, w + L.slS, s), "residues");
   if (!rc)
     rc = launched(h, launch_crt_residues(cc, Y, lam, 0, L.K, L.n_pad, nr, QK, sc + 2 * nr, w + L.slY, s), "residues");
+  mark(h, 2, s);  // (again) the operand preparation ends here: the contraction stage starts
   if (!rc)
     rc = launched(h, launch_hs_crt(cc, real, w + L.slL, w + L.slS, QK, L.n, nr, h->tile_group, h->hs_waves, w + L.crRes, s),
                   "residue contraction (S)");
@@ -351,6 +352,7 @@ int enqueue_split(hsbuild_t h, const Layout& L, char* w, double2* H, double2* S,
                                        w + L.slY, s),
                 "split slices");
   if (rc) return rc;
+  mark(h, 2, s);  // (again) the operand preparation ends here: the contraction stage starts
   rc = launched(h, launch_hs_split(h->precision, h->n_slices, w + L.slL, w + L.slS, sc, sc + L.n_pad, QK, L.n,
                                    L.n_pad, h->tile_group, S, s),
                 "split contraction (S)");
@@ -383,6 +385,7 @@ int enqueue_split_real(hsbuild_t h, const Layout& L, char* w, double* H, double*
                                        w + L.slY, s),
                 "split slices");
   if (rc) return rc;
+  mark(h, 2, s);  // (again) the operand preparation ends here: the contraction stage starts
   rc = launched(h, launch_hs_split8_real(h->n_slices, w + L.slL, w + L.slS, sc, sc + L.n_pad, QK, L.n, L.n_pad,
                                          h->tile_group, S, s),
                 "split contraction (real S)");
