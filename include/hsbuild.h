@@ -98,7 +98,7 @@ typedef struct {
                                  HSB_SPLIT_CRT */
   int32_t n_slices;           /* split path only: slices per operand, 3..6 (8 bits each
                                  for BF16/FP16, 7 for INT8); for HSB_SPLIT_CRT the number
-                                 of moduli, 8..14 (each adds about 3.7 bits per operand
+                                 of moduli, 8..13 (each adds about 3.7 bits per operand
                                  column; 11 keeps the error near 1e-11) */
 } hsb_config;
 

@@ -147,7 +147,9 @@ hipError_t launch_hs_split(int precision, int S, const void* L, const void* R, c
                            int QK, int n, int n_pad, int gr, double2* C, hipStream_t s);
 
 // ---- split precision by residues (Chinese remainder) ----
-constexpr int kCrtMinModuli = 8, kCrtMaxModuli = 14;
+// At most 13 moduli: M < 2^97, so the scaled integer operands stay below 2^48 (the residue
+// kernel's exact reduction needs that).
+constexpr int kCrtMinModuli = 8, kCrtMaxModuli = 13;
 constexpr int kCrtRows = 64;  // stacked rows per stage of the residue contraction (K padded to it)
 // Moduli and recombination constants, passed to the kernels by value.
 struct CrtConsts {

@@ -89,15 +89,12 @@ __global__ void __launch_bounds__(256) k_crt_scale(const double* __restrict__ pa
   scale[i] = sc;
 }
 
-// v - m * round(v / m) for an integer-valued double |v| < 2^52, in [-(m-1)/2, (m-1)/2] (m odd).
-// The quotient may be off by one near a half-integer; one correction step covers that.  The
-// product q m and the difference are exact.
-__device__ __forceinline__ double smod_d(double v, double m, double inv_m, double h) {
-  const double q = rint(v * inv_m);
-  double r = fma(-q, m, v);
-  if (r > h) r -= m;
-  if (r < -h) r += m;
-  return r;
+// v - m * round(v / m), in [-(m-1)/2, (m-1)/2], for an integer-valued double |v| < 2^48 and an
+// odd modulus 113 <= m < 256.  The computed v * fl(1/m) is within |v/m| 2^-52 < 2^-10 of v/m,
+// while v/m, with m odd, is never closer than 1/(2m) > 2^-9 to a half-integer: the rounded
+// quotient is exact, and so are q m and the difference (fma).
+__device__ __forceinline__ double smod_d(double v, double m, double inv_m) {
+  return fma(-rint(v * inv_m), m, v);
 }
 
 // One thread per (column G, 16-row group q): the 2 n_mod residue planes of 16 rows of X
@@ -128,15 +125,17 @@ __global__ void __launch_bounds__(256) k_crt_residues(CrtConsts cc, const d2* __
   const int64_t plane = (int64_t)NB * QK * 64;
   u4* o = out + ((int64_t)b * QK + q) * 64 + g;
   for (int i = 0; i < cc.n_mod; ++i) {
-    const double m = (double)cc.m[i], inv_m = 1.0 / m, h = 0.5 * (m - 1.0), jm = (double)cc.j[i];
+    const double m = (double)cc.m[i], inv_m = 1.0 / m, jm = (double)cc.j[i];
     u4 u0 = u4{0u, 0u, 0u, 0u}, u1 = u4{0u, 0u, 0u, 0u};
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      const double a = smod_d(re[r], m, inv_m, h), c = smod_d(im[r], m, inv_m, h);
-      const int p0 = (int)smod_d(fma(jm, c, a), m, inv_m, h);   // a + j c, |.| < 2^15: exact
-      const int p1 = (int)smod_d(fma(-jm, c, a), m, inv_m, h);  // a - j c
-      u0[r >> 2] |= ((unsigned)p0 & 0xffu) << (8 * (r & 3));
-      u1[r >> 2] |= ((unsigned)p1 & 0xffu) << (8 * (r & 3));
+      // c = x_i mod m; x_r + j c (exact: |x_r| < 2^48, |j c| < 2^15) mod m; then
+      // x_r - j c = (x_r + j c) - 2 j c from small values (|.| < 2^16)
+      const double c = smod_d(im[r], m, inv_m);
+      const double p0 = smod_d(fma(jm, c, re[r]), m, inv_m);
+      const double p1 = smod_d(fma(-2.0 * jm, c, p0), m, inv_m);
+      u0[r >> 2] |= ((unsigned)(int)p0 & 0xffu) << (8 * (r & 3));
+      u1[r >> 2] |= ((unsigned)(int)p1 & 0xffu) << (8 * (r & 3));
     }
     o[(2 * i) * plane] = u0;
     o[(2 * i + 1) * plane] = u1;
@@ -337,7 +336,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
 }
 
 // Recovery of each upper-triangle entry from its residues: value = M * frac(sum_i r_i y_i / m_i),
-// times 2^-(f_row + f_col).  sum r_i h_i is exact (h_i on a 2^-42 grid, |r_i| < 2^7, n <= 14
+// times 2^-(f_row + f_col).  sum r_i h_i is exact (h_i on a 2^-42 grid, |r_i| < 2^7, n <= 13
 // terms), so the rounding to the nearest integer is exact and the fraction keeps FP64
 // precision.  One thread per (row, col).
 template <bool REAL>

@@ -92,9 +92,9 @@ def test_create_rejects_split_slice_count(precision, n_slices):
     assert "n_slices" in N.last_error(None)
 
 
-@pytest.mark.parametrize("n_moduli", [0, 6, 7, 15, 24])
+@pytest.mark.parametrize("n_moduli", [0, 6, 7, 14, 15, 24])
 def test_create_rejects_residue_moduli_count(n_moduli):
-    """The residue form takes 8..14 moduli (checked before any device call)."""
+    """The residue form takes 8..13 moduli (checked before any device call)."""
     cfg, keep = _config(precision=N.HSB_SPLIT_CRT, n_slices=n_moduli)
     assert _create(cfg)[0] == N.HSB_ERR_ARG
     assert "moduli" in N.last_error(None)
