@@ -176,7 +176,7 @@ def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
                 "fp64_ms_adjacent": round(ms_fp64_adj, 4), "speedup_vs_headline_fp64": round(ms_fp64 / ms, 4),
                 "stages_ms": {"coefficients": round(stage_ms[0], 4),
                               "t_products_and_split_operands": round(stage_ms[1], 4),
-                              "split_contraction": round(stage_ms[2], 4)},
+                              "split_contraction": round(stage_ms[2], 4), "recombination": round(stage_ms[3], 4)},
                 "rel_err_vs_fp64": {"H": eh, "S": es}, "meets_1e-10": bool(eh <= 1e-10 and es <= 1e-10),
                 "slice_mfma": {"executed_ops": mfma_ops, "achieved": round(rate, 2), "peak": peak, "unit": unit,
                                "frac": round(rate / peak, 4)}}
@@ -390,6 +390,62 @@ def real_leg(args) -> dict:
             "flops_complex": flops_c, "real_tflops": round(flops_r / (ms_r * 1e-3) / 1e12, 4),
             "complex_imag_rel": imag, "rel_err_vs_complex": {"H": eh, "S": es}, "int8_split": int8,
             "crt_split": crt}
+
+
+def small_leg(args) -> dict:
+    """One k-point of the 16-atom l_max 8 cell at N_G = 3000 (k_c = 1296): the whole
+    forward, its contraction against the FP64 MFMA roofline (executed 3M flops), with
+    the automatic split of the stacked index (600 tiles: fewer than 4 per compute unit)
+    and without it."""
+    import torch
+
+    from flapw_cells import make_case
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
+    case = make_case(1)
+    n, n_at, n_l = case["n_g"], case["n_atoms"], case["n_l"]
+    k_c = n_at * n_l
+    flops = 16.0 * k_c * n * (n + 1) + 32.0 * n_at * n_l * n_l * n
+    flops_exec = 12.0 * k_c * n * (n + 1)
+    b = HSBuilder.from_case(case)
+    g, tau, T = case_tensors(case)
+    H = torch.empty((n, n), dtype=torch.complex128, device="cuda")
+    S = torch.empty_like(H)
+    reps = max(10, 4 * args.steps)
+    out = {"workload": case["name"], "n_g": n, "k_c": k_c, "flops_per_step": flops,
+           "algorithmic_flops_per_launch": flops_exec}
+    for mode, key in ((1, "split_k_auto"), (0, "one_pass")):
+        b.set_option(N.HSB_OPT_SPLIT_K, mode)
+        wsb = b.workspace_bytes(N.HSB_MODE_FORWARD, [n])
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+        for _ in range(3):
+            b.forward_raw(case["k_frac"], n, g, tau, T, H, S, ws, wsb)
+        torch.cuda.synchronize()
+        b.set_timing(True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            code = b.forward_raw(case["k_frac"], n, g, tau, T, H, S, ws, wsb)
+            if code != N.HSB_OK:
+                raise N.HSBuildError(code, N.last_error(b._h))
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        st, _ = b.stage_times()
+        b.set_timing(False)
+        del ws
+        achieved = flops_exec / (st[2] * 1e-3) / 1e12
+        out[key] = {"ms_per_step": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 4),
+                    "stages_ms": {"coefficients": round(st[0], 4), "t_products": round(st[1], 4),
+                                  "hs_contraction": round(st[2], 4), "segment_sum": round(st[3], 4)},
+                    "roofline": {"kernel": "k_hs_fp64_sk" if mode else "k_hs_fp64", "bound": "mfma",
+                                 "achieved": round(achieved, 4), "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                                 "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4)}}
+        log("N_G 3000 cell (%s): %.3f ms per forward, contraction %.3f ms = %.1f TFLOP/s executed (%.3f of peak), "
+            "segment sum %.3f ms" % (key, ms, st[2], achieved, achieved / FP64_MFMA_PEAK_TFLOPS, st[3]))
+    b.close()
+    torch.cuda.empty_cache()
+    return out
 
 
 def eigen_leg(args) -> dict:
@@ -695,6 +751,7 @@ def main() -> int:
     ap.add_argument("--no-factored", action="store_true", help="skip the type-factored leg")
     ap.add_argument("--no-hsdla", action="store_true", help="skip the rocBLAS HSDLA baseline leg")
     ap.add_argument("--no-real", action="store_true", help="skip the real-symmetric (inversion) leg")
+    ap.add_argument("--no-small", action="store_true", help="skip the one-k-point N_G 3000 leg (16-atom cell)")
     ap.add_argument("--no-eigen", action="store_true", help="skip the generalized eigensolve leg")
     ap.add_argument("--no-device-probe", action="store_true", help="skip the matrix-core rate probe")
     ap.add_argument("--split-slices", type=int, default=5,
@@ -817,7 +874,7 @@ def main() -> int:
                     "peak; the 3-product complex form lets it pass 100%",
         "contraction_options": options,
         "stages_ms": {"coefficients": round(stage_ms[0], 4), "t_products": round(stage_ms[1], 4),
-                      "hs_contraction": round(stage_ms[2], 4)},
+                      "hs_contraction": round(stage_ms[2], 4), "segment_sum": round(stage_ms[3], 4)},
         "roofline": {"kernel": "k_hs_fp64", "bound": "mfma", "achieved": round(hs_tflops, 4),
                      "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                      "frac": round(hs_tflops / FP64_MFMA_PEAK_TFLOPS, 4),
@@ -845,6 +902,8 @@ def main() -> int:
             result["split_speedup"] = result["split"]["speedup"]
     del H, S, ws
     torch.cuda.empty_cache()
+    if not args.no_small:
+        result["cfg1"] = small_leg(args)
     if not args.no_real:
         result["real_symmetric"] = real_leg(args)
     if not args.no_adjoint:

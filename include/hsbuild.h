@@ -240,7 +240,8 @@ int hsbuild_backward(hsbuild_t h, const double k_frac[3], int32_t ng, const int3
  * int32[n_k]; g: device int32, the n_k G lists concatenated in k order;
  * out_off: host int64[n_k], element offsets of each k's ng x ng block in H and
  * S (blocks must not overlap: HSB_ERR_SHAPE).  Each block holds exactly what
- * hsbuild_forward writes for that k (bitwise, with the same options), upper
+ * hsbuild_forward writes for that k (bitwise, with the same options and
+ * HSB_OPT_SPLIT_K = 0; to FP64 rounding where the forward splits), upper
  * triangle only.  FP64 only: a handle with a split precision gets
  * HSB_ERR_UNSUPPORTED.  The calls are recorded once into a hipGraph, replayed
  * while n_k, k_frac, ng, out_off and the device pointers stay the same (the
@@ -253,14 +254,18 @@ int hsbuild_batch(hsbuild_t h, int32_t n_k, const double* k_frac, const int32_t*
 
 /* Stage timing with HIP events recorded on the call's stream, for profiling.
  * hsbuild_set_timing(h, 1) creates an event pool and clears the record;
- * while enabled, each hsbuild_forward records events around its three stages
- * (0: coefficients and tables, 1: per-atom T products and, in the split
- * forms, the column scales and the slices or residues of the operands, 2: the
- * H/S contraction, with the split forms' recombination), for up to
- * HSB_TIMING_CAPACITY calls (later calls are not
- * recorded).  hsbuild_stage_times waits for the recorded events and returns
- * the average milliseconds of each stage over the recorded calls (ms_avg[3])
- * and their number.  hsbuild_set_timing(h, 0) destroys the pool. */
+ * while enabled, each forward entry point (hsbuild_forward, _static,
+ * _coefficients, _factored, _real, _hsdla) records events around its
+ * HSB_TIMING_STAGES stages (0: coefficients and tables, 1: per-atom T
+ * products and, in the split forms, the column scales and the slices or
+ * residues of the operands, 2: the H/S contraction kernels, 3: the sum of
+ * the stacked-index segments or the residue recombination, empty for the
+ * one-pass contractions), for up to HSB_TIMING_CAPACITY calls (later calls
+ * are not recorded).  hsbuild_stage_times waits for the recorded events and
+ * returns the average milliseconds of each stage over the recorded calls
+ * (ms_avg[HSB_TIMING_STAGES]) and their number.  hsbuild_set_timing(h, 0)
+ * destroys the pool. */
+#define HSB_TIMING_STAGES 4
 #define HSB_TIMING_CAPACITY 256
 int hsbuild_set_timing(hsbuild_t h, int32_t enable);
 int hsbuild_stage_times(hsbuild_t h, double* ms_avg, int32_t* n_calls);
@@ -276,8 +281,18 @@ int hsbuild_stage_times(hsbuild_t h, double* ms_avg, int32_t* n_calls);
  * 8 (32 x 32 per wave, two per SIMD; three real products per complex one, the
  * 3M form; 128 x 128 tiles of 32 x 64 for hsbuild_forward_real, which is
  * real); default 8.  The two complex forms agree to FP64 rounding, not
- * bitwise.  Setting an option drops a captured batch graph. */
-enum { HSB_OPT_TILE_GROUP = 1, HSB_OPT_HS_WAVES = 2 };
+ * bitwise.
+ * HSB_OPT_SPLIT_K: 1 (default) lets the 8-wave FP64 forward cut the stacked
+ * index into segments when the upper triangle has fewer than 4 tiles per
+ * compute unit (2..8 segments of at least 256 rows, chosen by a model of the
+ * rounds of workgroups): partial tiles go to the workspace
+ * (hsbuild_workspace_bytes includes them) and are added in a fixed order, so
+ * small bases fill the GPU; the results agree with the one-pass contraction to
+ * FP64 rounding, not bitwise, and repeat bitwise.  0 never splits; k = 2..8
+ * always cuts k segments (fewer if the stacked index is too short).
+ * Setting HSB_OPT_TILE_GROUP or HSB_OPT_HS_WAVES drops a captured batch graph
+ * (the batch contraction never splits). */
+enum { HSB_OPT_TILE_GROUP = 1, HSB_OPT_HS_WAVES = 2, HSB_OPT_SPLIT_K = 3 };
 int hsbuild_set_option(hsbuild_t h, int32_t option, int32_t value);
 int hsbuild_get_option(hsbuild_t h, int32_t option, int32_t* value);
 

@@ -50,6 +50,8 @@ HSB_STATIC_SCRATCH_BYTES = 256 << 20
 
 HSB_OPT_TILE_GROUP = 1
 HSB_OPT_HS_WAVES = 2
+HSB_OPT_SPLIT_K = 3
+HSB_TIMING_STAGES = 4
 
 
 class HsbConfig(ctypes.Structure):

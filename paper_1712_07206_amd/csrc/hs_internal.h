@@ -51,6 +51,8 @@ struct Layout {
   int n = 0, n_pad = 0, K = 0, K_pad = 0;
   size_t W = 0, Y = 0, ang = 0, ab = 0, kv = 0, lam = 0, consts = 0, end = 0;
   size_t WL = 0;  // lam W (the FP64 contraction's S operand), forward in FP64 only
+  int ns = 1;              // FP64 forward: segments of the stacked index (split contraction when > 1)
+  size_t skH = 0, skS = 0;  // FP64 forward with ns > 1: partial H and S per segment
   size_t PH = 0, PS = 0, partT = 0, partTau = 0;  // backward only
   size_t WT = 0, gHp = 0, gSp = 0;                // backward: operands of the 3M products
   size_t TT = 0;                                  // T^T per type, zero-padded (T products)
@@ -58,7 +60,7 @@ struct Layout {
   int K_pad2 = 0;                                  // split only: stacked rows padded to 32
   size_t mx = 0, scale = 0, slL = 0, slS = 0, slY = 0;  // split only (slL, slS, slY: residue planes in the CRT form)
   int K64 = 0, n_res = 0;                              // residue form: rows padded to 64, columns to 256
-  size_t crPart = 0, crRes = 0;                        // residue form: partial column norms, product residues
+  size_t crPart = 0, crRes = 0, crResH = 0;            // residue form: partial column norms, residues of S, H
   // factored only: rows [R_f] of X (E and W0 blocks), XL = lam X, Yx (Y0 on W0 rows, 0 on E rows)
   int R_f = 0;
   size_t X = 0, XL = 0, Yx = 0, lamx = 0, kind = 0, tau0 = 0;
@@ -116,6 +118,20 @@ hipError_t launch_tprod3m(const CellArgs& c, const double2* TT, const double2* W
 // four-MFMA form (lam applied to W while staging).
 hipError_t launch_hs_fp64(const double2* W, const double2* WL, const double2* Y, const double* lam, int K_pad, int n,
                           int n_pad, int gr, int waves, double2* H, double2* S, int64_t ldh, hipStream_t s);
+
+// Segments of the stacked index the 8-wave FP64 contraction is cut into (1: none) when the upper
+// triangle has fewer than 4 tiles per compute unit: the count (up to 8, segments of at least 256
+// rows) with the least rounds of workgroups times (rows per segment + 128).
+int hs_split_k(int n_pad, int K_pad, int num_cus);
+// Rows per segment (a multiple of the 16-row chunk; the last segment takes the rest).
+int hs_split_rows(int K_pad, int ns);
+// The 8-wave (3M) contraction in ns segments of the stacked index: partial tiles into Hp, Sp
+// ([ns][n_pad][n_pad] each); launch_sk_reduce then sets H, S = the segments added in order
+// (upper triangle, row <= col < n).
+hipError_t launch_hs_fp64_sk(const double2* W, const double2* WL, const double2* Y, int K_pad, int ns, int n,
+                             int n_pad, int gr, double2* Hp, double2* Sp, hipStream_t s);
+hipError_t launch_sk_reduce(const double2* Hp, const double2* Sp, int ns, int n, int n_pad, double2* H, double2* S,
+                            int64_t ldh, hipStream_t s);
 
 // The same contraction keeping only the real parts, Re(W^H Y) and Re(W^H lam W), as doubles.
 hipError_t launch_hs_fp64_real(const double2* W, const double2* WL, const double2* Y, const double* lam, int K_pad,

@@ -33,6 +33,7 @@ struct hsbuild_s {
   CrtConsts crt{};  // moduli of the residue form (HSB_SPLIT_CRT)
   int tile_group = 8;  // HSB_OPT_TILE_GROUP
   int hs_waves = 8;    // HSB_OPT_HS_WAVES
+  int split_k = 1;     // HSB_OPT_SPLIT_K
   double lattice[9];
   CellArgs cell;              // kfrac filled per call
   TypeConsts* consts = nullptr;  // pinned host copy, source of the per-call upload
@@ -167,6 +168,14 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
   }
   if ((mode == HSB_MODE_FORWARD || mode == HSB_MODE_REAL) && h.precision == HSB_FP64)
     L.WL = take((size_t)L.K_pad * np * sizeof(double2));
+  if (mode == HSB_MODE_FORWARD && h.precision == HSB_FP64 && h.hs_waves == 8 && h.split_k) {
+    L.ns = h.split_k == 1 ? hs_split_k(L.n_pad, L.K_pad, h.num_cus) : h.split_k;
+    while (L.ns > 1 && hs_split_rows(L.K_pad, L.ns) * (L.ns - 1) >= L.K_pad) --L.ns;  // every segment holds rows
+    if (L.ns > 1) {
+      L.skH = take((size_t)L.ns * np * np * sizeof(double2));
+      L.skS = take((size_t)L.ns * np * np * sizeof(double2));
+    }
+  }
   if ((mode == HSB_MODE_FORWARD || mode == HSB_MODE_REAL) && h.precision == HSB_SPLIT_CRT) {
     L.K64 = (int)round_up(L.K, kCrtRows);
     L.n_res = crt_cols(ng);
@@ -178,6 +187,7 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
     L.slS = take(planes);
     L.slY = take(planes);
     L.crRes = take((size_t)h.crt.n_mod * nr * nr * (mode == HSB_MODE_REAL ? 1 : 2));
+    L.crResH = take((size_t)h.crt.n_mod * nr * nr * (mode == HSB_MODE_REAL ? 1 : 2));
   } else if ((mode == HSB_MODE_FORWARD && h.precision != HSB_FP64) ||
              (mode == HSB_MODE_REAL && h.precision == HSB_SPLIT_INT8)) {
     L.K_pad2 = (int)round_up(L.K, 32);
@@ -237,11 +247,13 @@ int launched(hsbuild_t h, hipError_t e, const char* what) {
   return HSB_OK;
 }
 
-// Records stage boundary `idx` (0..3) of the current call when timing is on.
+// Records stage boundary `idx` (0..kMarks-1) of the current call when timing is on; the last one
+// closes the call's record.
+constexpr int kMarks = HSB_TIMING_STAGES + 1;
 void mark(hsbuild_t h, int idx, hipStream_t s) {
   if (h->capturing || h->events.empty() || h->n_timed >= HSB_TIMING_CAPACITY) return;
-  (void)hipEventRecord(h->events[4 * h->n_timed + idx], s);
-  if (idx == 3) ++h->n_timed;
+  (void)hipEventRecord(h->events[kMarks * h->n_timed + idx], s);
+  if (idx == kMarks - 1) ++h->n_timed;
 }
 
 void destroy_events(hsbuild_t h) {
@@ -299,6 +311,28 @@ int enqueue_operands(hsbuild_t h, const Layout& L, const double k_frac[3], const
   return rc;
 }
 
+// The FP64 H/S contraction of the forward (one pass, or in L.ns segments of the stacked index).
+// Marks 3 (after the contraction) and 4 (after the segments' sum).
+int enqueue_fp64_hs(hsbuild_t h, const Layout& L, char* w, int ng, void* H, void* S, hipStream_t s) {
+  const double2 *W = (const double2*)(w + L.W), *WL = (const double2*)(w + L.WL), *Y = (const double2*)(w + L.Y);
+  int rc;
+  if (L.ns > 1) {
+    double2 *Hp = (double2*)(w + L.skH), *Sp = (double2*)(w + L.skS);
+    rc = launched(h, launch_hs_fp64_sk(W, WL, Y, L.K_pad, L.ns, ng, L.n_pad, h->tile_group, Hp, Sp, s),
+                  "k_hs_fp64_sk");
+    mark(h, 3, s);
+    if (!rc)
+      rc = launched(h, launch_sk_reduce(Hp, Sp, L.ns, ng, L.n_pad, (double2*)H, (double2*)S, ng, s), "k_sk_reduce");
+  } else {
+    rc = launched(h, launch_hs_fp64(W, WL, Y, (const double*)(w + L.lam), L.K_pad, ng, L.n_pad, h->tile_group,
+                                    h->hs_waves, (double2*)H, (double2*)S, ng, s),
+                  "k_hs_fp64");
+    mark(h, 3, s);
+  }
+  mark(h, 4, s);
+  return rc;
+}
+
 // Residue form of the split contraction (complex, or real parts only): column scales, the
 // residue planes of W, lam W and Y, then per matrix the residue contraction and the FP64
 // recombination.  L.K is the number of stacked rows used (the representatives' in the real case).
@@ -319,14 +353,18 @@ int enqueue_crt(hsbuild_t h, const Layout& L, char* w, void* H, void* S, bool re
     rc = launched(h, launch_crt_residues(cc, Y, lam, 0, L.K, L.n_pad, nr, QK, sc + 2 * nr, w + L.slY, s), "residues");
   mark(h, 2, s);  // (again) the operand preparation ends here: the contraction stage starts
   if (!rc)
-    rc = launched(h, launch_hs_crt(cc, real, w + L.slL, w + L.slS, QK, L.n, nr, h->tile_group, h->hs_waves, w + L.crRes, s),
+    rc = launched(h, launch_hs_crt(cc, real, w + L.slL, w + L.slS, QK, L.n, nr, h->tile_group, h->hs_waves,
+                                   w + L.crRes, s),
                   "residue contraction (S)");
+  if (!rc)
+    rc = launched(h, launch_hs_crt(cc, real, w + L.slL, w + L.slY, QK, L.n, nr, h->tile_group, h->hs_waves,
+                                   w + L.crResH, s),
+                  "residue contraction (H)");
+  mark(h, 3, s);
   if (!rc) rc = launched(h, launch_crt_combine(cc, real, w + L.crRes, nr, sc, sc + nr, L.n, S, s), "recombination (S)");
   if (!rc)
-    rc = launched(h, launch_hs_crt(cc, real, w + L.slL, w + L.slY, QK, L.n, nr, h->tile_group, h->hs_waves, w + L.crRes, s),
-                  "residue contraction (H)");
-  if (!rc)
-    rc = launched(h, launch_crt_combine(cc, real, w + L.crRes, nr, sc, sc + 2 * nr, L.n, H, s), "recombination (H)");
+    rc = launched(h, launch_crt_combine(cc, real, w + L.crResH, nr, sc, sc + 2 * nr, L.n, H, s), "recombination (H)");
+  mark(h, 4, s);
   return rc;
 }
 
@@ -357,9 +395,12 @@ int enqueue_split(hsbuild_t h, const Layout& L, char* w, double2* H, double2* S,
                                    L.n_pad, h->tile_group, S, s),
                 "split contraction (S)");
   if (rc) return rc;
-  return launched(h, launch_hs_split(h->precision, h->n_slices, w + L.slL, w + L.slY, sc, sc + 2 * L.n_pad, QK, L.n,
-                                     L.n_pad, h->tile_group, H, s),
-                  "split contraction (H)");
+  rc = launched(h, launch_hs_split(h->precision, h->n_slices, w + L.slL, w + L.slY, sc, sc + 2 * L.n_pad, QK, L.n,
+                                   L.n_pad, h->tile_group, H, s),
+                "split contraction (H)");
+  mark(h, 3, s);  // the slice forms recombine inside the contraction
+  mark(h, 4, s);
+  return rc;
 }
 
 // Real-symmetric int8 split contraction on the representatives' rows (L.K): column scales and
@@ -390,9 +431,12 @@ int enqueue_split_real(hsbuild_t h, const Layout& L, char* w, double* H, double*
                                          h->tile_group, S, s),
                 "split contraction (real S)");
   if (rc) return rc;
-  return launched(h, launch_hs_split8_real(h->n_slices, w + L.slL, w + L.slY, sc, sc + 2 * L.n_pad, QK, L.n, L.n_pad,
-                                           h->tile_group, H, s),
-                  "split contraction (real H)");
+  rc = launched(h, launch_hs_split8_real(h->n_slices, w + L.slL, w + L.slY, sc, sc + 2 * L.n_pad, QK, L.n, L.n_pad,
+                                         h->tile_group, H, s),
+                "split contraction (real H)");
+  mark(h, 3, s);
+  mark(h, 4, s);
+  return rc;
 }
 
 // Operand builds of the k-points run in kBranches parallel graph branches, each with its own tables.
@@ -696,14 +740,10 @@ int forward_enqueue(hsbuild_t h, const Layout& L, const double k_frac[3], int32_
   mark(h, 0, s);
   if ((rc = enqueue_operands(h, L, k_frac, g, tau, T, w, s))) return rc;
   if (h->precision == HSB_FP64) {
-    rc = launched(h, launch_hs_fp64((const double2*)(w + L.W), (const double2*)(w + L.WL), (const double2*)(w + L.Y),
-                                    (const double*)(w + L.lam), L.K_pad, ng, L.n_pad, h->tile_group, h->hs_waves,
-                                    (double2*)H, (double2*)S, ng, s),
-                  "k_hs_fp64");
+    rc = enqueue_fp64_hs(h, L, w, ng, H, S, s);  // marks 3 and 4
   } else {
-    rc = enqueue_split(h, L, w, (double2*)H, (double2*)S, s);
+    rc = enqueue_split(h, L, w, (double2*)H, (double2*)S, s);  // marks 2 (again), 3 and 4
   }
-  mark(h, 3, s);
   return rc;
 }
 
@@ -823,6 +863,7 @@ int hsbuild_forward_factored(hsbuild_t h, const double k_frac[3], int32_t ng, co
                                   (double2*)H, (double2*)S, ng, s),
                 "k_hs_fact");
   mark(h, 3, s);
+  mark(h, 4, s);
   return rc;
 }
 
@@ -915,8 +956,9 @@ int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const 
       rc = launched(h, launch_hs_fp64_real((const double2*)(w + L.W), WL, Y, lam, Lr.K_pad, ng, L.n_pad,
                                            h->tile_group, h->hs_waves, H, S, ng, s),
                     "k_hs_fp64 (real)");
+    mark(h, 3, s);
+    mark(h, 4, s);
   }
-  mark(h, 3, s);
   return rc;
 }
 
@@ -978,6 +1020,7 @@ int hsbuild_forward_hsdla(hsbuild_t h, int32_t algorithm, const double k_frac[3]
                          (double2*)S, s, false, err))
     return fail(h, HSB_ERR_DEVICE, "%s", err.c_str());
   mark(h, 3, s);
+  mark(h, 4, s);
   return HSB_OK;
 }
 
@@ -998,6 +1041,7 @@ int hsbuild_forward_coefficients(hsbuild_t h, int32_t ng, const void* coef, cons
   CellArgs c = h->cell;
   double2* W = (double2*)(w + L.W);
   double2* Y = (double2*)(w + L.Y);
+  mark(h, 0, s);
   hipError_t e = hipMemcpyAsync(w + L.consts, h->consts, sizeof(TypeConsts), hipMemcpyHostToDevice, s);
   if ((rc = launched(h, e, "upload of type constants"))) return rc;
   if ((rc = launched(h, launch_lambda(c, (const TypeConsts*)(w + L.consts), L.K_pad, (double*)(w + L.lam), s),
@@ -1012,6 +1056,7 @@ int hsbuild_forward_coefficients(hsbuild_t h, int32_t ng, const void* coef, cons
   }
   if ((rc = launched(h, launch_zero_rows(W, L.n_pad, L.K, L.K_pad, s), "k_zero_rows"))) return rc;
   if ((rc = launched(h, launch_zero_rows(Y, L.n_pad, L.K, L.K_pad, s), "k_zero_rows"))) return rc;
+  mark(h, 1, s);
   if ((rc = launched(h, launch_tpad((const double2*)T, h->n_types, 2 * h->n_l, (double2*)(w + L.TT), s), "k_tpad")))
     return rc;
   if ((rc = launched(h, launch_tprod(c, (const double2*)(w + L.TT), W, Y, L.n_pad, s), "k_tprod3m"))) return rc;
@@ -1019,10 +1064,10 @@ int hsbuild_forward_coefficients(hsbuild_t h, int32_t ng, const void* coef, cons
     double2* WL = (double2*)(w + L.WL);
     if ((rc = launched(h, launch_scale_rows(W, (const double*)(w + L.lam), L.K_pad, L.n_pad, WL, s), "k_scale_rows")))
       return rc;
-    return launched(h, launch_hs_fp64(W, WL, Y, (const double*)(w + L.lam), L.K_pad, ng, L.n_pad, h->tile_group,
-                                      h->hs_waves, (double2*)H, (double2*)S, ng, s),
-                    "k_hs_fp64");
+    mark(h, 2, s);
+    return enqueue_fp64_hs(h, L, w, ng, H, S, s);
   }
+  mark(h, 2, s);
   return enqueue_split(h, L, w, (double2*)H, (double2*)S, s);
 }
 
@@ -1211,7 +1256,7 @@ int hsbuild_set_timing(hsbuild_t h, int32_t enable) {
   if (!h) return HSB_ERR_ARG;
   destroy_events(h);
   if (!enable) return HSB_OK;
-  h->events.resize(4 * HSB_TIMING_CAPACITY);
+  h->events.resize(kMarks * HSB_TIMING_CAPACITY);
   for (size_t i = 0; i < h->events.size(); ++i) {
     if (hipEventCreate(&h->events[i]) != hipSuccess) {
       h->events.resize(i);
@@ -1225,18 +1270,18 @@ int hsbuild_set_timing(hsbuild_t h, int32_t enable) {
 int hsbuild_stage_times(hsbuild_t h, double* ms_avg, int32_t* n_calls) {
   if (!h || !ms_avg || !n_calls) return HSB_ERR_ARG;
   if (h->events.empty()) return fail(h, HSB_ERR_ARG, "timing is not enabled");
-  double acc[3] = {0.0, 0.0, 0.0};
+  double acc[HSB_TIMING_STAGES] = {};
   for (int c = 0; c < h->n_timed; ++c) {
-    if (hipEventSynchronize(h->events[4 * c + 3]) != hipSuccess)
+    if (hipEventSynchronize(h->events[kMarks * c + kMarks - 1]) != hipSuccess)
       return fail(h, HSB_ERR_DEVICE, "hipEventSynchronize failed");
-    for (int k = 0; k < 3; ++k) {
+    for (int k = 0; k < HSB_TIMING_STAGES; ++k) {
       float ms = 0.0f;
-      if (hipEventElapsedTime(&ms, h->events[4 * c + k], h->events[4 * c + k + 1]) != hipSuccess)
+      if (hipEventElapsedTime(&ms, h->events[kMarks * c + k], h->events[kMarks * c + k + 1]) != hipSuccess)
         return fail(h, HSB_ERR_DEVICE, "hipEventElapsedTime failed");
       acc[k] += ms;
     }
   }
-  for (int k = 0; k < 3; ++k) ms_avg[k] = h->n_timed ? acc[k] / h->n_timed : 0.0;
+  for (int k = 0; k < HSB_TIMING_STAGES; ++k) ms_avg[k] = h->n_timed ? acc[k] / h->n_timed : 0.0;
   *n_calls = h->n_timed;
   return HSB_OK;
 }
@@ -1255,6 +1300,10 @@ int hsbuild_set_option(hsbuild_t h, int32_t option, int32_t value) {
       if (value != h->hs_waves) drop_graph(h);
       h->hs_waves = value;
       return HSB_OK;
+    case HSB_OPT_SPLIT_K:
+      if (value < 0 || value > 8) return fail(h, HSB_ERR_ARG, "split-K option %d outside [0, 8]", value);
+      h->split_k = value;  // the batch contraction never splits: its graph stays valid
+      return HSB_OK;
     default:
       return fail(h, HSB_ERR_ARG, "unknown option %d", option);
   }
@@ -1268,6 +1317,9 @@ int hsbuild_get_option(hsbuild_t h, int32_t option, int32_t* value) {
       return HSB_OK;
     case HSB_OPT_HS_WAVES:
       *value = h->hs_waves;
+      return HSB_OK;
+    case HSB_OPT_SPLIT_K:
+      *value = h->split_k;
       return HSB_OK;
     default:
       return fail(h, HSB_ERR_ARG, "unknown option %d", option);

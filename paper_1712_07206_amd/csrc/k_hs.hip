@@ -30,6 +30,8 @@
 // range of it; every tile costs the same (same stacked width), so a static
 // walk balances.  Both run the same tile body, so a batched H(k) is bitwise
 // equal to the single-k one.
+#include <cmath>
+
 #include "hs_internal.h"
 #include "tiles.h"
 
@@ -358,6 +360,45 @@ __global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64(const d2* __restrict__ 
   else hs_tile<WR, false>(sm, W, Y, lam, K_pad, n, n_pad, row0, col0, H, S, ldh);  // 64 x 32 per wave: plain form
 }
 
+// The 8-wave contraction with the stacked index cut into ns segments of kseg rows: workgroup
+// w = (segment p, tile t), segments outermost so the tiles running together read the same
+// rows; each writes its partial upper-triangle tile of H and S into Hp[p], Sp[p] ([n_pad]^2
+// each).  k_sk_reduce adds the segments in order p = 0, 1, ..., so results are reproducible.
+__global__ void __launch_bounds__(512, 1) k_hs_fp64_sk(const d2* __restrict__ W, const d2* __restrict__ WL,
+                                                       const d2* __restrict__ Y, int K_pad, int kseg, int n,
+                                                       int n_pad, int nbr, int num_wg, int total, int gr,
+                                                       d2* __restrict__ Hp, d2* __restrict__ Sp) {
+  __shared__ Smem sm;
+  const int x = blockIdx.x % kXcds;
+  int start, len;
+  xcd_range(x, total, start, len);
+  const int w = start + blockIdx.x / kXcds;
+  const int p = w / num_wg;
+  int row0, col0;
+  tile_origin(w - p * num_wg, nbr, gr, row0, col0);
+  if (col0 >= n) return;
+  const int k0 = p * kseg, kc = min(kseg, K_pad - k0);
+  const int64_t off = (int64_t)k0 * n_pad, plane = (int64_t)n_pad * n_pad;
+  hs_tile3m<4, true>(sm, W + off, WL + off, Y + off, kc, n_pad, n_pad, row0, col0, n, n, true, Hp + p * plane,
+                     Sp + p * plane, n_pad);
+}
+
+__global__ void __launch_bounds__(256) k_sk_reduce(const d2* __restrict__ Hp, const d2* __restrict__ Sp, int ns,
+                                                   int n, int n_pad, d2* __restrict__ H, d2* __restrict__ S,
+                                                   int64_t ldh) {
+  const int row = blockIdx.y;
+  const int col = blockIdx.x * 256 + threadIdx.x;
+  if (col >= n || col < row) return;
+  const int64_t plane = (int64_t)n_pad * n_pad, e = (int64_t)row * n_pad + col;
+  d2 h = Hp[e], sv = Sp[e];
+  for (int p = 1; p < ns; ++p) {
+    h += Hp[p * plane + e];
+    sv += Sp[p * plane + e];
+  }
+  H[(int64_t)row * ldh + col] = h;
+  S[(int64_t)row * ldh + col] = sv;
+}
+
 template <int WR>
 __global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64_batch(const d2* __restrict__ ws, const double* __restrict__ lam,
                                                            int K_pad, const BatchMeta* __restrict__ meta, int n_k,
@@ -588,6 +629,41 @@ hipError_t launch_hs_fp64(const double2* W, const double2* WL, const double2* Y,
   else
     hipLaunchKernelGGL((k_hs_fp64<2, false>), dim3(num_wg), dim3(256), 0, s, (const d2*)W, (const d2*)WL,
                        (const d2*)Y, lam, K_pad, n, n_pad, nbr, num_wg, gr, (void*)H, (void*)S, ldh);
+  return hipGetLastError();
+}
+
+int hs_split_k(int n_pad, int K_pad, int num_cus) {
+  // time model: rounds of workgroups on the compute units times (rows per segment + a fixed
+  // cost of a workgroup worth about 128 rows: the pipeline start and the tile's stores)
+  const int tiles = hs_tiles(n_pad);
+  if (tiles >= 4 * num_cus || num_cus < 1) return 1;
+  auto cost = [&](int ns) {
+    const double rounds = std::ceil((double)tiles * ns / num_cus);
+    return rounds * (hs_split_rows(K_pad, ns) + 128.0);
+  };
+  int best = 1;
+  for (int ns = 2; ns <= 8 && hs_split_rows(K_pad, ns) >= 256; ++ns)
+    if (cost(ns) < cost(best)) best = ns;
+  return best;
+}
+
+int hs_split_rows(int K_pad, int ns) { return (int)round_up((K_pad + ns - 1) / ns, BK); }
+
+hipError_t launch_hs_fp64_sk(const double2* W, const double2* WL, const double2* Y, int K_pad, int ns, int n,
+                             int n_pad, int gr, double2* Hp, double2* Sp, hipStream_t s) {
+  const int nbr = n_pad / BM;
+  const int num_wg = hs_tiles(n_pad), total = num_wg * ns;
+  const int kseg = hs_split_rows(K_pad, ns);
+  if (K_pad % BK || kseg * (ns - 1) >= K_pad) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_hs_fp64_sk, dim3(total), dim3(512), 0, s, (const d2*)W, (const d2*)WL, (const d2*)Y, K_pad,
+                     kseg, n, n_pad, nbr, num_wg, total, gr, (d2*)Hp, (d2*)Sp);
+  return hipGetLastError();
+}
+
+hipError_t launch_sk_reduce(const double2* Hp, const double2* Sp, int ns, int n, int n_pad, double2* H, double2* S,
+                            int64_t ldh, hipStream_t s) {
+  hipLaunchKernelGGL(k_sk_reduce, dim3((n + 255) / 256, n), dim3(256), 0, s, (const d2*)Hp, (const d2*)Sp, ns, n,
+                     n_pad, (d2*)H, (d2*)S, ldh);
   return hipGetLastError();
 }
 

@@ -345,11 +345,12 @@ class HSBuilder:
         N.check(N.lib().hsbuild_set_timing(self._h, 1 if enable else 0), self._h)
 
     def stage_times(self):
-        """(average ms of [coefficients, T products, contraction], recorded calls)."""
-        ms = (ctypes.c_double * 3)()
+        """(average ms of [coefficients, T products (and split operands), contraction kernels,
+        recombination], recorded calls)."""
+        ms = (ctypes.c_double * N.HSB_TIMING_STAGES)()
         n = ctypes.c_int32()
         N.check(N.lib().hsbuild_stage_times(self._h, ms, ctypes.byref(n)), self._h)
-        return [ms[0], ms[1], ms[2]], int(n.value)
+        return [ms[i] for i in range(N.HSB_TIMING_STAGES)], int(n.value)
 
     def forward_raw(self, k_frac, ng: int, g, tau, T, H, S, ws, ws_bytes: int) -> int:
         """Direct call with pointers already validated by the caller (timing loops)."""

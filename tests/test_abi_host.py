@@ -216,7 +216,7 @@ def test_options_null_handle():
     assert L.hsbuild_set_option(None, N.HSB_OPT_TILE_GROUP, 4) == N.HSB_ERR_ARG
     assert L.hsbuild_get_option(None, N.HSB_OPT_TILE_GROUP, ctypes.byref(v)) == N.HSB_ERR_ARG
     assert L.hsbuild_set_timing(None, 1) == N.HSB_ERR_ARG
-    ms = (ctypes.c_double * 3)()
+    ms = (ctypes.c_double * N.HSB_TIMING_STAGES)()
     n = ctypes.c_int32()
     assert L.hsbuild_stage_times(None, ms, ctypes.byref(n)) == N.HSB_ERR_ARG
 

@@ -22,8 +22,12 @@ def _full(M):
 
 
 def _setup(case):
+    """A builder whose single-k forwards run the one-pass contraction (HSB_OPT_SPLIT_K = 0),
+    the form the batch's blocks equal bitwise; the batch itself never splits."""
+    from paper_1712_07206_amd import _native as N
     from paper_1712_07206_amd.hsbuild import HSBuilder
     b = HSBuilder.from_case(case)
+    b.set_option(N.HSB_OPT_SPLIT_K, 0)
     tau = torch.as_tensor(case["tau"], device="cuda")
     T = torch.as_tensor(case["T"], device="cuda")
     gl = [torch.as_tensor(g, device="cuda") for g in case["g"]]

@@ -169,6 +169,8 @@ def test_gamma_in_batch():
     kf = np.concatenate([GAMMA[None, :], base["k_frac"][1:]])
     gs = [g0] + list(base["g"][1:])
     b = HSBuilder.from_case(dict(base, n_g=np.array([len(x) for x in gs])))
+    from paper_1712_07206_amd import _native as N
+    b.set_option(N.HSB_OPT_SPLIT_K, 0)  # single-k forwards in the one-pass form the batch equals bitwise
     tau = torch.as_tensor(base["tau"], device="cuda")
     T = torch.as_tensor(base["T"], device="cuda")
     gl = [torch.as_tensor(x, device="cuda") for x in gs]
