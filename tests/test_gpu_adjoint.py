@@ -63,38 +63,99 @@ def test_backward_deterministic():
 
 
 def test_backward_central_differences_full_size():
-    """Full-size differentiation workload (64 atoms, N_L = 121, N_G = 6000)."""
+    """Full-size differentiation workload (64 atoms, N_L = 121, N_G = 6000), against
+    central differences of the GPU forward: every one of the 64 x 3 tau components
+    (step 1e-6 bohr), three random Hermitian directions of T and, per type, 32 seeded
+    entries of T (28 off-diagonal pairs perturbed as Hermitian pairs, T_ij and T_ji
+    together, in the real and in the imaginary part; 4 diagonal entries in the real
+    part; step 1e-7, and 1e-4 for the entries).  Each set is checked norm-relative,
+    <= 1e-7 (the entries at step 1e-7: <= 1e-6, see below).  A difference of
+    the loss is taken as the loss of the difference of the two forwards' outputs: L is
+    Re sum_{i<=j} c_ij (W_ji H_ij + V_ji S_ij) over the written upper triangles (c = 2
+    off the diagonal, 1 on it, since W, V, H and S are Hermitian), which keeps the
+    rounding of L itself out of the quotient."""
     case = make_case(4)
     b, g, tau, T, Wm, Vm = _setup(case)
-    gT, gtau = b.backward(case["k_frac"], g, tau, T, Wm, Vm)
+    n, kf = case["n_g"], case["k_frac"]
+    gT, gtau = b.backward(kf, g, tau, T, Wm, Vm)
     gtau = gtau.cpu().numpy()
     gT = gT.cpu().numpy()
-    rng = np.random.default_rng(44)
+    c = torch.triu(torch.full((n, n), 2.0, dtype=torch.float64, device="cuda"))
+    c.diagonal().fill_(1.0)
+    A = c * Wm.transpose(0, 1)
+    B = c * Vm.transpose(0, 1)
+    del c
+    # the lower triangles of these outputs are never written and stay zero
+    Hp, Sp, Hm, Sm = (torch.zeros((n, n), dtype=torch.complex128, device="cuda") for _ in range(4))
+
+    def delta(tau_p, T_p, tau_m, T_m):
+        b.forward(kf, g, tau_p, T_p, Hp, Sp)
+        b.forward(kf, g, tau_m, T_m, Hm, Sm)
+        return float((torch.sum(A * (Hp - Hm)).real + torch.sum(B * (Sp - Sm)).real).item())
+
+    def check(name, fd, an, tol=1e-7):
+        fd, an = np.asarray(fd), np.asarray(an)
+        err = np.linalg.norm(fd - an) / np.linalg.norm(an)
+        big = np.abs(an) > 1e-3 * np.abs(an).max()
+        worst = np.max(np.abs(fd - an)[big] / np.abs(an)[big])
+        print("%s: %d derivatives, norm-relative error %.3e, worst component %.3e" % (name, len(an), err, worst),
+              flush=True)
+        assert err <= tol, name
+
     h = 1e-6
-    picks = [(int(a), int(c)) for a, c in zip(rng.integers(0, case["n_atoms"], 6), rng.integers(0, 3, 6))]
-    fd, an = [], []
-    for a, c in picks:
-        tp = tau.clone()
-        tp[a, c] += h
-        tm = tau.clone()
-        tm[a, c] -= h
-        fd.append((_loss(b, case, g, tp, T, Wm, Vm) - _loss(b, case, g, tm, T, Wm, Vm)) / (2 * h))
-        an.append(gtau[a, c])
-    fd, an = np.array(fd), np.array(an)
-    err = np.abs(fd - an).max() / np.abs(gtau).max()
-    print("tau FD max err (rel to max |grad|)", err, fd, an)
-    assert err <= 1e-7
-    # T: L is linear in T, so the central difference along a Hermitian direction is exact up to rounding
+    fd = []
+    for a in range(case["n_atoms"]):
+        for k in range(3):
+            tp, tm = tau.clone(), tau.clone()
+            tp[a, k] += h
+            tm[a, k] -= h
+            fd.append(delta(tp, T, tm, T) / (2 * h))
+    check("tau (all components)", fd, gtau.reshape(-1))
+
+    rng = np.random.default_rng(44)
+    ht = 1e-7
     m = T.shape[1]
-    for _ in range(2):
+    fd, an = [], []
+    for _ in range(3):
         D = rng.normal(size=(case["n_types"], m, m)) + 1j * rng.normal(size=(case["n_types"], m, m))
         D = D + np.conj(np.transpose(D, (0, 2, 1)))
         Dt = torch.as_tensor(D, device="cuda")
-        ht = 1e-7
-        fdT = (_loss(b, case, g, tau, T + ht * Dt, Wm, Vm) - _loss(b, case, g, tau, T - ht * Dt, Wm, Vm)) / (2 * ht)
-        pred = float(np.real(np.sum(np.conj(gT) * D)))
-        print("T FD", fdT, pred)
-        assert abs(fdT - pred) <= 1e-7 * abs(pred)
+        fd.append(delta(tau, T + ht * Dt, tau, T - ht * Dt) / (2 * ht))
+        an.append(float(np.real(np.sum(np.conj(gT) * D))))
+    check("T (Hermitian directions)", fd, an)
+
+    # Single entries.  L is linear in T, so a central difference has no truncation error at
+    # any step; at the configured 1e-7 step the FP64 rounding of the two forwards' H
+    # (about 1e-16 of |H| per entry) is a sizeable part of the change one entry makes,
+    # so these small derivatives are held to that floor (measured 2.1e-7 norm-relative),
+    # and the same entries at a 1e-4 step, where the rounding is 1e3 times smaller
+    # against the change, to 1e-7.
+    entries = []
+    for t in range(case["n_types"]):
+        pairs = set()
+        while len(pairs) < 28:
+            i, j = sorted(int(x) for x in rng.integers(0, m, 2))
+            if i != j:
+                pairs.add((i, j))
+        diag = [int(x) for x in rng.choice(m, 4, replace=False)]
+        entries += [(t, i, j, part) for (i, j) in sorted(pairs) for part in ("re", "im")]
+        entries += [(t, d, d, "re") for d in diag]
+    for step, tol in ((ht, 1e-6), (1e-4, 1e-7)):
+        fd, an = [], []
+        for t, i, j, part in entries:
+            D = torch.zeros_like(T)
+            if i == j:
+                D[t, i, i] = 1.0
+                pred = gT[t, i, i].real
+            elif part == "re":
+                D[t, i, j] = D[t, j, i] = 1.0
+                pred = gT[t, i, j].real + gT[t, j, i].real
+            else:
+                D[t, i, j], D[t, j, i] = 1j, -1j
+                pred = gT[t, i, j].imag - gT[t, j, i].imag
+            fd.append(delta(tau, T + step * D, tau, T - step * D) / (2 * step))
+            an.append(pred)
+        check("T (single entries, 32 per type, step %.0e)" % step, fd, an, tol)
 
 
 def test_backward_identities():
