@@ -419,7 +419,9 @@ def small_leg(args) -> dict:
         wsb = b.workspace_bytes(N.HSB_MODE_FORWARD, [n])
         ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
         for _ in range(3):
-            b.forward_raw(case["k_frac"], n, g, tau, T, H, S, ws, wsb)
+            code = b.forward_raw(case["k_frac"], n, g, tau, T, H, S, ws, wsb)
+            if code != N.HSB_OK:
+                raise N.HSBuildError(code, N.last_error(b._h))
         torch.cuda.synchronize()
         b.set_timing(True)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -514,29 +516,43 @@ def batch_leg(args) -> dict:
     e1.record()
     torch.cuda.synchronize()
     ms_graph = e0.elapsed_time(e1) / reps
-    # sequential: one forward per k on the same stream, outputs written in place
-    wsb = b.workspace_bytes(N.HSB_MODE_FORWARD, [max(ng)])
-    ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+    # sequential: one forward per k on the same stream, outputs written in place, with the
+    # library's default split of the stacked index (small bases) and with the one-pass form
     outs = [(H[int(off[k]): int(off[k]) + ng[k] ** 2].view(ng[k], ng[k]),
              S[int(off[k]): int(off[k]) + ng[k] ** 2].view(ng[k], ng[k])) for k in range(n_k)]
-    for k in range(n_k):
-        b.forward_raw(case["k_frac"][k], ng[k], gl[k], tau, T, outs[k][0], outs[k][1], ws, wsb)
-    torch.cuda.synchronize()
-    e0.record()
-    for _ in range(reps):
-        for k in range(n_k):
-            b.forward_raw(case["k_frac"][k], ng[k], gl[k], tau, T, outs[k][0], outs[k][1], ws, wsb)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_seq = e0.elapsed_time(e1) / reps
-    log("batch %d k-points: graph %.3f ms, sequential %.3f ms, speedup %.3f, %.2f TFLOP/s"
-        % (n_k, ms_graph, ms_seq, ms_seq / ms_graph, flops / (ms_graph * 1e-3) / 1e12))
-    del H, S, ws, outs
+    seq = {}
+    for mode, key in ((1, "split_k_auto"), (0, "one_pass")):
+        b.set_option(N.HSB_OPT_SPLIT_K, mode)
+        wsb = max(b.workspace_bytes(N.HSB_MODE_FORWARD, [n]) for n in ng)  # the split's partials vary with n
+        ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
+
+        def all_k():
+            for k in range(n_k):
+                code = b.forward_raw(case["k_frac"][k], ng[k], gl[k], tau, T, outs[k][0], outs[k][1], ws, wsb)
+                if code != N.HSB_OK:
+                    raise N.HSBuildError(code, N.last_error(b._h))
+
+        all_k()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            all_k()
+        e1.record()
+        torch.cuda.synchronize()
+        seq[key] = e0.elapsed_time(e1) / reps
+        del ws
+    ms_seq = seq["split_k_auto"]
+    log("batch %d k-points: graph %.3f ms, sequential %.3f ms (one-pass %.3f ms), speedup %.3f (%.3f), %.2f TFLOP/s"
+        % (n_k, ms_graph, ms_seq, seq["one_pass"], ms_seq / ms_graph, seq["one_pass"] / ms_graph,
+           flops / (ms_graph * 1e-3) / 1e12))
+    del H, S, outs
     b.close()
     torch.cuda.empty_cache()
     return {"workload": case["name"], "n_k": n_k, "n_g_min": min(ng), "n_g_max": max(ng),
             "ms_graph": round(ms_graph, 4), "ms_sequential": round(ms_seq, 4),
-            "speedup": round(ms_seq / ms_graph, 4), "fp64_equiv_tflops": round(flops / (ms_graph * 1e-3) / 1e12, 4),
+            "ms_sequential_one_pass": round(seq["one_pass"], 4),
+            "speedup": round(ms_seq / ms_graph, 4), "speedup_vs_one_pass": round(seq["one_pass"] / ms_graph, 4),
+            "fp64_equiv_tflops": round(flops / (ms_graph * 1e-3) / 1e12, 4),
             "autotuned": {"waves": tuned["waves"], "tile_group": tuned["tile_group"],
                           "candidates_ms": {k: round(v, 3) for k, v in tuned["candidates_ms"].items()}}}
 

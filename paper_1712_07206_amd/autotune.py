@@ -58,14 +58,20 @@ def tune(builder, k_frac, g, tau, T, precision: int = N.HSB_FP64, groups: Iterab
     n = int(g.shape[0])
     H = torch.empty((n, n), dtype=torch.complex128, device="cuda")
     S = torch.empty((n, n), dtype=torch.complex128, device="cuda")
-    wsb = builder.workspace_bytes(N.HSB_MODE_FORWARD, [n])
+    waves = list(waves)
+    wsb = 0
+    for wv in waves:  # the workspace depends on the wave count (the 8-wave form may split its stacked index)
+        builder.set_option(N.HSB_OPT_HS_WAVES, wv)
+        wsb = max(wsb, builder.workspace_bytes(N.HSB_MODE_FORWARD, [n]))
     ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
     times = {}
     for wv in waves:
         for gr in groups:
             builder.set_option(N.HSB_OPT_HS_WAVES, wv)
             builder.set_option(N.HSB_OPT_TILE_GROUP, gr)
-            builder.forward_raw(k_frac, n, g, tau, T, H, S, ws, wsb)  # warm
+            code = builder.forward_raw(k_frac, n, g, tau, T, H, S, ws, wsb)  # warm
+            if code != N.HSB_OK:
+                raise N.HSBuildError(code, N.last_error(builder._h))
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record()
             for _ in range(reps):
