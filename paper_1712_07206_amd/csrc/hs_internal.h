@@ -188,7 +188,8 @@ int crt_tiles(int n_res);
 // Column scales (powers of two) of W, lam W and Y: scale[0..3 n_res); part: 3 crt_norm_blocks(K) n_res doubles.
 hipError_t launch_crt_scales(const double2* W, const double2* Y, const double* lam, int K, int n_pad, int n_res,
                              const CrtConsts& cc, double* part, double* scale, hipStream_t s);
-// Residue planes of X (times lam if use_lam): 2 n_mod planes of [n_res / 64][QK][64] 16-byte units, QK = K64 / 16.
+// Residue planes of X (times lam if use_lam): per modulus [QK / 4][n_res / 64][2][4][64] 16-byte units
+// (chunk-major), QK = K64 / 16.
 hipError_t launch_crt_residues(const CrtConsts& cc, const double2* X, const double* lam, int use_lam, int K, int n_pad,
                                int n_res, int QK, const double* scale, void* out, hipStream_t s);
 // Residues of the upper triangle of conj(L)^T R per modulus: res [n_mod][n_res][n_res], 2 bytes per

@@ -21,9 +21,11 @@
 // small remainder.  The only approximation is the rounding of the scaled operands to
 // integers; at 11 moduli that keeps 40 bits of each column's 2-norm.
 //
-// Residue layout (16-byte units of 16 consecutive k, one byte each): unit
-// ((p * NB + b) * QK + q) * 64 + g holds plane p = 2 i + {0: x_r + j_i x_i, 1: x_r - j_i x_i}
-// of modulus i, column G = 64 b + g, rows k = 16 q .. 16 q + 15; NB = n_res / 64, with
+// Residue layout (16-byte units of 16 consecutive k, one byte each), chunk-major so that
+// the bytes one contraction tile copies for a 64-row chunk are two contiguous runs:
+// unit i * 2 NB QK * 64 + (((c * NB + b) * 2 + p) * 4 + qq) * 64 + g holds, for modulus i,
+// plane p (0: x_r + j_i x_i, 1: x_r - j_i x_i), column G = 64 b + g and rows
+// k = 64 c + 16 qq .. 64 c + 16 qq + 15; NB = n_res / 64, QK = 4 * (number of chunks), with
 // the columns padded to n_res (a multiple of 256) and the rows to a multiple of 64, the
 // pads zero.
 #include <cmath>
@@ -122,8 +124,8 @@ __global__ void __launch_bounds__(256) k_crt_residues(CrtConsts cc, const d2* __
     im[r] = rint(v.y * sc);
   }
   const int NB = n_res / 64;
-  const int64_t plane = (int64_t)NB * QK * 64;
-  u4* o = out + ((int64_t)b * QK + q) * 64 + g;
+  const int64_t modstride = (int64_t)2 * NB * QK * 64;
+  u4* o = out + ((((int64_t)(q >> 2) * NB + b) * 2) * 4 + (q & 3)) * 64 + g;
   for (int i = 0; i < cc.n_mod; ++i) {
     const double m = (double)cc.m[i], inv_m = 1.0 / m, jm = (double)cc.j[i];
     u4 u0 = u4{0u, 0u, 0u, 0u}, u1 = u4{0u, 0u, 0u, 0u};
@@ -137,8 +139,8 @@ __global__ void __launch_bounds__(256) k_crt_residues(CrtConsts cc, const d2* __
       u0[r >> 2] |= ((unsigned)(int)p0 & 0xffu) << (8 * (r & 3));
       u1[r >> 2] |= ((unsigned)(int)p1 & 0xffu) << (8 * (r & 3));
     }
-    o[(2 * i) * plane] = u0;
-    o[(2 * i + 1) * plane] = u1;
+    o[i * modstride] = u0;
+    o[i * modstride + 256] = u1;
   }
 }
 
@@ -200,9 +202,9 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
   tile_origin_256(w - mod * num_tiles, nbs, gr, row0, col0);
   if (col0 >= n) return;
   const int bL = row0 >> 6, bR = col0 >> 6;
-  const int64_t plane = (int64_t)NB * QK * 64;
-  const u4* Lm = L + 2 * mod * plane;
-  const u4* Rm = R + 2 * mod * plane;
+  const int64_t modstride = (int64_t)2 * NB * QK * 64, cstride = (int64_t)NB * 512;  // units
+  const u4* Lm = L + mod * modstride;
+  const u4* Rm = R + mod * modstride;
 
   const u4* src[NPW];
   int dst[NPW];
@@ -211,18 +213,18 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
     const int j = wave + WAVES * i;
     if (j < 32) {
       const int p = j >> 4, b = (j >> 2) & 3, qq = j & 3;
-      src[i] = Lm + p * plane + ((int64_t)(bL + b) * QK + qq) * 64;
+      src[i] = Lm + (((bL + b) * 2 + p) * 4 + qq) * 64;
       dst[i] = ((p * 4 + b) * 4 + qq) * 64;
     } else {
       const int jj = j - 32, p = jj >> 3, b = (jj >> 2) & 1, qq = jj & 3;
-      src[i] = Rm + p * plane + ((int64_t)(bR + b) * QK + qq) * 64;
+      src[i] = Rm + (((bR + b) * 2 + p) * 4 + qq) * 64;
       dst[i] = kCrtLeftUnits + ((p * 2 + b) * 4 + qq) * 64;
     }
   }
   auto issue = [&](int c, int buf) {
 #pragma unroll
     for (int i = 0; i < NPW; ++i)
-      __builtin_amdgcn_global_load_lds((const void*)(src[i] + (int64_t)c * 256 + lane),
+      __builtin_amdgcn_global_load_lds((const void*)(src[i] + c * cstride + lane),
                                        (lds_ptr)(&lds[buf][dst[i]]), 16, 0, 0);
   };
 
@@ -297,7 +299,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
           accP[rb][cb] = mfma_i8(a1[rb], b0[cb], accP[rb][cb]);  // (a_r - j a_i)(b_r + j b_i)
           accQ[rb][cb] = mfma_i8(a0[rb], b1[cb], accQ[rb][cb]);  // (a_r + j a_i)(b_r - j b_i)
           if (more && ci < NPW)
-            __builtin_amdgcn_global_load_lds((const void*)(src[ci] + (int64_t)(c + 2) * 256 + lane),
+            __builtin_amdgcn_global_load_lds((const void*)(src[ci] + (c + 2) * cstride + lane),
                                              (lds_ptr)(&lds[nbuf][dst[ci]]), 16, 0, 0);
           ++ci;
           __builtin_amdgcn_sched_barrier(0);
