@@ -631,9 +631,10 @@ def coefficient_leg(case, ms_coef: float) -> dict:
 
 def device_leg() -> dict:
     """CU count, and the sustained matrix-core rates of the two instructions the
-    contractions run on (FP64 16x16x4 and int8 32x32x32), measured by the
-    library's probe; each rate divided by the per-CU rate per clock gives the
-    clock the matrix cores hold under that load."""
+    contractions run on (FP64 16x16x4 and int8 32x32x32, the latter on constant
+    and on changing random operands), measured by the library's probe; each rate
+    divided by the per-CU rate per clock gives the clock the matrix cores hold
+    under that load."""
     import torch
 
     from paper_1712_07206_amd import _native as N
@@ -643,7 +644,8 @@ def device_leg() -> dict:
     out = {"name": props.name, "arch": getattr(props, "gcnArchName", ""), "cus": cus}
     # per CU per clock: 4 SIMDs x (2048 FP64 operations per 64 cycles | 65536 int8 operations per 32 cycles)
     for key, kind, iters, per_clk, peak in (("fp64", N.HSB_PROBE_FP64, 50000, 128.0, 78.6),
-                                            ("int8", N.HSB_PROBE_INT8, 100000, 8192.0, 5000.0)):
+                                            ("int8", N.HSB_PROBE_INT8, 100000, 8192.0, 5000.0),
+                                            ("int8_random", N.HSB_PROBE_INT8_RANDOM, 100000, 8192.0, 5000.0)):
         blocks = 8 * cus
         ops, buf = mfma_probe(kind, blocks, 160)
         torch.cuda.synchronize()
@@ -938,6 +940,8 @@ def main() -> int:
             if form["precision"] in ("int8", "crt"):
                 sm = form["slice_mfma"]
                 sm["probe_frac"] = round(sm["achieved"] / dev["int8_mfma_probe"]["achieved"], 4)
+                # against the rate the int8 matrix cores hold on random operands (power-bound)
+                sm["random_probe_frac"] = round(sm["achieved"] / dev["int8_random_mfma_probe"]["achieved"], 4)
     if not args.no_cpu_baseline:
         log("timing the oracle sample on the host (N_G=%d)" % args.cpu_ng)
         from paper_1712_07206_amd import HSB_SPLIT_BF16, HSB_SPLIT_CRT, HSB_SPLIT_FP16, HSB_SPLIT_INT8

@@ -311,13 +311,17 @@ int hsbuild_host_angular(int32_t lmax, const double kvec[3], double pre, void* o
  * independent chains of `iters` (a multiple of 16) MFMAs on register operands
  * (HSB_PROBE_FP64: v_mfma_f64_16x16x4f64, the instruction of the FP64
  * contraction; HSB_PROBE_INT8: v_mfma_i32_32x32x32_i8, the instruction of the
- * int8 split contraction).  out: device buffer of at least blocks * 256 * 8
- * bytes (FP64) or blocks * 256 * 4 bytes (INT8) that receives one value per
+ * int8 split contractions, on constant bytes; HSB_PROBE_INT8_RANDOM: the same
+ * instruction on hashed bytes in [-120, 120] that change every instruction,
+ * like the residue contraction's operands, on which the matrix cores draw more
+ * power and may hold a lower clock).  out: device buffer of at least
+ * blocks * 256 * 8 bytes (FP64) or blocks * 256 * 4 bytes (INT8, INT8_RANDOM)
+ * that receives one value per
  * thread; *ops (host) receives the arithmetic operations the launch executes
  * (2 per multiply-add).  Enqueued on `stream`; the caller times it.  Returns
  * HSB_ERR_ARG or HSB_ERR_WORKSPACE (checked before any device call), or
  * HSB_ERR_DEVICE if the launch fails. */
-enum { HSB_PROBE_FP64 = 0, HSB_PROBE_INT8 = 1 };
+enum { HSB_PROBE_FP64 = 0, HSB_PROBE_INT8 = 1, HSB_PROBE_INT8_RANDOM = 2 };
 int hsbuild_mfma_probe(int32_t kind, int32_t blocks, int32_t iters, void* out, size_t out_bytes, void* stream,
                        double* ops);
 

@@ -28,6 +28,7 @@ HSB_SPLIT_INT8 = 3
 HSB_SPLIT_CRT = 4
 HSB_PROBE_FP64 = 0
 HSB_PROBE_INT8 = 1
+HSB_PROBE_INT8_RANDOM = 2
 
 HSB_MODE_FORWARD = 0
 HSB_MODE_BACKWARD = 1

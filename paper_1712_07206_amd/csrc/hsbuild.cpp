@@ -1349,7 +1349,8 @@ int hsbuild_host_angular(int32_t lmax, const double kvec[3], double pre, void* o
 
 int hsbuild_mfma_probe(int32_t kind, int32_t blocks, int32_t iters, void* out, size_t out_bytes, void* stream,
                        double* ops) {
-  if (kind != HSB_PROBE_FP64 && kind != HSB_PROBE_INT8) return fail(nullptr, HSB_ERR_ARG, "unknown probe kind %d", kind);
+  if (kind != HSB_PROBE_FP64 && kind != HSB_PROBE_INT8 && kind != HSB_PROBE_INT8_RANDOM)
+    return fail(nullptr, HSB_ERR_ARG, "unknown probe kind %d", kind);
   if (blocks < 1 || blocks > (1 << 20) || iters < 1 || iters > (1 << 26) || iters % kProbeUnroll)
     return fail(nullptr, HSB_ERR_ARG, "blocks=%d or iters=%d out of range (iters: a multiple of %d)", blocks, iters,
                 kProbeUnroll);

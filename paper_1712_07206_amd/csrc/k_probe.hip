@@ -2,8 +2,8 @@
 // register operands, with no memory traffic until one store at the end.  The
 // sustained rate it measures is what the contraction kernels can reach on the
 // same device (FP64 16x16x4 for the complex FP64 path, int8 32x32x32 for the
-// int8 split path), and, divided by the per-CU rate per clock, the clock the
-// matrix cores hold under that load.
+// int8 split paths, on constant or on changing random operands), and, divided by
+// the per-CU rate per clock, the clock the matrix cores hold under that load.
 #include "hs_internal.h"
 
 namespace hsb {
@@ -59,6 +59,64 @@ __global__ void __launch_bounds__(256) k_probe_i8(int iters, unsigned* __restric
   out[(int64_t)blockIdx.x * 256 + threadIdx.x] = s;
 }
 
+// 32-bit integer hash (xor-shift-multiply rounds of Wellons' "lowbias32"), for operand bytes.
+__device__ __forceinline__ unsigned mix32(unsigned x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+
+// Four signed bytes in [-120, 120] from a hash: the spread of the residue contraction's
+// operands (residues modulo m < 256, centred).
+__device__ __forceinline__ int rand_bytes(unsigned key) {
+  const unsigned h = mix32(key);
+  unsigned r = 0u;
+#pragma unroll
+  for (int b = 0; b < 4; ++b) {
+    const int v = (int)(((h >> (8 * b)) & 0xffu) % 241u) - 120;
+    r |= ((unsigned)v & 0xffu) << (8 * b);
+  }
+  return (int)r;
+}
+
+// int8 MFMAs on operands that change every instruction: four register sets of hashed bytes,
+// taken in turn, as the residue contraction feeds the matrix cores.  The matrix cores draw
+// more power on such operands than on the constant bytes of k_probe_i8 and may hold a lower
+// clock.  The int32 sums wrap: only the rate is of interest.
+__global__ void __launch_bounds__(256) k_probe_i8_random(int iters, unsigned* __restrict__ out) {
+  constexpr int kSets = 4;
+  const unsigned id = blockIdx.x * 256u + threadIdx.x;
+  i4v a[kSets], b[kSets];
+#pragma unroll
+  for (int t = 0; t < kSets; ++t)
+#pragma unroll
+    for (int w = 0; w < 4; ++w) {
+      a[t][w] = rand_bytes(id * 64u + (unsigned)(t * 8 + w));
+      b[t][w] = rand_bytes(id * 64u + (unsigned)(t * 8 + 4 + w));
+    }
+  i16v c[kChains];
+#pragma unroll
+  for (int j = 0; j < kChains; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) c[j][r] = 0;
+  for (int i = 0; i < iters; i += kUnroll) {
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+      for (int j = 0; j < kChains; ++j)
+        c[j] = __builtin_amdgcn_mfma_i32_32x32x32_i8(a[(u + j) % kSets], b[(u + 2 * j + 1) % kSets], c[j], 0, 0, 0);
+  }
+  unsigned s = 0u;
+#pragma unroll
+  for (int j = 0; j < kChains; ++j)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) s += (unsigned)c[j][r];
+  out[(int64_t)blockIdx.x * 256 + threadIdx.x] = s;
+}
+
 }  // namespace
 
 double probe_ops_per_mfma(int kind) { return kind == 0 ? 2.0 * 16 * 16 * 4 : 2.0 * 32 * 32 * 32; }
@@ -66,8 +124,10 @@ double probe_ops_per_mfma(int kind) { return kind == 0 ? 2.0 * 16 * 16 * 4 : 2.0
 hipError_t launch_mfma_probe(int kind, int blocks, int iters, void* out, hipStream_t s) {
   if (kind == 0)
     hipLaunchKernelGGL(k_probe_f64, dim3(blocks), dim3(256), 0, s, iters, (double*)out);
-  else
+  else if (kind == 1)
     hipLaunchKernelGGL(k_probe_i8, dim3(blocks), dim3(256), 0, s, iters, (unsigned*)out);
+  else
+    hipLaunchKernelGGL(k_probe_i8_random, dim3(blocks), dim3(256), 0, s, iters, (unsigned*)out);
   return hipGetLastError();
 }
 

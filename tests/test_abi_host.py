@@ -248,7 +248,9 @@ def test_header_is_plain_c(tmp_path):
 
 
 @pytest.mark.parametrize("kind,blocks,iters,nbytes,code", [
-    (2, 8, 16, 1 << 20, N.HSB_ERR_ARG),                    # unknown kind
+    (3, 8, 16, 1 << 20, N.HSB_ERR_ARG),                    # unknown kind
+    (-1, 8, 16, 1 << 20, N.HSB_ERR_ARG),                   # unknown kind
+    (N.HSB_PROBE_INT8_RANDOM, 8, 16, 8 * 256 * 4 - 1, N.HSB_ERR_WORKSPACE),
     (N.HSB_PROBE_FP64, 0, 16, 1 << 20, N.HSB_ERR_ARG),     # no workgroups
     (N.HSB_PROBE_INT8, 8, 0, 1 << 20, N.HSB_ERR_ARG),      # no iterations
     (N.HSB_PROBE_INT8, 8, 24, 1 << 20, N.HSB_ERR_ARG),     # not a multiple of 16

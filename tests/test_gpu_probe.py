@@ -14,11 +14,12 @@ def gpu():
     yield
 
 
-@pytest.mark.parametrize("kind_name,iters,lo", [("fp64", 4000, 20.0), ("int8", 8000, 1000.0)])
+@pytest.mark.parametrize("kind_name,iters,lo", [("fp64", 4000, 20.0), ("int8", 8000, 1000.0),
+                                               ("int8_random", 8000, 1000.0)])
 def test_probe_rate(kind_name, iters, lo):
     from paper_1712_07206_amd import _native as N
     from paper_1712_07206_amd.hsbuild import mfma_probe
-    kind = N.HSB_PROBE_FP64 if kind_name == "fp64" else N.HSB_PROBE_INT8
+    kind = {"fp64": N.HSB_PROBE_FP64, "int8": N.HSB_PROBE_INT8, "int8_random": N.HSB_PROBE_INT8_RANDOM}[kind_name]
     cus = torch.cuda.get_device_properties(0).multi_processor_count
     blocks = 8 * cus
     ops, buf = mfma_probe(kind, blocks, 16)
@@ -34,7 +35,9 @@ def test_probe_rate(kind_name, iters, lo):
     vals = buf.view(torch.float64 if kind_name == "fp64" else torch.int32)
     if kind_name == "fp64":
         assert bool(torch.isfinite(vals).all()) and bool((vals > 0).all())
-    else:
+    elif kind_name == "int8":
         assert bool((vals >= 0).all())
+    else:  # wrapping sums of random products: not all equal
+        assert int(torch.unique(vals).numel()) > 1
     print("%s probe: %.1f T ops/s" % (kind_name, rate))
     assert rate > lo
