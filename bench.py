@@ -151,9 +151,9 @@ def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
         eh = (torch.linalg.norm(hermitian_full(H) - H64) / torch.linalg.norm(H64)).item()
         es = (torch.linalg.norm(hermitian_full(S) - S64) / torch.linalg.norm(S64)).item()
         if precision == HSB_SPLIT_CRT:
-            # residue-MFMA work of the two contraction launches (S and H): every 256 x 128 tile of the
-            # upper triangle (two per 256 x 256 super-tile), the stacked rows padded to 64, per modulus
-            # two int8 products (P and Q) x 2 operations
+            # residue-MFMA work of the two contraction launches (S and H): every 256 x 256 block of the
+            # upper triangle, the stacked rows padded to 64, per modulus two int8 products (P and Q,
+            # one workgroup each) x 2 operations
             nbs = -(-n // 256)
             k64 = -(-2 * case["n_atoms"] * case["n_l"] // 64) * 64
             mfma_ops = 2.0 * nbs * (nbs + 1) * 256 * 128 * k64 * slices * 2 * 2
@@ -166,12 +166,14 @@ def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
             pairs = slices * (slices + 1) // 2
             mfma_ops = 2.0 * nbr * (nbr + 1) * 128 * 64 * k_pad2 * pairs * 8
         rate = mfma_ops / (stage_ms[2] * 1e-3) / 1e12
+        options = {"waves": bs.get_option(N.HSB_OPT_HS_WAVES), "tile_group": bs.get_option(N.HSB_OPT_TILE_GROUP)}
         log("split %s x%d: %.3f ms/step (contraction stage %.3f ms); FP64 path next to it %.3f ms: speedup %.3f; "
             "rel err vs FP64 H %.2e S %.2e" % (name, slices, ms, stage_ms[2], ms_fp64_adj, ms_fp64_adj / ms, eh, es))
         del wss
         bs.close()
         torch.cuda.empty_cache()
-        return {"precision": name, "slices": slices, "slice_bits": bits, "kernel": kernel, "ms_per_step": round(ms, 4),
+        return {"precision": name, "slices": slices, "slice_bits": bits, "kernel": kernel, "options": options,
+                "ms_per_step": round(ms, 4),
                 "fp64_equiv_tflops": round(flops / (ms * 1e-3) / 1e12, 4), "speedup": round(ms_fp64_adj / ms, 4),
                 "fp64_ms_adjacent": round(ms_fp64_adj, 4), "speedup_vs_headline_fp64": round(ms_fp64 / ms, 4),
                 "stages_ms": {"coefficients": round(stage_ms[0], 4),

@@ -281,7 +281,12 @@ int hsbuild_stage_times(hsbuild_t h, double* ms_avg, int32_t* n_calls);
  * 8 (32 x 32 per wave, two per SIMD; three real products per complex one, the
  * 3M form; 128 x 128 tiles of 32 x 64 for hsbuild_forward_real, which is
  * real); default 8.  The two complex forms agree to FP64 rounding, not
- * bitwise.
+ * bitwise.  On a handle with HSB_SPLIT_CRT the option picks the layout of the
+ * residue contraction instead (256 x 256 blocks): 4 (waves of 128 x 128, one
+ * per SIMD; the default there) or 8 (64 x 128, two per SIMD); the 4-wave
+ * layout keeps its int32 sums unreduced and so runs up to 2048 stages of 64
+ * stacked rows (the real form takes two stages per 64 rows), beyond which the
+ * 8-wave layout runs.  Both give bitwise the same H and S.
  * HSB_OPT_SPLIT_K: 1 (default) lets the 8-wave FP64 forward cut the stacked
  * index into segments when the upper triangle has fewer than 4 tiles per
  * compute unit (2..8 segments of at least 256 rows, chosen by a model of the

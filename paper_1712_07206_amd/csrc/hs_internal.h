@@ -192,12 +192,14 @@ hipError_t launch_crt_scales(const double2* W, const double2* Y, const double* l
 // (chunk-major), QK = K64 / 16.
 hipError_t launch_crt_residues(const CrtConsts& cc, const double2* X, const double* lam, int use_lam, int K, int n_pad,
                                int n_res, int QK, const double* scale, void* out, hipStream_t s);
-// Residues of the upper triangle of conj(L)^T R per modulus: res [n_mod][n_res][n_res], 2 bytes per
-// entry (1 if real: Re only).
-// waves: 8 (waves of 64 x 64) or 4 (128 x 64).
+// Residues of the upper triangle of conj(L)^T R per modulus: res [n_mod][2][n_res][n_res] signed
+// bytes, P then Q (the images of the product under the two factors of Z[i]/m); the real form
+// [n_mod][n_res][n_res], its one product.  256 x 256 blocks; waves: 8 (waves of 64 x 128) or
+// 4 (128 x 128).
 hipError_t launch_hs_crt(const CrtConsts& cc, bool real, const void* L, const void* R, int QK, int n, int n_res,
                          int gr, int waves, void* res, hipStream_t s);
-// C[row][col] (row <= col < n, ld n) from the residues, scaled by 1 / (scL[row] scR[col]); complex or real.
+// C[row][col] (row <= col < n, ld n) from the residues (Re, Im from P, Q per modulus), scaled by
+// 1 / (scL[row] scR[col]); complex or real.
 hipError_t launch_crt_combine(const CrtConsts& cc, bool real, const void* res, int n_res, const double* scL,
                               const double* scR, int n, void* C, hipStream_t s);
 

@@ -634,6 +634,7 @@ int hsbuild_create(const hsb_config* cfg, hsbuild_t* out) {
   h->max_ng = cfg->max_ng;
   h->precision = cfg->precision;
   if (cfg->precision != HSB_FP64) h->tile_group = 4;  // measured best for the split contraction
+  if (cfg->precision == HSB_SPLIT_CRT) h->hs_waves = 4;  // residue contraction: waves of 128 x 128, measured best
   h->n_slices = cfg->n_slices;
   h->crt = crt;
   std::memcpy(h->lattice, cfg->lattice, sizeof h->lattice);

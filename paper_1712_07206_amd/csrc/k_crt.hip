@@ -157,16 +157,18 @@ __device__ __forceinline__ int smod_i(int v, int m, double inv_m, int h) {
   return r;
 }
 
-// Contraction tile: 256 rows (G') x 128 columns (G) per workgroup, rows of the stacked index
-// in chunks of 64 copied straight into LDS (global_load_lds_dwordx4) through a ring of three
-// stages (48 KB each): a chunk is copied two chunks ahead of its use.  WAVES = 8: waves of
-// 64 x 64 (2 x 2 blocks of 32 x 32, two int32 sums P and Q each, two waves per SIMD);
-// WAVES = 4: waves of 128 x 64 (4 x 2 blocks, one wave per SIMD), which read 3/4 of the LDS
-// bytes per MFMA.
+// Contraction tile: one product (P, Q, or the real product) over a 256 x 256 block of
+// (G', G) per workgroup, so each side needs one residue plane: a 64-row chunk of the stacked
+// index is 16 KB of left and 16 KB of right residues, copied straight into LDS
+// (global_load_lds_dwordx4) through a ring of three 32 KB stages, two chunks ahead of its use.
+// (Computing P and Q together on a 256 x 128 tile takes the same registers and MFMAs but copies
+// 48 KB per chunk: both planes of both sides.)  WAVES = 8: waves of 64 x 128 (2 x 4 blocks of
+// 32 x 32, two waves per SIMD); WAVES = 4: waves of 128 x 128 (4 x 4 blocks, one wave per SIMD,
+// 2/3 of the LDS reads per MFMA).
 constexpr int kCrtStages = 3;
-constexpr int kCrtLeftUnits = 2 * 4 * 4 * 64;                     // 2 planes x 4 blocks x 4 row groups x 64
-constexpr int kCrtStageUnits = kCrtLeftUnits + 2 * 2 * 4 * 64;    // + 2 planes x 2 blocks x 4 x 64
-constexpr int kCrtCopies = kCrtStageUnits / 64;                   // 1 KB copies per chunk (48)
+constexpr int kCrtSideUnits = 4 * 4 * 64;                 // 4 blocks of 64 columns x 4 row groups x 64
+constexpr int kCrtStageUnits = 2 * kCrtSideUnits;         // left, then right (32 KB)
+constexpr int kCrtCopies = kCrtStageUnits / 64;           // 1 KB copies per chunk (32)
 constexpr int kCrtWindow = 1024;  // chunks (65536 rows) between reductions of the int32 sums: 2^16 * 120^2 < 2^30
 // Chunks whose sums stay exact with no reduction at all: 2^17 rows * 120^2 < 2^31.  Reducing
 // 256 accumulators held in AGPRs costs the 4-wave form its registers, so it runs only up to
@@ -176,19 +178,26 @@ constexpr int kCrtNoReduce = 2048;
 // s_waitcnt immediates (gfx9 encoding): vector-memory count N, the other counters not waited on.
 constexpr int vmcnt_only(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) | (15 << 8); }
 
-// Workgroup w: modulus w / num_tiles, tile w % num_tiles (XCD-contiguous numbering, so the
-// tiles an XCD runs together belong to one modulus and a compact patch of the triangle).
-// res: residues of the product per modulus, [n_mod][n_res][n_res] of 16-bit (Re, Im) pairs of
-// signed bytes, Re in the low byte (REAL: Re bytes only), written for row <= col < n.
+// Workgroup w: (modulus, product) = w / num_tiles, product fastest (P then Q; the real form has
+// one), 256 x 256 block w % num_tiles of the upper triangle (XCD-contiguous numbering, so the
+// blocks an XCD runs together belong to one modulus and product and to a compact patch of the
+// triangle).  P multiplies the left plane 1 (x_r - j x_i) by the right plane 0 (y_r + j y_i), Q
+// the left plane 0 by the right plane 1.  The real form wants Re = (P + Q) / 2 only: it adds both
+// products into one sum, running through 2 x (chunks) stages, each chunk once with the planes
+// of P and once with those of Q.
+// res: residues in [-(m-1)/2, (m-1)/2] as signed bytes, [n_mod][nprod][n_res][n_res] (the real
+// form: of Re), written for row <= col < n.
 template <int WAVES, bool REAL>
 __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__ L, const u4* __restrict__ R,
                                                           CrtConsts cc, int QK, int n, int NB, int nbs,
-                                                          int num_tiles, int num_wg, int gr, void* __restrict__ res,
+                                                          int num_tiles, int num_wg, int gr, int8_t* __restrict__ res,
                                                           int64_t ld) {
-  constexpr int WRN = WAVES / 2;    // wave rows
-  constexpr int RB = 8 / WRN;       // 32-row blocks per wave (2 or 4)
-  constexpr int NPW = kCrtCopies / WAVES;  // copies per wave and chunk
-  static_assert(NPW <= 2 * RB * 2, "one copy per MFMA pair of the chunk");
+  constexpr int NPROD = REAL ? 1 : 2;
+  constexpr int WRN = WAVES / 2;           // wave rows
+  constexpr int RB = 8 / WRN;              // 32-row blocks per wave (2 or 4); 4 column blocks
+  constexpr int NPW = kCrtCopies / WAVES;  // copies per wave and chunk (4 or 8)
+  constexpr int NMF = 2 * RB * 4;          // MFMAs per wave and chunk (16 or 32)
+  static_assert(NPW <= NMF / 2, "one copy per MFMA pair of the chunk");
   __shared__ u4 lds[kCrtStages][kCrtStageUnits];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -197,47 +206,48 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
   int start, len;
   xcd_range(x, num_wg, start, len);
   const int w = start + blockIdx.x / kXcds;
-  const int mod = w / num_tiles;
-  int row0, col0;
-  tile_origin_256(w - mod * num_tiles, nbs, gr, row0, col0);
+  const int mp = w / num_tiles;
+  const int mod = mp / NPROD, prod = mp - mod * NPROD;
+  int bi, bj;
+  if (gr > 0) grouped_decode(w - mp * num_tiles, nbs, gr, bi, bj);
+  else tri_decode(w - mp * num_tiles, nbs, bi, bj);
+  const int row0 = bi * 256, col0 = bj * 256;
   if (col0 >= n) return;
-  const int bL = row0 >> 6, bR = col0 >> 6;
+  const int planeL = 1 - prod, planeR = prod;  // the real form starts with P's planes
   const int64_t modstride = (int64_t)2 * NB * QK * 64, cstride = (int64_t)NB * 512;  // units
   const u4* Lm = L + mod * modstride;
   const u4* Rm = R + mod * modstride;
 
   const u4* src[NPW];
-  int dst[NPW];
+  int dst[NPW], dlt[NPW];
 #pragma unroll
   for (int i = 0; i < NPW; ++i) {
-    const int j = wave + WAVES * i;
-    if (j < 32) {
-      const int p = j >> 4, b = (j >> 2) & 3, qq = j & 3;
-      src[i] = Lm + (((bL + b) * 2 + p) * 4 + qq) * 64;
-      dst[i] = ((p * 4 + b) * 4 + qq) * 64;
-    } else {
-      const int jj = j - 32, p = jj >> 3, b = (jj >> 2) & 1, qq = jj & 3;
-      src[i] = Rm + (((bR + b) * 2 + p) * 4 + qq) * 64;
-      dst[i] = kCrtLeftUnits + ((p * 2 + b) * 4 + qq) * 64;
-    }
+    const int j = wave + WAVES * i;  // copy j: side j / 16, block (j / 4) % 4, row group j % 4
+    const int side = j >> 4, b = (j >> 2) & 3, qq = j & 3;
+    const u4* base = side ? Rm : Lm;
+    const int b0 = side ? (col0 >> 6) : (row0 >> 6);
+    src[i] = base + (((b0 + b) * 2 + (side ? planeR : planeL)) * 4 + qq) * 64;
+    dst[i] = side * kCrtSideUnits + (b * 4 + qq) * 64;
+    dlt[i] = side ? 256 : -256;  // real form, Q's stage: the other plane of each side
   }
-  auto issue = [&](int c, int buf) {
+  // stage v: chunk v (complex), or chunk v / 2 with P's (v even) or Q's (v odd) planes (real)
+  auto at = [&](int i, int v) -> const u4* {
+    if constexpr (REAL) return src[i] + (v >> 1) * cstride + (v & 1) * dlt[i];
+    else return src[i] + v * cstride;
+  };
+  auto issue = [&](int v, int buf) {
 #pragma unroll
     for (int i = 0; i < NPW; ++i)
-      __builtin_amdgcn_global_load_lds((const void*)(src[i] + c * cstride + lane),
-                                       (lds_ptr)(&lds[buf][dst[i]]), 16, 0, 0);
+      __builtin_amdgcn_global_load_lds((const void*)(at(i, v) + lane), (lds_ptr)(&lds[buf][dst[i]]), 16, 0, 0);
   };
 
-  i16v accP[RB][2], accQ[RB][2];
+  i16v acc[RB][4];
 #pragma unroll
   for (int a = 0; a < RB; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        accP[a][b][r] = 0;
-        accQ[a][b][r] = 0;
-      }
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0;
 
   const int m = cc.m[mod], hm = (m - 1) / 2;
   const double inv_m = 1.0 / (double)m;
@@ -245,21 +255,19 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
 #pragma unroll
     for (int a = 0; a < RB; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          accP[a][b][r] = smod_i(accP[a][b][r], m, inv_m, hm);
-          accQ[a][b][r] = smod_i(accQ[a][b][r], m, inv_m, hm);
-        }
+        for (int r = 0; r < 16; ++r) acc[a][b][r] = smod_i(acc[a][b][r], m, inv_m, hm);
   };
 
   const int qh = lane >> 5, g32 = lane & 31;
-  // A operand of block rb (rows wr * 32 RB + 32 rb of the tile) for k step s, plane p: unit
-  // la(rb) + p * 1024 + s * 128 with la(rb) = ((wr RB + rb) / 2 * 4 + qh) * 64 + (rb & 1) * 32 + g32;
-  // B operand: ra + p * 512 + s * 128 + cb * 32.
-  const int la = ((wr * RB) / 2 * 4 + qh) * 64 + g32;
-  const int ra = kCrtLeftUnits + (wc * 4 + qh) * 64 + g32;
-  const int nchunks = QK >> 2;
+  // A operand of row block rb (rows 32 (RB wr + rb) of the block) at step s (rows 32 s .. 32 s + 31
+  // of the chunk): left unit ((RB wr + rb) / 2 * 4 + 2 s + qh) * 64 + ((RB wr + rb) & 1) * 32 + g32.
+  // B operand of column block cb (columns 32 (4 wc + cb)): right unit
+  // kCrtSideUnits + ((4 wc + cb) / 2 * 4 + 2 s + qh) * 64 + (cb & 1) * 32 + g32.
+  const int la = qh * 64 + g32;
+  const int ra = kCrtSideUnits + (2 * wc * 4 + qh) * 64 + g32;
+  const int nchunks = (QK >> 2) * (REAL ? 2 : 1);  // stages
   if (nchunks > 0) issue(0, 0);
   if (nchunks > 1) issue(1, 1);
   for (int c = 0; c < nchunks; ++c) {
@@ -272,77 +280,67 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
     // The copies of chunk c + 2 go out one after each pair of MFMAs (scheduling fences keep
-    // them there): issued together after the barrier they held up the MFMAs behind them
-    // (8 waves: 69 ms against 52 ms per matrix at the bench workload).
+    // them there): issued together after the barrier they hold up the MFMAs behind them.
     const bool more = c + 2 < nchunks;
     const int nbuf = (c + 2) % kCrtStages;
     const u4* B = lds[c % kCrtStages];
     int ci = 0;
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
-      u4 a0[RB], a1[RB], b0[2], b1[2];
+      u4 a[RB], b[4];
 #pragma unroll
       for (int t = 0; t < RB; ++t) {
-        const int off = la + (t >> 1) * 256 + (t & 1) * 32 + s * 128;
-        a0[t] = B[off];
-        a1[t] = B[off + 1024];
+        const int rbb = RB * wr + t;
+        a[t] = B[la + ((rbb >> 1) * 4 + 2 * s) * 64 + (rbb & 1) * 32];
       }
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        b0[t] = B[ra + s * 128 + t * 32];
-        b1[t] = B[ra + 512 + s * 128 + t * 32];
-      }
+      for (int t = 0; t < 4; ++t) b[t] = B[ra + ((t >> 1) * 4 + 2 * s) * 64 + (t & 1) * 32];
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-        for (int cb = 0; cb < 2; ++cb) {
-          accP[rb][cb] = mfma_i8(a1[rb], b0[cb], accP[rb][cb]);  // (a_r - j a_i)(b_r + j b_i)
-          accQ[rb][cb] = mfma_i8(a0[rb], b1[cb], accQ[rb][cb]);  // (a_r + j a_i)(b_r - j b_i)
-          if (more && ci < NPW)
-            __builtin_amdgcn_global_load_lds((const void*)(src[ci] + (c + 2) * cstride + lane),
-                                             (lds_ptr)(&lds[nbuf][dst[ci]]), 16, 0, 0);
-          ++ci;
-          __builtin_amdgcn_sched_barrier(0);
+        for (int cb = 0; cb < 4; ++cb) {
+          acc[rb][cb] = mfma_i8(a[rb], b[cb], acc[rb][cb]);
+          if ((cb & 1) && more && ci < NPW)
+            __builtin_amdgcn_global_load_lds((const void*)(at(ci, c + 2) + lane), (lds_ptr)(&lds[nbuf][dst[ci]]), 16,
+                                             0, 0);
+          if (cb & 1) {
+            ++ci;
+            __builtin_amdgcn_sched_barrier(0);
+          }
         }
     }
-    // the 4-wave form runs only where no reduction is needed (at most kCrtNoReduce chunks)
+    // the 4-wave form runs only where no reduction is needed (at most kCrtNoReduce stages)
     if constexpr (WAVES == 8)
       if ((c + 1) % kCrtWindow == 0) reduce();
   }
 
-  // residues of Re and Im; output element r of a 32 x 32 block: row 8 (r / 4) + 4 qh + r % 4, column g32
-  const int inv2 = cc.inv2[mod], inv2j = cc.inv2j[mod];
-  int rbase = row0 + wr * 32 * RB + 4 * qh, cbase = col0 + wc * 64 + g32;
+  // residues of the product; output element r of a 32 x 32 block: row 8 (r / 4) + 4 qh + r % 4, column g32
+  int rbase = row0 + wr * 32 * RB + 4 * qh, cbase = col0 + wc * 128 + g32;
   asm volatile("" : "+v"(rbase), "+v"(cbase));
-  const int64_t obase = (int64_t)mod * ld * ld;
+  int8_t* out = res + (int64_t)(mod * NPROD + prod) * ld * ld;
 #pragma unroll
   for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 2; ++cb)
+    for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int row = rbase + rb * 32 + 8 * (r >> 2) + (r & 3);
         const int col = cbase + cb * 32;
         if (row < n && col < n && col >= row) {
-          const int p = smod_i(accP[rb][cb][r], m, inv_m, hm);
-          const int q = smod_i(accQ[rb][cb][r], m, inv_m, hm);
-          const int re = smod_i((p + q) * inv2, m, inv_m, hm);
-          if constexpr (REAL) {
-            ((int8_t*)res)[obase + (int64_t)row * ld + col] = (int8_t)re;
-          } else {
-            const int im = smod_i((p - q) * inv2j, m, inv_m, hm);
-            ((uint16_t*)res)[obase + (int64_t)row * ld + col] = (uint16_t)((re & 0xff) | ((im & 0xff) << 8));
-          }
+          int v = smod_i(acc[rb][cb][r], m, inv_m, hm);
+          if constexpr (REAL) v = smod_i(v * cc.inv2[mod], m, inv_m, hm);  // (P + Q) / 2
+          out[(int64_t)row * ld + col] = (int8_t)v;
         }
       }
 }
 
-// Recovery of each upper-triangle entry from its residues: value = M * frac(sum_i r_i y_i / m_i),
-// times 2^-(f_row + f_col).  sum r_i h_i is exact (h_i on a 2^-42 grid, |r_i| < 2^7, n <= 13
-// terms), so the rounding to the nearest integer is exact and the fraction keeps FP64
-// precision.  One thread per (row, col).
+// Recovery of each upper-triangle entry from its residues: per modulus Re = (P + Q) / 2 and
+// Im = (P - Q) / (2 j) (mod m) (the real form: its one product), then
+// value = M * frac(sum_i r_i y_i / m_i), times 2^-(f_row + f_col).  sum r_i h_i is exact (h_i on a
+// 2^-42 grid, |r_i| < 2^7, n <= 13 terms), so the rounding to the nearest integer is exact and
+// the fraction keeps FP64 precision.  One thread per (row, col).
 template <bool REAL>
-__global__ void __launch_bounds__(256) k_crt_combine(CrtConsts cc, const void* __restrict__ res, int64_t ld,
+__global__ void __launch_bounds__(256) k_crt_combine(CrtConsts cc, const int8_t* __restrict__ res, int64_t ld,
                                                      const double* __restrict__ scL, const double* __restrict__ scR,
                                                      int n, void* __restrict__ Cv) {
   const int row = blockIdx.y;
@@ -352,12 +350,15 @@ __global__ void __launch_bounds__(256) k_crt_combine(CrtConsts cc, const void* _
   double hr = 0.0, lr = 0.0, hi = 0.0, li = 0.0;
   for (int i = 0; i < cc.n_mod; ++i) {
     if constexpr (REAL) {
-      const double r = (double)((const int8_t*)res)[i * mstride + e];
+      const double r = (double)res[i * mstride + e];
       hr += r * cc.h[i];
       lr += r * cc.l[i];
     } else {
-      const unsigned v = ((const uint16_t*)res)[i * mstride + e];
-      const double r = (double)(int8_t)(v & 0xffu), t = (double)(int8_t)(v >> 8);
+      const int p = res[(2 * i) * mstride + e], q = res[(2 * i + 1) * mstride + e];
+      const int m = cc.m[i], hm = (m - 1) / 2;
+      const double inv_m = 1.0 / (double)m;
+      const double r = (double)smod_i((p + q) * cc.inv2[i], m, inv_m, hm);
+      const double t = (double)smod_i((p - q) * cc.inv2j[i], m, inv_m, hm);
       hr += r * cc.h[i];
       lr += r * cc.l[i];
       hi += t * cc.h[i];
@@ -433,7 +434,7 @@ int crt_norm_blocks(int K) { return (K + kNormRows - 1) / kNormRows; }
 
 int crt_tiles(int n_res) {
   const int nbs = n_res / 256;
-  return nbs * (nbs + 1);
+  return nbs * (nbs + 1) / 2;
 }
 
 hipError_t launch_crt_scales(const double2* W, const double2* Y, const double* lam, int K, int n_pad, int n_res,
@@ -460,25 +461,26 @@ hipError_t launch_hs_crt(const CrtConsts& cc, bool real, const void* L, const vo
                          int gr, int waves, void* res, hipStream_t s) {
   const int nbs = n_res / 256;
   const int num_tiles = crt_tiles(n_res);
-  const int num_wg = num_tiles * cc.n_mod;
+  const int num_wg = num_tiles * cc.n_mod * (real ? 1 : 2);
   const int NB = n_res / 64;
   const dim3 grid(num_wg);
   const u4 *l = (const u4*)L, *r = (const u4*)R;
+  int8_t* o = (int8_t*)res;
   const int64_t ld = n_res;
-  if (waves == 4 && QK / 4 <= kCrtNoReduce) {
+  if (waves == 4 && QK / 4 * (real ? 2 : 1) <= kCrtNoReduce) {
     if (real)
       hipLaunchKernelGGL((k_hs_crt<4, true>), grid, dim3(256), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr,
-                         res, ld);
+                         o, ld);
     else
       hipLaunchKernelGGL((k_hs_crt<4, false>), grid, dim3(256), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr,
-                         res, ld);
+                         o, ld);
   } else {
     if (real)
       hipLaunchKernelGGL((k_hs_crt<8, true>), grid, dim3(512), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr,
-                         res, ld);
+                         o, ld);
     else
       hipLaunchKernelGGL((k_hs_crt<8, false>), grid, dim3(512), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr,
-                         res, ld);
+                         o, ld);
   }
   return hipGetLastError();
 }
@@ -486,10 +488,11 @@ hipError_t launch_hs_crt(const CrtConsts& cc, bool real, const void* L, const vo
 hipError_t launch_crt_combine(const CrtConsts& cc, bool real, const void* res, int n_res, const double* scL,
                               const double* scR, int n, void* C, hipStream_t s) {
   dim3 grid((n + 255) / 256, n);
+  const int8_t* r = (const int8_t*)res;
   if (real)
-    hipLaunchKernelGGL((k_crt_combine<true>), grid, dim3(256), 0, s, cc, res, (int64_t)n_res, scL, scR, n, C);
+    hipLaunchKernelGGL((k_crt_combine<true>), grid, dim3(256), 0, s, cc, r, (int64_t)n_res, scL, scR, n, C);
   else
-    hipLaunchKernelGGL((k_crt_combine<false>), grid, dim3(256), 0, s, cc, res, (int64_t)n_res, scL, scR, n, C);
+    hipLaunchKernelGGL((k_crt_combine<false>), grid, dim3(256), 0, s, cc, r, (int64_t)n_res, scL, scR, n, C);
   return hipGetLastError();
 }
 

@@ -66,14 +66,4 @@ __device__ inline void tile_origin(int w, int nbr, int gr, int& row0, int& col0)
   col0 = sj * 128 + (w & 1) * 64;
 }
 
-// Tile w -> (row0, col0) of a 256 x 128 tile: two per 256 x 256 super-tile of an
-// nbs x nbs grid, in the same orders as tile_origin.
-__device__ inline void tile_origin_256(int w, int nbs, int gr, int& row0, int& col0) {
-  int bi, sj;
-  if (gr > 0) grouped_decode(w >> 1, nbs, gr, bi, sj);
-  else tri_decode(w >> 1, nbs, bi, sj);
-  row0 = bi * 256;
-  col0 = sj * 256 + (w & 1) * 128;
-}
-
 }  // namespace hsb
