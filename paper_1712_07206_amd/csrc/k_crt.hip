@@ -160,12 +160,12 @@ __device__ __forceinline__ int smod_i(int v, int m, double inv_m, int h) {
 // Contraction tile: one product (P, Q, or the real product) over a 256 x 256 block of
 // (G', G) per workgroup, so each side needs one residue plane: a 64-row chunk of the stacked
 // index is 16 KB of left and 16 KB of right residues, copied straight into LDS
-// (global_load_lds_dwordx4) through a ring of three 32 KB stages, two chunks ahead of its use.
+// (global_load_lds_dwordx4) through a ring of four 32 KB stages, three chunks ahead of its use.
 // (Computing P and Q together on a 256 x 128 tile takes the same registers and MFMAs but copies
 // 48 KB per chunk: both planes of both sides.)  WAVES = 8: waves of 64 x 128 (2 x 4 blocks of
 // 32 x 32, two waves per SIMD); WAVES = 4: waves of 128 x 128 (4 x 4 blocks, one wave per SIMD,
 // 2/3 of the LDS reads per MFMA).
-constexpr int kCrtStages = 3;
+constexpr int kCrtStages = 4;
 constexpr int kCrtSideUnits = 4 * 4 * 64;                 // 4 blocks of 64 columns x 4 row groups x 64
 constexpr int kCrtStageUnits = 2 * kCrtSideUnits;         // left, then right (32 KB)
 constexpr int kCrtCopies = kCrtStageUnits / 64;           // 1 KB copies per chunk (32)
@@ -268,21 +268,25 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
   const int la = qh * 64 + g32;
   const int ra = kCrtSideUnits + (2 * wc * 4 + qh) * 64 + g32;
   const int nchunks = (QK >> 2) * (REAL ? 2 : 1);  // stages
-  if (nchunks > 0) issue(0, 0);
-  if (nchunks > 1) issue(1, 1);
+#pragma unroll
+  for (int i = 0; i < kCrtStages - 1; ++i)
+    if (i < nchunks) issue(i, i);
   for (int c = 0; c < nchunks; ++c) {
-    // this wave's copies of chunk c are done once at most those of chunk c + 1 are pending
-    if (c + 1 < nchunks) __builtin_amdgcn_s_waitcnt(vmcnt_only(NPW));
+    // this wave's copies of chunk c are done once at most those of the chunks after it
+    // (up to kCrtStages - 2 of them) are pending
+    const int pend = min(kCrtStages - 2, nchunks - 1 - c);
+    if (pend >= 2) __builtin_amdgcn_s_waitcnt(vmcnt_only(2 * NPW));
+    else if (pend == 1) __builtin_amdgcn_s_waitcnt(vmcnt_only(NPW));
     else __builtin_amdgcn_s_waitcnt(vmcnt_only(0));
-    // Every wave's copies of chunk c are in LDS past this barrier, and stage (c + 2) % 3 is
+    // Every wave's copies of chunk c are in LDS past this barrier, and stage (c - 1) % 4 is
     // free (its reads, of chunk c - 1, fed MFMAs before the barrier).  A plain s_barrier: the
-    // release fence of __syncthreads would wait for the copies of chunk c + 1 as well.
+    // release fence of __syncthreads would wait for the copies still in flight as well.
     __builtin_amdgcn_s_barrier();
     asm volatile("" ::: "memory");
-    // The copies of chunk c + 2 go out one after each pair of MFMAs (scheduling fences keep
+    // The copies of chunk c + 3 go out one after each pair of MFMAs (scheduling fences keep
     // them there): issued together after the barrier they hold up the MFMAs behind them.
-    const bool more = c + 2 < nchunks;
-    const int nbuf = (c + 2) % kCrtStages;
+    const bool more = c + kCrtStages - 1 < nchunks;
+    const int nbuf = (c + kCrtStages - 1) % kCrtStages;
     const u4* B = lds[c % kCrtStages];
     int ci = 0;
 #pragma unroll
@@ -301,8 +305,8 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
         for (int cb = 0; cb < 4; ++cb) {
           acc[rb][cb] = mfma_i8(a[rb], b[cb], acc[rb][cb]);
           if ((cb & 1) && more && ci < NPW)
-            __builtin_amdgcn_global_load_lds((const void*)(at(ci, c + 2) + lane), (lds_ptr)(&lds[nbuf][dst[ci]]), 16,
-                                             0, 0);
+            __builtin_amdgcn_global_load_lds((const void*)(at(ci, c + kCrtStages - 1) + lane),
+                                             (lds_ptr)(&lds[nbuf][dst[ci]]), 16, 0, 0);
           if (cb & 1) {
             ++ci;
             __builtin_amdgcn_sched_barrier(0);
@@ -338,40 +342,59 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
 // Im = (P - Q) / (2 j) (mod m) (the real form: its one product), then
 // value = M * frac(sum_i r_i y_i / m_i), times 2^-(f_row + f_col).  sum r_i h_i is exact (h_i on a
 // 2^-42 grid, |r_i| < 2^7, n <= 13 terms), so the rounding to the nearest integer is exact and
-// the fraction keeps FP64 precision.  One thread per (row, col).
+// the fraction keeps FP64 precision.  One thread per four consecutive columns of a row (4-byte
+// loads of the residues; the rows are n_res bytes long, so the four are always in the row).
 template <bool REAL>
 __global__ void __launch_bounds__(256) k_crt_combine(CrtConsts cc, const int8_t* __restrict__ res, int64_t ld,
                                                      const double* __restrict__ scL, const double* __restrict__ scR,
                                                      int n, void* __restrict__ Cv) {
   const int row = blockIdx.y;
-  const int col = blockIdx.x * 256 + threadIdx.x;
-  if (col >= n || col < row) return;
-  const int64_t mstride = ld * ld, e = (int64_t)row * ld + col;
-  double hr = 0.0, lr = 0.0, hi = 0.0, li = 0.0;
+  const int col0 = (blockIdx.x * 256 + threadIdx.x) * 4;
+  if (col0 >= n || col0 + 3 < row) return;
+  const int64_t mstride = ld * ld, e = (int64_t)row * ld + col0;
+  double hr[4] = {0.0, 0.0, 0.0, 0.0}, lr[4] = {0.0, 0.0, 0.0, 0.0};
+  double hi[4] = {0.0, 0.0, 0.0, 0.0}, li[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = 0; i < cc.n_mod; ++i) {
+    const double h = cc.h[i], l = cc.l[i];
     if constexpr (REAL) {
-      const double r = (double)res[i * mstride + e];
-      hr += r * cc.h[i];
-      lr += r * cc.l[i];
+      const unsigned v = *(const unsigned*)(res + i * mstride + e);
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const double r = (double)(int8_t)(v >> (8 * u));
+        hr[u] += r * h;
+        lr[u] += r * l;
+      }
     } else {
-      const int p = res[(2 * i) * mstride + e], q = res[(2 * i + 1) * mstride + e];
+      const unsigned vp = *(const unsigned*)(res + (2 * i) * mstride + e);
+      const unsigned vq = *(const unsigned*)(res + (2 * i + 1) * mstride + e);
       const int m = cc.m[i], hm = (m - 1) / 2;
       const double inv_m = 1.0 / (double)m;
-      const double r = (double)smod_i((p + q) * cc.inv2[i], m, inv_m, hm);
-      const double t = (double)smod_i((p - q) * cc.inv2j[i], m, inv_m, hm);
-      hr += r * cc.h[i];
-      lr += r * cc.l[i];
-      hi += t * cc.h[i];
-      li += t * cc.l[i];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int p = (int8_t)(vp >> (8 * u)), q = (int8_t)(vq >> (8 * u));
+        const double r = (double)smod_i((p + q) * cc.inv2[i], m, inv_m, hm);
+        const double t = (double)smod_i((p - q) * cc.inv2j[i], m, inv_m, hm);
+        hr[u] += r * h;
+        lr[u] += r * l;
+        hi[u] += t * h;
+        li[u] += t * l;
+      }
     }
   }
-  const double sc = cc.M / (scL[row] * scR[col]);
-  const double fr = (hr - rint(hr)) + lr;
-  if constexpr (REAL) {
-    ((double*)Cv)[(int64_t)row * n + col] = fr * sc;
-  } else {
-    const double fi = (hi - rint(hi)) + li;
-    ((d2*)Cv)[(int64_t)row * n + col] = d2{fr * sc, fi * sc};
+  const double sl = cc.M / scL[row];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int col = col0 + u;
+    if (col < n && col >= row) {
+      const double sc = sl / scR[col];
+      const double fr = (hr[u] - rint(hr[u])) + lr[u];
+      if constexpr (REAL) {
+        ((double*)Cv)[(int64_t)row * n + col] = fr * sc;
+      } else {
+        const double fi = (hi[u] - rint(hi[u])) + li[u];
+        ((d2*)Cv)[(int64_t)row * n + col] = d2{fr * sc, fi * sc};
+      }
+    }
   }
 }
 
@@ -487,7 +510,7 @@ hipError_t launch_hs_crt(const CrtConsts& cc, bool real, const void* L, const vo
 
 hipError_t launch_crt_combine(const CrtConsts& cc, bool real, const void* res, int n_res, const double* scL,
                               const double* scR, int n, void* C, hipStream_t s) {
-  dim3 grid((n + 255) / 256, n);
+  dim3 grid((n + 1023) / 1024, n);
   const int8_t* r = (const int8_t*)res;
   if (real)
     hipLaunchKernelGGL((k_crt_combine<true>), grid, dim3(256), 0, s, cc, r, (int64_t)n_res, scL, scR, n, C);
