@@ -185,10 +185,13 @@ def test_crt_past_the_reduction_window(waves):
     assert eh <= TOL_SPLIT and es <= TOL_SPLIT
 
 
-def _real_crt(case, poison=True):
+def _real_crt(case, poison=True, waves=None):
     from paper_1712_07206_amd import HSB_SPLIT_CRT
+    from paper_1712_07206_amd import _native as N
     from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
     b = HSBuilder.from_case(case, precision=HSB_SPLIT_CRT, n_slices=N_MOD)
+    if waves is not None:
+        b.set_option(N.HSB_OPT_HS_WAVES, waves)
     g, tau, T = case_tensors(case)
     n = case["n_g"]
     print("real residue form: N_G %d, %d atoms" % (n, case["n_atoms"]), flush=True)
@@ -232,3 +235,27 @@ def test_crt_is_reproducible():
     H1, S1 = _crt(case, poison=False)
     H2, S2 = _crt(case, poison=False)
     assert np.array_equal(H1, H2) and np.array_equal(S1, S2)
+
+
+@pytest.mark.parametrize("waves", [4, 8])
+def test_crt_stacked_widths_shorter_than_the_copy_ring(waves):
+    """Stacked widths of one, two and three 64-row chunks, fewer than the four stages of
+    the copy ring: a one-atom cell (50 rows), the two-atom cell (100) and the five-atom
+    cell (160), and the real form of the five-atom cell (3 representatives, 96 rows: two
+    chunks, each taken twice), against the oracle, in both contraction layouts."""
+    base = make_case(0)
+    one = dict(base)
+    one["atom_type"], one["tau"], one["n_atoms"] = base["atom_type"][:1], base["tau"][:1], 1
+    for case in (one, base, make_case(8)):
+        Hr, Sr = o.hs(case)
+        H, S = _crt(case, waves=waves)
+        eh, es = rel(_full(H), Hr), rel(_full(S), Sr)
+        print("residue form (%d waves), stacked width %d: H %.3e S %.3e" % (
+            waves, 2 * case["n_atoms"] * case["n_l"], eh, es))
+        assert eh <= TOL_SPLIT and es <= TOL_SPLIT
+    rcase, (Hr, Sr) = oracle(8, None)
+    H, S = _real_crt(rcase, waves=waves)
+    eh = rel(np.triu(H) + np.triu(H, 1).T, Hr.real)
+    es = rel(np.triu(S) + np.triu(S, 1).T, Sr.real)
+    print("real residue form (%d waves), five-atom cell: H %.3e S %.3e" % (waves, eh, es))
+    assert eh <= TOL_SPLIT and es <= TOL_SPLIT
