@@ -99,13 +99,15 @@ def cpu_baseline(index: int, n_g: int, split_forms=()) -> dict:
 
 
 def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
-    """The split-precision forwards on the same workload (int8 slices, then BF16
-    slices): time per step, speedup over the FP64 path timed next to them and the
-    relative Frobenius error against it.  The first form that meets the 1e-10 bar
-    is the headline split figure."""
+    """The split-precision forwards on the same workload (the residue form on the
+    int8, BF16 and FP16 matrix cores, then int8, BF16 and FP16 slices): time per
+    step, speedup over the FP64 path timed next to them and the relative Frobenius
+    error against it.  The fastest form that meets the 1e-10 bar is the headline
+    split figure."""
     import torch
 
-    from paper_1712_07206_amd import HSB_SPLIT_BF16, HSB_SPLIT_CRT, HSB_SPLIT_FP16, HSB_SPLIT_INT8
+    from paper_1712_07206_amd import (HSB_SPLIT_BF16, HSB_SPLIT_CRT, HSB_SPLIT_CRT_BF16, HSB_SPLIT_CRT_FP16,
+                                      HSB_SPLIT_FP16, HSB_SPLIT_INT8)
     from paper_1712_07206_amd import _native as N
     from paper_1712_07206_amd.hsbuild import HSBuilder, hermitian_full
     n = case["n_g"]
@@ -150,7 +152,7 @@ def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
         stage_ms, _ = bs.stage_times()
         eh = (torch.linalg.norm(hermitian_full(H) - H64) / torch.linalg.norm(H64)).item()
         es = (torch.linalg.norm(hermitian_full(S) - S64) / torch.linalg.norm(S64)).item()
-        if precision == HSB_SPLIT_CRT:
+        if precision in (HSB_SPLIT_CRT, HSB_SPLIT_CRT_BF16, HSB_SPLIT_CRT_FP16):
             # residue-MFMA work of the two contraction launches (S and H): every 256 x 256 block of the
             # upper triangle, the stacked rows padded to 64, per modulus two int8 products (P and Q,
             # one workgroup each) x 2 operations
@@ -186,6 +188,9 @@ def split_leg(args, case, b64, g, tau, T, H, S, ws, ms_fp64, flops) -> dict:
     forms = []
     if args.crt_moduli > 0:  # "slices" of the residue form: its moduli; "slice_bits": bits per residue byte
         forms.append(one("crt", HSB_SPLIT_CRT, args.crt_moduli, 8, 5000.0, "TOP/s", "k_hs_crt"))
+    if args.crt16_moduli > 0:  # the residues as bfloat16 / half integers on the 16-bit matrix cores
+        forms.append(one("crt_bf16", HSB_SPLIT_CRT_BF16, args.crt16_moduli, 8, 2500.0, "TFLOP/s", "k_hs_crt"))
+        forms.append(one("crt_fp16", HSB_SPLIT_CRT_FP16, args.crt16_moduli, 8, 2500.0, "TFLOP/s", "k_hs_crt"))
     if args.int8_slices > 0:
         forms.append(one("int8", HSB_SPLIT_INT8, args.int8_slices, 7, 5000.0, "TOP/s", "k_hs_split8"))
     if args.split_slices > 0:
@@ -782,6 +787,9 @@ def main() -> int:
                     help="also time the FP16 split-precision path with this many slices (0: skip)")
     ap.add_argument("--crt-moduli", type=int, default=11,
                     help="also time the residue (CRT) split-precision path with this many moduli (0: skip)")
+    ap.add_argument("--crt16-moduli", type=int, default=11,
+                    help="also time the residue form on the BF16 and FP16 matrix cores with this many moduli "
+                         "(0: skip)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
                     help="first run one plain device-to-device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
@@ -916,7 +924,8 @@ def main() -> int:
         result["factored"] = factored_leg(args, case, g, tau, T, H, S, ms_step)
     if not args.no_hsdla:
         result["hsdla_rocblas"] = hsdla_leg(args, case, g, tau, T, H, S, ms_step)
-    if args.split_slices > 0 or args.int8_slices > 0 or args.fp16_slices > 0 or args.crt_moduli > 0:
+    if args.split_slices > 0 or args.int8_slices > 0 or args.fp16_slices > 0 or args.crt_moduli > 0 or \
+            args.crt16_moduli > 0:
         result["split"] = split_leg(args, case, b, g, tau, T, H, S, ws, ms_step, flops)
         if result["split"]["meets_1e-10"]:
             result["split_speedup"] = result["split"]["speedup"]

@@ -72,8 +72,13 @@ enum {
  * Gaussian integers, multiplies their residues modulo n_slices coprime moduli
  * below 256 on the int8 matrix cores (exact int32 sums, two products per
  * modulus for a complex product) and recovers the integer products by the
- * Chinese remainder theorem in FP64. */
-enum { HSB_FP64 = 0, HSB_SPLIT_FP16 = 1, HSB_SPLIT_BF16 = 2, HSB_SPLIT_INT8 = 3, HSB_SPLIT_CRT = 4 };
+ * Chinese remainder theorem in FP64.  HSB_SPLIT_CRT_BF16 and
+ * HSB_SPLIT_CRT_FP16 are the same residue form with the residues as bfloat16
+ * or half integers on the 16-bit matrix cores (FP32 sums, exact for integers
+ * below 2^24: reduced modulo each modulus every 1024 stacked rows); the three
+ * give bitwise the same H and S. */
+enum { HSB_FP64 = 0, HSB_SPLIT_FP16 = 1, HSB_SPLIT_BF16 = 2, HSB_SPLIT_INT8 = 3, HSB_SPLIT_CRT = 4,
+       HSB_SPLIT_CRT_BF16 = 5, HSB_SPLIT_CRT_FP16 = 6 };
 
 /* Workspace modes for hsbuild_workspace_bytes. */
 enum { HSB_MODE_FORWARD = 0, HSB_MODE_BACKWARD = 1, HSB_MODE_BATCH = 2, HSB_MODE_COEFFICIENTS = 3, HSB_MODE_FACTORED = 4,
@@ -94,12 +99,13 @@ typedef struct {
   const double* r_mt;         /* [n_types] muffin-tin radii (bohr), > 0 */
   const double* radial;       /* [n_types][l_max+1][4]: u, u', udot, udot' at R_MT */
   const double* udot_norm2;   /* [n_types][l_max+1]: ||udot_l||^2 >= 0 */
-  int32_t precision;          /* HSB_FP64, HSB_SPLIT_FP16, HSB_SPLIT_BF16, HSB_SPLIT_INT8 or
-                                 HSB_SPLIT_CRT */
+  int32_t precision;          /* HSB_FP64, HSB_SPLIT_FP16, HSB_SPLIT_BF16, HSB_SPLIT_INT8,
+                                 HSB_SPLIT_CRT, HSB_SPLIT_CRT_BF16 or HSB_SPLIT_CRT_FP16 */
   int32_t n_slices;           /* split path only: slices per operand, 3..6 (8 bits each
-                                 for BF16/FP16, 7 for INT8); for HSB_SPLIT_CRT the number
-                                 of moduli, 8..13 (each adds about 3.7 bits per operand
-                                 column; 11 keeps the error near 1e-11) */
+                                 for BF16/FP16, 7 for INT8); for the residue forms
+                                 (HSB_SPLIT_CRT*) the number of moduli, 8..13 (each adds
+                                 about 3.7 bits per operand column; 11 keeps the error
+                                 near 1e-11) */
 } hsb_config;
 
 /* Create a handle.  Returns HSB_ERR_NUMERIC if some radial Wronskian
@@ -176,9 +182,9 @@ int hsbuild_forward_factored(hsbuild_t h, const double k_frac[3], int32_t ng, co
  * upper triangle written; equal to the real parts of hsbuild_forward's
  * outputs up to FP64 rounding (undefined if the symmetry does not hold).
  * Other arguments as hsbuild_forward.  A handle created with HSB_FP64 runs
- * the FP64 contraction; one created with HSB_SPLIT_INT8 or HSB_SPLIT_CRT runs
- * that split contraction (the real parts of the split products, to the split
- * path's error); HSB_SPLIT_BF16 and HSB_SPLIT_FP16 handles get
+ * the FP64 contraction; one created with HSB_SPLIT_INT8 or a residue form
+ * (HSB_SPLIT_CRT*) runs that split contraction (the real parts of the split
+ * products, to the split path's error); HSB_SPLIT_BF16 and HSB_SPLIT_FP16 handles get
  * HSB_ERR_UNSUPPORTED before anything is enqueued.
  * Workspace: hsbuild_workspace_bytes(h, HSB_MODE_REAL, 1, &ng). */
 int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const int32_t* g, const double* tau,
@@ -281,12 +287,14 @@ int hsbuild_stage_times(hsbuild_t h, double* ms_avg, int32_t* n_calls);
  * 8 (32 x 32 per wave, two per SIMD; three real products per complex one, the
  * 3M form; 128 x 128 tiles of 32 x 64 for hsbuild_forward_real, which is
  * real); default 8.  The two complex forms agree to FP64 rounding, not
- * bitwise.  On a handle with HSB_SPLIT_CRT the option picks the layout of the
- * residue contraction instead (256 x 256 blocks): 4 (waves of 128 x 128, one
- * per SIMD; the default there) or 8 (64 x 128, two per SIMD); the 4-wave
- * layout keeps its int32 sums unreduced and so runs up to 2048 stages of 64
- * stacked rows (the real form takes two stages per 64 rows), beyond which the
- * 8-wave layout runs.  Both give bitwise the same H and S.
+ * bitwise.  On a handle with a residue form (HSB_SPLIT_CRT*) the option
+ * picks the layout of the residue contraction instead (256 x 256 blocks): 4
+ * (waves of 128 x 128, one per SIMD; the default there) or 8 (64 x 128, two
+ * per SIMD); in HSB_SPLIT_CRT the 4-wave layout keeps its int32 sums
+ * unreduced and so runs up to 2048 stages of 64 stacked rows (the real form
+ * takes two stages per 64 rows), beyond which the 8-wave layout runs; the
+ * 16-bit residue forms run the 8-wave layout only (their default is 8).  All
+ * give bitwise the same H and S.
  * HSB_OPT_SPLIT_K: 1 (default) lets the 8-wave FP64 forward cut the stacked
  * index into segments when the upper triangle has fewer than 4 tiles per
  * compute unit (2..8 segments of at least 256 rows, chosen by a model of the

@@ -26,6 +26,8 @@ HSB_SPLIT_FP16 = 1
 HSB_SPLIT_BF16 = 2
 HSB_SPLIT_INT8 = 3
 HSB_SPLIT_CRT = 4
+HSB_SPLIT_CRT_BF16 = 5
+HSB_SPLIT_CRT_FP16 = 6
 HSB_PROBE_FP64 = 0
 HSB_PROBE_INT8 = 1
 HSB_PROBE_INT8_RANDOM = 2

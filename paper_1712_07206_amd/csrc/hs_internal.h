@@ -188,16 +188,26 @@ int crt_tiles(int n_res);
 // Column scales (powers of two) of W, lam W and Y: scale[0..3 n_res); part: 3 crt_norm_blocks(K) n_res doubles.
 hipError_t launch_crt_scales(const double2* W, const double2* Y, const double* lam, int K, int n_pad, int n_res,
                              const CrtConsts& cc, double* part, double* scale, hipStream_t s);
+// Element kind of the residues: signed bytes on the int8 MFMA (HSB_SPLIT_CRT), bfloat16
+// (HSB_SPLIT_CRT_BF16) or half (HSB_SPLIT_CRT_FP16) integers on the 16-bit MFMAs.
+inline int crt_kind(int precision) {
+  return precision == HSB_SPLIT_CRT_BF16 ? 1 : precision == HSB_SPLIT_CRT_FP16 ? 2 : 0;
+}
+inline bool is_crt(int precision) {
+  return precision == HSB_SPLIT_CRT || precision == HSB_SPLIT_CRT_BF16 || precision == HSB_SPLIT_CRT_FP16;
+}
+// Stacked rows per 16-byte residue unit: 16 bytes, or 8 16-bit elements.
+inline int crt_unit_rows(int ek) { return ek == 0 ? 16 : 8; }
 // Residue planes of X (times lam if use_lam): per modulus [QK / 4][n_res / 64][2][4][64] 16-byte units
-// (chunk-major), QK = K64 / 16.
-hipError_t launch_crt_residues(const CrtConsts& cc, const double2* X, const double* lam, int use_lam, int K, int n_pad,
-                               int n_res, int QK, const double* scale, void* out, hipStream_t s);
+// (chunk-major), QK = K64 / crt_unit_rows(ek).
+hipError_t launch_crt_residues(const CrtConsts& cc, int ek, const double2* X, const double* lam, int use_lam, int K,
+                               int n_pad, int n_res, int QK, const double* scale, void* out, hipStream_t s);
 // Residues of the upper triangle of conj(L)^T R per modulus: res [n_mod][2][n_res][n_res] signed
 // bytes, P then Q (the images of the product under the two factors of Z[i]/m); the real form
 // [n_mod][n_res][n_res], its one product.  256 x 256 blocks; waves: 8 (waves of 64 x 128) or
 // 4 (128 x 128).
-hipError_t launch_hs_crt(const CrtConsts& cc, bool real, const void* L, const void* R, int QK, int n, int n_res,
-                         int gr, int waves, void* res, hipStream_t s);
+hipError_t launch_hs_crt(const CrtConsts& cc, int ek, bool real, const void* L, const void* R, int QK, int n,
+                         int n_res, int gr, int waves, void* res, hipStream_t s);
 // C[row][col] (row <= col < n, ld n) from the residues (Re, Im from P, Q per modulus), scaled by
 // 1 / (scL[row] scR[col]); complex or real.
 hipError_t launch_crt_combine(const CrtConsts& cc, bool real, const void* res, int n_res, const double* scL,

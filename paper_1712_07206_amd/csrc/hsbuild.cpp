@@ -176,11 +176,12 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
       L.skS = take((size_t)L.ns * np * np * sizeof(double2));
     }
   }
-  if ((mode == HSB_MODE_FORWARD || mode == HSB_MODE_REAL) && h.precision == HSB_SPLIT_CRT) {
+  if ((mode == HSB_MODE_FORWARD || mode == HSB_MODE_REAL) && is_crt(h.precision)) {
     L.K64 = (int)round_up(L.K, kCrtRows);
     L.n_res = crt_cols(ng);
     const size_t nr = (size_t)L.n_res;
-    const size_t planes = (size_t)2 * h.crt.n_mod * L.K64 * nr;  // bytes of one operand's residue planes
+    // bytes of one operand's residue planes: bytes, or 16-bit elements
+    const size_t planes = (size_t)2 * h.crt.n_mod * L.K64 * nr * (crt_kind(h.precision) ? 2 : 1);
     L.crPart = take((size_t)3 * crt_norm_blocks(L.K) * nr * sizeof(double));
     L.scale = take(3 * nr * sizeof(double));
     L.slL = take(planes);
@@ -341,23 +342,24 @@ int enqueue_crt(hsbuild_t h, const Layout& L, char* w, void* H, void* S, bool re
   const double2* Y = (const double2*)(w + L.Y);
   const double* lam = (const double*)(w + L.lam);
   double* sc = (double*)(w + L.scale);
-  const int QK = (int)round_up(L.K, kCrtRows) / 16;  // 16-byte units (16 rows of int8) per column
+  const int ek = crt_kind(h->precision);
+  const int QK = (int)round_up(L.K, kCrtRows) / crt_unit_rows(ek);  // 16-byte units per column
   const int nr = L.n_res;
   const CrtConsts& cc = h->crt;
   int rc = launched(h, launch_crt_scales(W, Y, lam, L.K, L.n_pad, nr, cc, (double*)(w + L.crPart), sc, s),
                     "residue scales");
-  if (!rc) rc = launched(h, launch_crt_residues(cc, W, lam, 0, L.K, L.n_pad, nr, QK, sc, w + L.slL, s), "residues");
+  if (!rc) rc = launched(h, launch_crt_residues(cc, ek, W, lam, 0, L.K, L.n_pad, nr, QK, sc, w + L.slL, s), "residues");
   if (!rc)
-    rc = launched(h, launch_crt_residues(cc, W, lam, 1, L.K, L.n_pad, nr, QK, sc + nr, w + L.slS, s), "residues");
+    rc = launched(h, launch_crt_residues(cc, ek, W, lam, 1, L.K, L.n_pad, nr, QK, sc + nr, w + L.slS, s), "residues");
   if (!rc)
-    rc = launched(h, launch_crt_residues(cc, Y, lam, 0, L.K, L.n_pad, nr, QK, sc + 2 * nr, w + L.slY, s), "residues");
+    rc = launched(h, launch_crt_residues(cc, ek, Y, lam, 0, L.K, L.n_pad, nr, QK, sc + 2 * nr, w + L.slY, s), "residues");
   mark(h, 2, s);  // (again) the operand preparation ends here: the contraction stage starts
   if (!rc)
-    rc = launched(h, launch_hs_crt(cc, real, w + L.slL, w + L.slS, QK, L.n, nr, h->tile_group, h->hs_waves,
+    rc = launched(h, launch_hs_crt(cc, ek, real, w + L.slL, w + L.slS, QK, L.n, nr, h->tile_group, h->hs_waves,
                                    w + L.crRes, s),
                   "residue contraction (S)");
   if (!rc)
-    rc = launched(h, launch_hs_crt(cc, real, w + L.slL, w + L.slY, QK, L.n, nr, h->tile_group, h->hs_waves,
+    rc = launched(h, launch_hs_crt(cc, ek, real, w + L.slL, w + L.slY, QK, L.n, nr, h->tile_group, h->hs_waves,
                                    w + L.crResH, s),
                   "residue contraction (H)");
   mark(h, 3, s);
@@ -370,7 +372,7 @@ int enqueue_crt(hsbuild_t h, const Layout& L, char* w, void* H, void* S, bool re
 
 // Split-precision contraction: column scales, slices of W, lam W and Y, then S and H.
 int enqueue_split(hsbuild_t h, const Layout& L, char* w, double2* H, double2* S, hipStream_t s) {
-  if (h->precision == HSB_SPLIT_CRT) return enqueue_crt(h, L, w, H, S, false, s);
+  if (is_crt(h->precision)) return enqueue_crt(h, L, w, H, S, false, s);
   const double2* W = (const double2*)(w + L.W);
   const double2* Y = (const double2*)(w + L.Y);
   const double* lam = (const double*)(w + L.lam);
@@ -406,7 +408,7 @@ int enqueue_split(hsbuild_t h, const Layout& L, char* w, double2* H, double2* S,
 // Real-symmetric int8 split contraction on the representatives' rows (L.K): column scales and
 // slices as in the complex form, then S = Re(W^H lam W) and H = Re(W^H Y) into real arrays.
 int enqueue_split_real(hsbuild_t h, const Layout& L, char* w, double* H, double* S, hipStream_t s) {
-  if (h->precision == HSB_SPLIT_CRT) return enqueue_crt(h, L, w, H, S, true, s);
+  if (is_crt(h->precision)) return enqueue_crt(h, L, w, H, S, true, s);
   const double2* W = (const double2*)(w + L.W);
   const double2* Y = (const double2*)(w + L.Y);
   const double* lam = (const double*)(w + L.lam);
@@ -551,10 +553,10 @@ int hsbuild_create(const hsb_config* cfg, hsbuild_t* out) {
   if (!cfg->atom_type || !cfg->r_mt || !cfg->radial || !cfg->udot_norm2)
     return fail(nullptr, HSB_ERR_ARG, "null atom_type, r_mt, radial or udot_norm2");
   if (cfg->precision != HSB_FP64 && cfg->precision != HSB_SPLIT_FP16 && cfg->precision != HSB_SPLIT_BF16 &&
-      cfg->precision != HSB_SPLIT_INT8 && cfg->precision != HSB_SPLIT_CRT)
+      cfg->precision != HSB_SPLIT_INT8 && !is_crt(cfg->precision))
     return fail(nullptr, HSB_ERR_ARG, "unknown precision %d", cfg->precision);
   CrtConsts crt{};
-  if (cfg->precision == HSB_SPLIT_CRT) {
+  if (is_crt(cfg->precision)) {
     if (!crt_make_consts(cfg->n_slices, &crt))
       return fail(nullptr, HSB_ERR_ARG, "n_slices=%d (moduli of the residue form) outside [%d, %d]", cfg->n_slices,
                   kCrtMinModuli, kCrtMaxModuli);
@@ -634,7 +636,9 @@ int hsbuild_create(const hsb_config* cfg, hsbuild_t* out) {
   h->max_ng = cfg->max_ng;
   h->precision = cfg->precision;
   if (cfg->precision != HSB_FP64) h->tile_group = 4;  // measured best for the split contraction
-  if (cfg->precision == HSB_SPLIT_CRT) h->hs_waves = 4;  // residue contraction: waves of 128 x 128, measured best
+  // residue contraction: waves of 128 x 128 in the byte form (measured best); the 16-bit forms have
+  // the 8-wave layout only
+  if (is_crt(cfg->precision)) h->hs_waves = crt_kind(cfg->precision) == 0 ? 4 : 8;
   h->n_slices = cfg->n_slices;
   h->crt = crt;
   std::memcpy(h->lattice, cfg->lattice, sizeof h->lattice);
@@ -876,7 +880,7 @@ int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const 
   if (!k_frac || !g || !tau || !partner || !T || !H || !S)
     return fail(h, HSB_ERR_ARG, "null k_frac, g, tau, partner, T, H or S");
   if (H == S) return fail(h, HSB_ERR_ARG, "H and S must be distinct buffers");
-  if (h->precision != HSB_FP64 && h->precision != HSB_SPLIT_INT8 && h->precision != HSB_SPLIT_CRT)
+  if (h->precision != HSB_FP64 && h->precision != HSB_SPLIT_INT8 && !is_crt(h->precision))
     return fail(h, HSB_ERR_UNSUPPORTED,
                 "the real-symmetric build has FP64, int8 slice and residue forms only (no BF16/FP16)");
   int rc = check_ng(h, ng);
@@ -948,7 +952,7 @@ int hsbuild_forward_real(hsbuild_t h, const double k_frac[3], int32_t ng, const 
                                     tau_rep, wrow, lam, s),
                 "k_rep_setup");
   if (!rc) rc = launched(h, launch_scale_rows(Y, wrow, Lr.K_pad, L.n_pad, Y, s), "k_scale_rows");
-  if (!rc && (h->precision == HSB_SPLIT_INT8 || h->precision == HSB_SPLIT_CRT)) {
+  if (!rc && (h->precision == HSB_SPLIT_INT8 || is_crt(h->precision))) {
     rc = enqueue_split_real(h, Lr, w, H, S, s);
   } else if (!rc) {
     double2* WL = (double2*)(w + L.WL);  // S's right operand, lam W (lam with the pair weights)

@@ -41,6 +41,9 @@ typedef double d2 __attribute__((ext_vector_type(2)));
 typedef unsigned int u4 __attribute__((ext_vector_type(4)));
 typedef int i4v __attribute__((ext_vector_type(4)));
 typedef int i16v __attribute__((ext_vector_type(16)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef __attribute__((address_space(3))) void* lds_ptr;
 
 constexpr int kNormRows = 512;  // stacked rows per partial sum of the column norms
@@ -99,22 +102,34 @@ __device__ __forceinline__ double smod_d(double v, double m, double inv_m) {
   return fma(-rint(v * inv_m), m, v);
 }
 
-// One thread per (column G, 16-row group q): the 2 n_mod residue planes of 16 rows of X
-// (times lam if use_lam), scaled by scale[G] and rounded.
+// Residue r (an integer in [-(m-1)/2, (m-1)/2], as a double) as the element of kind EK: a signed
+// byte (0), or the bits of a bfloat16 (1) or an IEEE half (2), both exact for |r| <= 256.
+template <int EK>
+__device__ __forceinline__ unsigned residue_bits(double r) {
+  if constexpr (EK == 0) return (unsigned)(int)r & 0xffu;
+  else if constexpr (EK == 1) return (unsigned)__builtin_bit_cast(unsigned short, (__bf16)(float)r);
+  else return (unsigned)__builtin_bit_cast(unsigned short, (_Float16)(float)r);
+}
+
+// One thread per (column G, unit q of RU = 16 (bytes) or 8 (16-bit elements) rows): the 2 n_mod
+// residue planes of those rows of X (times lam if use_lam), scaled by scale[G] and rounded.
+template <int EK>
 __global__ void __launch_bounds__(256) k_crt_residues(CrtConsts cc, const d2* __restrict__ X,
                                                       const double* __restrict__ lam, int use_lam, int K, int n_pad,
                                                       int n_res, int QK, const double* __restrict__ scale,
                                                       u4* __restrict__ out) {
+  constexpr int RU = EK == 0 ? 16 : 8;  // rows per 16-byte unit
+  constexpr int EB = 16 / RU;           // bytes per element
   const int g = threadIdx.x & 63;
   const int q = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int b = blockIdx.x;
   const int G = b * 64 + g;
   if (q >= QK) return;
   const double sc = scale[G];
-  double re[16], im[16];
+  double re[RU], im[RU];
 #pragma unroll
-  for (int r = 0; r < 16; ++r) {
-    const int k = q * 16 + r;
+  for (int r = 0; r < RU; ++r) {
+    const int k = q * RU + r;
     d2 v = d2{0.0, 0.0};
     if (k < K && G < n_pad) {
       v = X[(int64_t)k * n_pad + G];
@@ -130,14 +145,15 @@ __global__ void __launch_bounds__(256) k_crt_residues(CrtConsts cc, const d2* __
     const double m = (double)cc.m[i], inv_m = 1.0 / m, jm = (double)cc.j[i];
     u4 u0 = u4{0u, 0u, 0u, 0u}, u1 = u4{0u, 0u, 0u, 0u};
 #pragma unroll
-    for (int r = 0; r < 16; ++r) {
+    for (int r = 0; r < RU; ++r) {
       // c = x_i mod m; x_r + j c (exact: |x_r| < 2^48, |j c| < 2^15) mod m; then
       // x_r - j c = (x_r + j c) - 2 j c from small values (|.| < 2^16)
       const double c = smod_d(im[r], m, inv_m);
       const double p0 = smod_d(fma(jm, c, re[r]), m, inv_m);
       const double p1 = smod_d(fma(-2.0 * jm, c, p0), m, inv_m);
-      u0[r >> 2] |= ((unsigned)(int)p0 & 0xffu) << (8 * (r & 3));
-      u1[r >> 2] |= ((unsigned)(int)p1 & 0xffu) << (8 * (r & 3));
+      constexpr int PER = 4 / EB;  // elements per 32-bit word
+      u0[r / PER] |= residue_bits<EK>(p0) << (8 * EB * (r % PER));
+      u1[r / PER] |= residue_bits<EK>(p1) << (8 * EB * (r % PER));
     }
     o[i * modstride] = u0;
     o[i * modstride + 256] = u1;
@@ -146,6 +162,42 @@ __global__ void __launch_bounds__(256) k_crt_residues(CrtConsts cc, const d2* __
 
 __device__ __forceinline__ i16v mfma_i8(u4 a, u4 b, i16v c) {
   return __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(i4v, a), __builtin_bit_cast(i4v, b), c, 0, 0, 0);
+}
+
+// One 32 x 32 residue MFMA over a unit of K: 32 rows of bytes into int32 sums (EK 0), or 16 rows
+// of bfloat16 (1) or half (2) values into FP32 sums, exact for integers below 2^24.
+template <int EK>
+struct CrtAcc;
+template <>
+struct CrtAcc<0> {
+  typedef i16v T;
+  static __device__ __forceinline__ T mma(u4 a, u4 b, T c) { return mfma_i8(a, b, c); }
+};
+template <>
+struct CrtAcc<1> {
+  typedef f32x16 T;
+  static __device__ __forceinline__ T mma(u4 a, u4 b, T c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a), __builtin_bit_cast(bf16x8, b), c,
+                                                   0, 0, 0);
+  }
+};
+template <>
+struct CrtAcc<2> {
+  typedef f32x16 T;
+  static __device__ __forceinline__ T mma(u4 a, u4 b, T c) {
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a), __builtin_bit_cast(f16x8, b), c,
+                                                  0, 0, 0);
+  }
+};
+
+// v mod m in [-(m-1)/2, (m-1)/2] for an integer-valued float |v| < 2^24: the quotient from FP32 is
+// off by at most one (|v/m| < 2^17.2, relative error 2^-22), q m and v - q m are exact.
+__device__ __forceinline__ float smod_f(float v, float m, float inv_m, float h) {
+  const float q = rintf(v * inv_m);
+  float r = fmaf(-q, m, v);
+  r = r > h ? r - m : r;
+  r = r < -h ? r + m : r;
+  return r;
 }
 
 // v mod m in [-(m-1)/2, (m-1)/2] for |v| < 2^30 (the quotient from FP64, one correction).
@@ -170,6 +222,9 @@ constexpr int kCrtSideUnits = 4 * 4 * 64;                 // 4 blocks of 64 colu
 constexpr int kCrtStageUnits = 2 * kCrtSideUnits;         // left, then right (32 KB)
 constexpr int kCrtCopies = kCrtStageUnits / 64;           // 1 KB copies per chunk (32)
 constexpr int kCrtWindow = 1024;  // chunks (65536 rows) between reductions of the int32 sums: 2^16 * 120^2 < 2^30
+// 16-bit elements: chunks of 32 rows; FP32 sums stay exact integers below 2^24 for 1024 rows
+// (2^10 * 120^2 + 120 < 2^24), so they are reduced modulo m every 32 chunks, in both layouts.
+constexpr int kCrtWindow16 = 32;
 // Chunks whose sums stay exact with no reduction at all: 2^17 rows * 120^2 < 2^31.  Reducing
 // 256 accumulators held in AGPRs costs the 4-wave form its registers, so it runs only up to
 // this many chunks and the 8-wave form takes longer stacked widths.
@@ -187,7 +242,7 @@ constexpr int vmcnt_only(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) 
 // of P and once with those of Q.
 // res: residues in [-(m-1)/2, (m-1)/2] as signed bytes, [n_mod][nprod][n_res][n_res] (the real
 // form: of Re), written for row <= col < n.
-template <int WAVES, bool REAL>
+template <int EK, int WAVES, bool REAL>
 __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__ L, const u4* __restrict__ R,
                                                           CrtConsts cc, int QK, int n, int NB, int nbs,
                                                           int num_tiles, int num_wg, int gr, int8_t* __restrict__ res,
@@ -241,7 +296,8 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
       __builtin_amdgcn_global_load_lds((const void*)(at(i, v) + lane), (lds_ptr)(&lds[buf][dst[i]]), 16, 0, 0);
   };
 
-  i16v acc[RB][4];
+  typedef CrtAcc<EK> Mma;
+  typename Mma::T acc[RB][4];
 #pragma unroll
   for (int a = 0; a < RB; ++a)
 #pragma unroll
@@ -251,13 +307,17 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
 
   const int m = cc.m[mod], hm = (m - 1) / 2;
   const double inv_m = 1.0 / (double)m;
+  const float mf = (float)m, inv_mf = 1.0f / mf, hmf = (float)hm;
   auto reduce = [&]() {
 #pragma unroll
     for (int a = 0; a < RB; ++a)
 #pragma unroll
       for (int b = 0; b < 4; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) acc[a][b][r] = smod_i(acc[a][b][r], m, inv_m, hm);
+        for (int r = 0; r < 16; ++r) {
+          if constexpr (EK == 0) acc[a][b][r] = smod_i(acc[a][b][r], m, inv_m, hm);
+          else acc[a][b][r] = smod_f(acc[a][b][r], mf, inv_mf, hmf);
+        }
   };
 
   const int qh = lane >> 5, g32 = lane & 31;
@@ -303,7 +363,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
-          acc[rb][cb] = mfma_i8(a[rb], b[cb], acc[rb][cb]);
+          acc[rb][cb] = Mma::mma(a[rb], b[cb], acc[rb][cb]);
           if ((cb & 1) && more && ci < NPW)
             __builtin_amdgcn_global_load_lds((const void*)(at(ci, c + kCrtStages - 1) + lane),
                                              (lds_ptr)(&lds[nbuf][dst[ci]]), 16, 0, 0);
@@ -313,9 +373,12 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
           }
         }
     }
-    // the 4-wave form runs only where no reduction is needed (at most kCrtNoReduce stages)
-    if constexpr (WAVES == 8)
+    // the 4-wave byte form runs only where no reduction is needed (at most kCrtNoReduce stages)
+    if constexpr (EK != 0) {
+      if ((c + 1) % kCrtWindow16 == 0) reduce();
+    } else if constexpr (WAVES == 8) {
       if ((c + 1) % kCrtWindow == 0) reduce();
+    }
   }
 
   // residues of the product; output element r of a 32 x 32 block: row 8 (r / 4) + 4 qh + r % 4, column g32
@@ -331,7 +394,7 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
         const int row = rbase + rb * 32 + 8 * (r >> 2) + (r & 3);
         const int col = cbase + cb * 32;
         if (row < n && col < n && col >= row) {
-          int v = smod_i(acc[rb][cb][r], m, inv_m, hm);
+          int v = smod_i((int)acc[rb][cb][r], m, inv_m, hm);  // 16-bit forms: an exact integer < 2^24
           if constexpr (REAL) v = smod_i(v * cc.inv2[mod], m, inv_m, hm);  // (P + Q) / 2
           out[(int64_t)row * ld + col] = (int8_t)v;
         }
@@ -472,16 +535,49 @@ hipError_t launch_crt_scales(const double2* W, const double2* Y, const double* l
   return hipGetLastError();
 }
 
-hipError_t launch_crt_residues(const CrtConsts& cc, const double2* X, const double* lam, int use_lam, int K, int n_pad,
-                               int n_res, int QK, const double* scale, void* out, hipStream_t s) {
+hipError_t launch_crt_residues(const CrtConsts& cc, int ek, const double2* X, const double* lam, int use_lam, int K,
+                               int n_pad, int n_res, int QK, const double* scale, void* out, hipStream_t s) {
   dim3 grid(n_res / 64, (QK + 3) / 4);
-  hipLaunchKernelGGL(k_crt_residues, grid, dim3(256), 0, s, cc, (const d2*)X, lam, use_lam, K, n_pad, n_res, QK, scale,
-                     (u4*)out);
+  if (ek == 0)
+    hipLaunchKernelGGL(k_crt_residues<0>, grid, dim3(256), 0, s, cc, (const d2*)X, lam, use_lam, K, n_pad, n_res, QK,
+                       scale, (u4*)out);
+  else if (ek == 1)
+    hipLaunchKernelGGL(k_crt_residues<1>, grid, dim3(256), 0, s, cc, (const d2*)X, lam, use_lam, K, n_pad, n_res, QK,
+                       scale, (u4*)out);
+  else
+    hipLaunchKernelGGL(k_crt_residues<2>, grid, dim3(256), 0, s, cc, (const d2*)X, lam, use_lam, K, n_pad, n_res, QK,
+                       scale, (u4*)out);
   return hipGetLastError();
 }
 
-hipError_t launch_hs_crt(const CrtConsts& cc, bool real, const void* L, const void* R, int QK, int n, int n_res,
-                         int gr, int waves, void* res, hipStream_t s) {
+namespace {
+template <int EK>
+void launch_hs_crt_k(bool real, bool four, dim3 grid, const u4* l, const u4* r, const CrtConsts& cc, int QK, int n,
+                     int NB, int nbs, int num_tiles, int num_wg, int gr, int8_t* o, int64_t ld, hipStream_t s) {
+  if constexpr (EK == 0) {
+    if (four) {
+      if (real)
+        hipLaunchKernelGGL((k_hs_crt<EK, 4, true>), grid, dim3(256), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles,
+                           num_wg, gr, o, ld);
+      else
+        hipLaunchKernelGGL((k_hs_crt<EK, 4, false>), grid, dim3(256), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles,
+                           num_wg, gr, o, ld);
+      return;
+    }
+  }
+  {
+    if (real)
+      hipLaunchKernelGGL((k_hs_crt<EK, 8, true>), grid, dim3(512), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg,
+                         gr, o, ld);
+    else
+      hipLaunchKernelGGL((k_hs_crt<EK, 8, false>), grid, dim3(512), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg,
+                         gr, o, ld);
+  }
+}
+}  // namespace
+
+hipError_t launch_hs_crt(const CrtConsts& cc, int ek, bool real, const void* L, const void* R, int QK, int n,
+                         int n_res, int gr, int waves, void* res, hipStream_t s) {
   const int nbs = n_res / 256;
   const int num_tiles = crt_tiles(n_res);
   const int num_wg = num_tiles * cc.n_mod * (real ? 1 : 2);
@@ -490,21 +586,13 @@ hipError_t launch_hs_crt(const CrtConsts& cc, bool real, const void* L, const vo
   const u4 *l = (const u4*)L, *r = (const u4*)R;
   int8_t* o = (int8_t*)res;
   const int64_t ld = n_res;
-  if (waves == 4 && QK / 4 * (real ? 2 : 1) <= kCrtNoReduce) {
-    if (real)
-      hipLaunchKernelGGL((k_hs_crt<4, true>), grid, dim3(256), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr,
-                         o, ld);
-    else
-      hipLaunchKernelGGL((k_hs_crt<4, false>), grid, dim3(256), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr,
-                         o, ld);
-  } else {
-    if (real)
-      hipLaunchKernelGGL((k_hs_crt<8, true>), grid, dim3(512), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr,
-                         o, ld);
-    else
-      hipLaunchKernelGGL((k_hs_crt<8, false>), grid, dim3(512), 0, s, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr,
-                         o, ld);
-  }
+  // The byte form's 4-wave layout has no reduction of its sums: it runs up to kCrtNoReduce stages.
+  // The 16-bit forms reduce their FP32 sums every 32 chunks, which the 4-wave layout, its 256
+  // sums in AGPRs, could only do by spilling inside the loop: they run the 8-wave layout.
+  const bool four = waves == 4 && ek == 0 && QK / 4 * (real ? 2 : 1) <= kCrtNoReduce;
+  if (ek == 0) launch_hs_crt_k<0>(real, four, grid, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr, o, ld, s);
+  else if (ek == 1) launch_hs_crt_k<1>(real, four, grid, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr, o, ld, s);
+  else launch_hs_crt_k<2>(real, four, grid, l, r, cc, QK, n, NB, nbs, num_tiles, num_wg, gr, o, ld, s);
   return hipGetLastError();
 }
 

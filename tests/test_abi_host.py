@@ -92,16 +92,18 @@ def test_create_rejects_split_slice_count(precision, n_slices):
     assert "n_slices" in N.last_error(None)
 
 
+@pytest.mark.parametrize("precision", [N.HSB_SPLIT_CRT, N.HSB_SPLIT_CRT_BF16, N.HSB_SPLIT_CRT_FP16])
 @pytest.mark.parametrize("n_moduli", [0, 6, 7, 14, 15, 24])
-def test_create_rejects_residue_moduli_count(n_moduli):
-    """The residue form takes 8..13 moduli (checked before any device call)."""
-    cfg, keep = _config(precision=N.HSB_SPLIT_CRT, n_slices=n_moduli)
+def test_create_rejects_residue_moduli_count(precision, n_moduli):
+    """The residue forms take 8..13 moduli (checked before any device call)."""
+    cfg, keep = _config(precision=precision, n_slices=n_moduli)
     assert _create(cfg)[0] == N.HSB_ERR_ARG
     assert "moduli" in N.last_error(None)
 
 
-def test_create_rejects_unknown_precision():
-    cfg, keep = _config(precision=N.HSB_SPLIT_CRT + 1, n_slices=5)
+@pytest.mark.parametrize("precision", [N.HSB_SPLIT_CRT_FP16 + 1, -1, 99])
+def test_create_rejects_unknown_precision(precision):
+    cfg, keep = _config(precision=precision, n_slices=5)
     assert _create(cfg)[0] == N.HSB_ERR_ARG
     assert "precision" in N.last_error(None)
 

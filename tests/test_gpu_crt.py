@@ -42,11 +42,11 @@ def rel(a, b):
     return float(np.linalg.norm(a - b) / np.linalg.norm(b))
 
 
-def _crt(case, n_mod=N_MOD, poison=True, waves=None):
+def _crt(case, n_mod=N_MOD, poison=True, waves=None, precision=None):
     from paper_1712_07206_amd import HSB_SPLIT_CRT
     from paper_1712_07206_amd import _native as N
     from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
-    b = HSBuilder.from_case(case, precision=HSB_SPLIT_CRT, n_slices=n_mod)
+    b = HSBuilder.from_case(case, precision=HSB_SPLIT_CRT if precision is None else precision, n_slices=n_mod)
     if waves is not None:
         b.set_option(N.HSB_OPT_HS_WAVES, waves)
     g, tau, T = case_tensors(case)
@@ -185,11 +185,11 @@ def test_crt_past_the_reduction_window(waves):
     assert eh <= TOL_SPLIT and es <= TOL_SPLIT
 
 
-def _real_crt(case, poison=True, waves=None):
+def _real_crt(case, poison=True, waves=None, precision=None):
     from paper_1712_07206_amd import HSB_SPLIT_CRT
     from paper_1712_07206_amd import _native as N
     from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
-    b = HSBuilder.from_case(case, precision=HSB_SPLIT_CRT, n_slices=N_MOD)
+    b = HSBuilder.from_case(case, precision=HSB_SPLIT_CRT if precision is None else precision, n_slices=N_MOD)
     if waves is not None:
         b.set_option(N.HSB_OPT_HS_WAVES, waves)
     g, tau, T = case_tensors(case)
@@ -259,3 +259,53 @@ def test_crt_stacked_widths_shorter_than_the_copy_ring(waves):
     es = rel(np.triu(S) + np.triu(S, 1).T, Sr.real)
     print("real residue form (%d waves), five-atom cell: H %.3e S %.3e" % (waves, eh, es))
     assert eh <= TOL_SPLIT and es <= TOL_SPLIT
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp16"])
+@pytest.mark.parametrize("idx,n_g", [(0, None), (1, 129), (1, 1000), (8, None), (2, 3000)])
+def test_crt_16bit_forms_bitwise_equal_to_byte_form(kind, idx, n_g):
+    """The residues as bfloat16 or half integers on the 16-bit matrix cores, FP32 sums reduced
+    modulo m every 1024 stacked rows (the 16-atom cell has 2592, the bench cell at N_G 3000
+    30976): the residues are the same integers, so H and S equal the byte form's bitwise,
+    and the oracle's bar holds."""
+    from paper_1712_07206_amd import HSB_SPLIT_CRT_BF16, HSB_SPLIT_CRT_FP16
+    prec = HSB_SPLIT_CRT_BF16 if kind == "bf16" else HSB_SPLIT_CRT_FP16
+    case, (Hr, Sr) = oracle(idx, n_g)
+    H8, S8 = _crt(case)
+    H, S = _crt(case, precision=prec)
+    n = case["n_g"]
+    iu, il = np.triu_indices(n), np.tril_indices(n, -1)
+    assert np.all(np.isnan(H[il])) and np.all(np.isnan(S[il])), "strict lower triangle was written"
+    assert np.array_equal(H[iu], H8[iu]) and np.array_equal(S[iu], S8[iu])
+    eh, es = rel(_full(H), Hr), rel(_full(S), Sr)
+    print("residue form (%s) idx %d N_G %d: rel err H %.3e S %.3e" % (kind, idx, n, eh, es))
+    assert eh <= TOL_SPLIT and es <= TOL_SPLIT
+
+
+@pytest.mark.parametrize("kind", ["bf16", "fp16"])
+def test_real_crt_16bit_forms_bitwise_equal_to_byte_form(kind):
+    """Real-symmetric form (both products in one FP32 sum, two stages per chunk) at N_G 300
+    and on the full inversion-symmetric cell at N_G 3000."""
+    from paper_1712_07206_amd import HSB_SPLIT_CRT_BF16, HSB_SPLIT_CRT_FP16
+    prec = HSB_SPLIT_CRT_BF16 if kind == "bf16" else HSB_SPLIT_CRT_FP16
+    for idx, n_g in ((5, 300), (6, 3000)):
+        case, (Hr, Sr) = oracle(idx, n_g)
+        H8, S8 = _real_crt(case)
+        H, S = _real_crt(case, precision=prec)
+        iu = np.triu_indices(case["n_g"])
+        assert np.array_equal(H[iu], H8[iu]) and np.array_equal(S[iu], S8[iu])
+        eh = rel(np.triu(H) + np.triu(H, 1).T, Hr.real)
+        es = rel(np.triu(S) + np.triu(S, 1).T, Sr.real)
+        print("real residue form (%s) idx %d N_G %d: H %.3e S %.3e" % (kind, idx, case["n_g"], eh, es))
+        assert eh <= TOL_SPLIT and es <= TOL_SPLIT
+
+
+def test_crt_16bit_past_the_reduction_window():
+    """69696 stacked rows: the FP32 sums are reduced modulo m 68 times; bitwise equal to the
+    byte form."""
+    from paper_1712_07206_amd import HSB_SPLIT_CRT_BF16
+    case = _wide_case(96, 40)
+    H8, S8 = _crt(case)
+    H, S = _crt(case, precision=HSB_SPLIT_CRT_BF16)
+    iu = np.triu_indices(case["n_g"])
+    assert np.array_equal(H[iu], H8[iu]) and np.array_equal(S[iu], S8[iu])
