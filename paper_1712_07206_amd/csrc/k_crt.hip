@@ -1,5 +1,6 @@
-// Split-precision contraction by residues (Chinese remainder theorem) on the int8
-// matrix cores: the residue form of the split path.
+// Split-precision contraction by residues (Chinese remainder theorem) on the int8 matrix
+// cores, or on the BF16/FP16 matrix cores with the residues as 16-bit integers: the residue
+// forms of the split path.
 //
 // Every operand column (one G: the vector over the stacked index k) is scaled by a
 // power of two 2^f_G and rounded to Gaussian integers x' = rint(2^f x) (exact in
@@ -14,20 +15,22 @@
 //     P = sum_k (a_r - j a_i)_k (b_r + j b_i)_k,   Q = sum_k (a_r + j a_i)_k (b_r - j b_i)_k,
 //     Re = (P + Q) / 2,   Im = (P - Q) / (2j)      (mod m),
 // with the residues stored as signed bytes in [-(m-1)/2, (m-1)/2] and P, Q exact int32
-// sums on v_mfma_i32_32x32x32_i8.  The column scaling keeps |Re|, |Im| of the integer
+// sums on v_mfma_i32_32x32x32_i8 (or as bfloat16/half integers with FP32 sums on
+// v_mfma_f32_32x32x16_{bf16,f16}, exact below 2^24 and reduced modulo m every 1024 rows, so
+// the residues, and H and S, are the same).  The column scaling keeps |Re|, |Im| of the integer
 // product below M/2 (M = prod m_i) by Cauchy-Schwarz, so the residues fix it uniquely;
 // it is recovered in FP64 as M * frac(sum_i r_i y_i / m_i), y_i = (M/m_i)^{-1} mod m_i,
 // with y_i / m_i split into a part on a 2^-42 grid (whose weighted sum is exact) and a
 // small remainder.  The only approximation is the rounding of the scaled operands to
 // integers; at 11 moduli that keeps 40 bits of each column's 2-norm.
 //
-// Residue layout (16-byte units of 16 consecutive k, one byte each), chunk-major so that
-// the bytes one contraction tile copies for a 64-row chunk are two contiguous runs:
+// Residue layout: 16-byte units of RU consecutive k (RU = 16 bytes, or 8 16-bit elements),
+// chunk-major, a chunk being 4 units (64 rows of bytes, 32 of 16-bit elements):
 // unit i * 2 NB QK * 64 + (((c * NB + b) * 2 + p) * 4 + qq) * 64 + g holds, for modulus i,
 // plane p (0: x_r + j_i x_i, 1: x_r - j_i x_i), column G = 64 b + g and rows
-// k = 64 c + 16 qq .. 64 c + 16 qq + 15; NB = n_res / 64, QK = 4 * (number of chunks), with
-// the columns padded to n_res (a multiple of 256) and the rows to a multiple of 64, the
-// pads zero.
+// k = RU (4 c + qq) .. RU (4 c + qq) + RU - 1; NB = n_res / 64, QK = 4 * (number of chunks),
+// with the columns padded to n_res (a multiple of 256) and the rows to a multiple of 64, the
+// pads zero.  A 256-column block of one plane is then four 4 KB runs per chunk.
 #include <cmath>
 
 #include "hs_internal.h"
@@ -210,8 +213,8 @@ __device__ __forceinline__ int smod_i(int v, int m, double inv_m, int h) {
 }
 
 // Contraction tile: one product (P, Q, or the real product) over a 256 x 256 block of
-// (G', G) per workgroup, so each side needs one residue plane: a 64-row chunk of the stacked
-// index is 16 KB of left and 16 KB of right residues, copied straight into LDS
+// (G', G) per workgroup, so each side needs one residue plane: a chunk of the stacked index
+// is 16 KB of left and 16 KB of right residues, copied straight into LDS
 // (global_load_lds_dwordx4) through a ring of four 32 KB stages, three chunks ahead of its use.
 // (Computing P and Q together on a 256 x 128 tile takes the same registers and MFMAs but copies
 // 48 KB per chunk: both planes of both sides.)  WAVES = 8: waves of 64 x 128 (2 x 4 blocks of
@@ -223,11 +226,12 @@ constexpr int kCrtStageUnits = 2 * kCrtSideUnits;         // left, then right (3
 constexpr int kCrtCopies = kCrtStageUnits / 64;           // 1 KB copies per chunk (32)
 constexpr int kCrtWindow = 1024;  // chunks (65536 rows) between reductions of the int32 sums: 2^16 * 120^2 < 2^30
 // 16-bit elements: chunks of 32 rows; FP32 sums stay exact integers below 2^24 for 1024 rows
-// (2^10 * 120^2 + 120 < 2^24), so they are reduced modulo m every 32 chunks, in both layouts.
+// (2^10 * 120^2 + 120 < 2^24), so they are reduced modulo m every 32 chunks (8-wave layout).
 constexpr int kCrtWindow16 = 32;
-// Chunks whose sums stay exact with no reduction at all: 2^17 rows * 120^2 < 2^31.  Reducing
-// 256 accumulators held in AGPRs costs the 4-wave form its registers, so it runs only up to
-// this many chunks and the 8-wave form takes longer stacked widths.
+// Byte form: chunks whose sums stay exact with no reduction at all: 2^17 rows * 120^2 < 2^31.
+// Reducing 256 accumulators held in AGPRs inside the loop makes the 4-wave layout spill, so it
+// has no reduction, runs only up to this many chunks and the 8-wave layout takes longer
+// stacked widths (and the 16-bit forms, which reduce every 32 chunks).
 constexpr int kCrtNoReduce = 2048;
 
 // s_waitcnt immediates (gfx9 encoding): vector-memory count N, the other counters not waited on.
