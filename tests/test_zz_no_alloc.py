@@ -4,9 +4,11 @@ hsbuild_forward with a caller workspace, through the C-ABI.
 Two calls in a row on one handle, the second with a smaller basis, so the
 second runs in a scratch that still holds the first call's data: each must
 equal hsbuild_forward's result bitwise (same kernels, same inputs) and the
-oracle to the FP64 bar (relative Frobenius error <= 1e-12; the int8 split
-form to <= 1e-10), with the strict lower triangle untouched.  A problem
-larger than the static scratch is refused before anything is enqueued.
+oracle to the FP64 bar (relative Frobenius error <= 1e-12; the int8 slice
+and the residue forms to <= 1e-10), with the strict lower triangle untouched.
+The residue forms take more workspace per basis function, so they run at
+bases that fit the scratch.  A problem larger than the static scratch is
+refused before anything is enqueued.
 """
 import ctypes
 
@@ -19,7 +21,7 @@ from oracle import hs_oracle as o
 
 pytestmark = pytest.mark.gpu
 
-TOL = {0: 1e-12, 3: 1e-10}  # HSB_FP64, HSB_SPLIT_INT8
+TOL = {0: 1e-12, 3: 1e-10, 4: 1e-10, 5: 1e-10}  # HSB_FP64, HSB_SPLIT_INT8, HSB_SPLIT_CRT, HSB_SPLIT_CRT_BF16
 
 
 @pytest.fixture(scope="module", autouse=True)
@@ -43,11 +45,12 @@ def _poisoned(n):
     return torch.full((n, n), complex(float("nan"), float("nan")), dtype=torch.complex128, device="cuda")
 
 
-@pytest.mark.parametrize("precision,n_slices", [(0, 0), (3, 6)])
-def test_static_forward_matches_forward_twice(precision, n_slices):
+@pytest.mark.parametrize("precision,n_slices,sizes", [(0, 0, (1000, 300)), (3, 6, (1000, 300)), (4, 11, (600, 300)),
+                                                      (5, 11, (400, 200))])
+def test_static_forward_matches_forward_twice(precision, n_slices, sizes):
     from paper_1712_07206_amd import _native as N
     from paper_1712_07206_amd.hsbuild import HSBuilder, case_tensors
-    sizes = (1000, 300)  # second call smaller: a scratch left dirty by the first
+    # sizes: the second call smaller, in a scratch left dirty by the first
     b = HSBuilder.from_case(make_case(1, n_g=sizes[0]), max_ng=sizes[0], precision=precision, n_slices=n_slices)
     for n_g in sizes:
         case = make_case(1, n_g=n_g)
