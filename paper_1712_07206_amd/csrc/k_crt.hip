@@ -111,7 +111,8 @@ template <int EK>
 __device__ __forceinline__ unsigned residue_bits(double r) {
   if constexpr (EK == 0) return (unsigned)(int)r & 0xffu;
   else if constexpr (EK == 1) return (unsigned)__builtin_bit_cast(unsigned short, (__bf16)(float)r);
-  else return (unsigned)__builtin_bit_cast(unsigned short, (_Float16)(float)r);
+  // through int and float (both exact here): a direct double -> half cast is rounded in software
+  else return (unsigned)__builtin_bit_cast(unsigned short, (_Float16)(float)(int)r);
 }
 
 // One thread per (column G, unit q of RU = 16 (bytes) or 8 (16-bit elements) rows): the 2 n_mod
