@@ -300,12 +300,27 @@ def test_real_crt_16bit_forms_bitwise_equal_to_byte_form(kind):
         assert eh <= TOL_SPLIT and es <= TOL_SPLIT
 
 
-def test_crt_16bit_past_the_reduction_window():
+@pytest.mark.parametrize("kind", ["bf16", "fp16"])
+def test_crt_16bit_past_the_reduction_window(kind):
     """69696 stacked rows: the FP32 sums are reduced modulo m 68 times; bitwise equal to the
-    byte form."""
-    from paper_1712_07206_amd import HSB_SPLIT_CRT_BF16
+    byte form.  The 16-bit forms have the 8-wave layout only: asking for 4 waves runs it too."""
+    from paper_1712_07206_amd import HSB_SPLIT_CRT_BF16, HSB_SPLIT_CRT_FP16
+    prec = HSB_SPLIT_CRT_BF16 if kind == "bf16" else HSB_SPLIT_CRT_FP16
     case = _wide_case(96, 40)
     H8, S8 = _crt(case)
-    H, S = _crt(case, precision=HSB_SPLIT_CRT_BF16)
     iu = np.triu_indices(case["n_g"])
-    assert np.array_equal(H[iu], H8[iu]) and np.array_equal(S[iu], S8[iu])
+    for waves in (None, 4):
+        H, S = _crt(case, precision=prec, waves=waves)
+        assert np.array_equal(H[iu], H8[iu]) and np.array_equal(S[iu], S8[iu]), waves
+
+
+def test_crt_default_layouts():
+    """Defaults: the byte form takes the 4-wave layout, the 16-bit forms the 8-wave one; tile
+    group 4 for all."""
+    from paper_1712_07206_amd import HSB_SPLIT_CRT, HSB_SPLIT_CRT_BF16, HSB_SPLIT_CRT_FP16
+    from paper_1712_07206_amd import _native as N
+    from paper_1712_07206_amd.hsbuild import HSBuilder
+    for prec, waves in ((HSB_SPLIT_CRT, 4), (HSB_SPLIT_CRT_BF16, 8), (HSB_SPLIT_CRT_FP16, 8)):
+        b = HSBuilder.from_case(make_case(0), precision=prec, n_slices=N_MOD)
+        assert b.get_option(N.HSB_OPT_HS_WAVES) == waves and b.get_option(N.HSB_OPT_TILE_GROUP) == 4
+        b.close()
