@@ -224,14 +224,15 @@ def test_batch_small_uneven_bases_against_oracle():
         assert np.array_equal(hb[iu], h1.cpu().numpy()[iu]) and np.array_equal(sb[iu], s1.cpu().numpy()[iu]), k
 
 
-@pytest.mark.parametrize("prec_name", ["int8", "bf16"])
+@pytest.mark.parametrize("prec_name", ["int8", "bf16", "crt", "crt_fp16"])
 def test_batch_rejects_split_precision(prec_name):
     """The batch entry point runs the FP64 contraction only: a handle created
     with a split precision gets HSB_ERR_UNSUPPORTED, checked on the host before
     anything is enqueued, and the outputs stay untouched."""
     from paper_1712_07206_amd import _native as N
     from paper_1712_07206_amd.hsbuild import HSBuilder
-    prec, slices = (N.HSB_SPLIT_INT8, 6) if prec_name == "int8" else (N.HSB_SPLIT_BF16, 5)
+    prec, slices = {"int8": (N.HSB_SPLIT_INT8, 6), "bf16": (N.HSB_SPLIT_BF16, 5),
+                    "crt": (N.HSB_SPLIT_CRT, 11), "crt_fp16": (N.HSB_SPLIT_CRT_FP16, 11)}[prec_name]
     case = make_batch_case(3, n_k=2)
     sizes = [37, 64]
     case["g"] = [np.ascontiguousarray(case["g"][k][:sizes[k]]) for k in range(2)]
