@@ -354,26 +354,35 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
     const int nbuf = (c + kCrtStages - 1) % kCrtStages;
     const u4* B = lds[c % kCrtStages];
     int ci = 0;
-#pragma unroll
-    for (int s = 0; s < 2; ++s) {
-      u4 a[RB], b[4];
+    u4 a[2][RB], b[2][4];
+    auto read_step = [&](int s) {
 #pragma unroll
       for (int t = 0; t < RB; ++t) {
         const int rbb = RB * wr + t;
-        a[t] = B[la + ((rbb >> 1) * 4 + 2 * s) * 64 + (rbb & 1) * 32];
+        a[s][t] = B[la + ((rbb >> 1) * 4 + 2 * s) * 64 + (rbb & 1) * 32];
       }
 #pragma unroll
-      for (int t = 0; t < 4; ++t) b[t] = B[ra + ((t >> 1) * 4 + 2 * s) * 64 + (t & 1) * 32];
+      for (int t = 0; t < 4; ++t) b[s][t] = B[ra + ((t >> 1) * 4 + 2 * s) * 64 + (t & 1) * 32];
+    };
+    read_step(0);
+#pragma unroll
+    for (int s = 0; s < 2; ++s) {
 #pragma unroll
       for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
-          acc[rb][cb] = Mma::mma(a[rb], b[cb], acc[rb][cb]);
+          acc[rb][cb] = Mma::mma(a[s][rb], b[s][cb], acc[rb][cb]);
           if ((cb & 1) && more && ci < NPW)
             __builtin_amdgcn_global_load_lds((const void*)(at(ci, c + kCrtStages - 1) + lane),
                                              (lds_ptr)(&lds[nbuf][dst[ci]]), 16, 0, 0);
           if (cb & 1) {
             ++ci;
+            __builtin_amdgcn_sched_barrier(0);
+          }
+          // the second step's operands are read halfway through the first step's MFMAs, so
+          // their LDS latency is hidden behind the rest of them
+          if (s == 0 && rb * 4 + cb == 2 * RB - 1) {
+            read_step(1);
             __builtin_amdgcn_sched_barrier(0);
           }
         }
