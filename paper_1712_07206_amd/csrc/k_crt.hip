@@ -355,16 +355,23 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
     const u4* B = lds[c % kCrtStages];
     int ci = 0;
     u4 a[2][RB], b[2][4];
-    auto read_step = [&](int s) {
+    auto read_a = [&](int s, int t0, int t1) {
 #pragma unroll
-      for (int t = 0; t < RB; ++t) {
+      for (int t = t0; t < t1; ++t) {
         const int rbb = RB * wr + t;
         a[s][t] = B[la + ((rbb >> 1) * 4 + 2 * s) * 64 + (rbb & 1) * 32];
       }
+    };
+    auto read_b = [&](int s) {
 #pragma unroll
       for (int t = 0; t < 4; ++t) b[s][t] = B[ra + ((t >> 1) * 4 + 2 * s) * 64 + (t & 1) * 32];
     };
-    read_step(0);
+    // With one wave per SIMD (4 waves) the chunk's first MFMA waits only for the operands of
+    // row block 0 (5 reads), and the other row blocks' are read right after it; with two waves
+    // per SIMD the other wave covers that wait, and all 8 are read at once.
+    read_a(0, 0, WAVES == 4 ? 1 : RB);
+    read_b(0);
+    if constexpr (WAVES == 4) __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int s = 0; s < 2; ++s) {
 #pragma unroll
@@ -372,6 +379,12 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
 #pragma unroll
         for (int cb = 0; cb < 4; ++cb) {
           acc[rb][cb] = Mma::mma(a[s][rb], b[s][cb], acc[rb][cb]);
+          if constexpr (WAVES == 4) {
+            if (s == 0 && rb == 0 && cb == 0) {
+              read_a(0, 1, RB);
+              __builtin_amdgcn_sched_barrier(0);
+            }
+          }
           if ((cb & 1) && more && ci < NPW)
             __builtin_amdgcn_global_load_lds((const void*)(at(ci, c + kCrtStages - 1) + lane),
                                              (lds_ptr)(&lds[nbuf][dst[ci]]), 16, 0, 0);
@@ -382,7 +395,8 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
           // the second step's operands are read halfway through the first step's MFMAs, so
           // their LDS latency is hidden behind the rest of them
           if (s == 0 && rb * 4 + cb == 2 * RB - 1) {
-            read_step(1);
+            read_a(1, 0, RB);
+            read_b(1);
             __builtin_amdgcn_sched_barrier(0);
           }
         }
