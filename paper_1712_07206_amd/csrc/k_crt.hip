@@ -246,7 +246,8 @@ constexpr int vmcnt_only(int n) { return (n & 15) | ((n >> 4) << 14) | (7 << 4) 
 // products into one sum, running through 2 x (chunks) stages, each chunk once with the planes
 // of P and once with those of Q.
 // res: residues in [-(m-1)/2, (m-1)/2] as signed bytes, [n_mod][nprod][n_res][n_res] (the real
-// form: of Re), written for row <= col < n.
+// form: of Re), written for row <= col < n (the 4-wave layout writes the whole of each 256 x 256
+// block it computes, inside the plane).
 template <int EK, int WAVES, bool REAL>
 __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__ L, const u4* __restrict__ R,
                                                           CrtConsts cc, int QK, int n, int NB, int nbs,
@@ -409,24 +410,59 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
     }
   }
 
-  // residues of the product; output element r of a 32 x 32 block: row 8 (r / 4) + 4 qh + r % 4, column g32
-  int rbase = row0 + wr * 32 * RB + 4 * qh, cbase = col0 + wc * 128 + g32;
-  asm volatile("" : "+v"(rbase), "+v"(cbase));
-  int8_t* out = res + (int64_t)(mod * NPROD + prod) * ld * ld;
+  // Residues of the product (the real form: of (P + Q) / 2).  Output element r of a 32 x 32 block:
+  // row 8 (r / 4) + 4 qh + r % 4, column g32.
+  if constexpr (WAVES == 4) {
+    // Each sum is an exact integer below 2^31 in magnitude, reduced in FP64 as the residues of
+    // the operands are.  Every element of the block is written: the block lies inside the
+    // n_res x n_res plane, its rows and columns past n hold products of zero pads, and the
+    // recombination reads row <= col < n only.  The wave's base is made visibly uniform, so the
+    // per-element offsets are scalar arithmetic.
+    const double md = (double)m;
+    const double inv2 = REAL ? (double)cc.inv2[mod] : 0.0;
+    auto residue = [&](double v) -> int8_t {
+      double r = smod_d(v, md, inv_m);
+      if constexpr (REAL) r = smod_d(r * inv2, md, inv_m);  // (P + Q) / 2
+      return (int8_t)(int)r;
+    };
+    const uint64_t wb = (uint64_t)(res + (int64_t)(mod * NPROD + prod) * ld * ld +
+                                   (int64_t)(row0 + wr * 32 * RB) * ld + col0 + wc * 128);
+    // (readfirstlane returns a signed int: each half goes through unsigned, or the low one would
+    // sign-extend into the high word)
+    const unsigned wb_hi = (unsigned)__builtin_amdgcn_readfirstlane((unsigned)(wb >> 32));
+    const unsigned wb_lo = (unsigned)__builtin_amdgcn_readfirstlane((unsigned)wb);
+    typedef __attribute__((address_space(1))) int8_t gbyte;
+    gbyte* const ow = (gbyte*)(((uint64_t)wb_hi << 32) | (uint64_t)wb_lo);
+    const unsigned lane_off = (unsigned)(4 * qh) * (unsigned)ld + (unsigned)g32;
 #pragma unroll
-  for (int rb = 0; rb < RB; ++rb)
+    for (int rb = 0; rb < RB; ++rb)
 #pragma unroll
-    for (int cb = 0; cb < 4; ++cb)
+      for (int cb = 0; cb < 4; ++cb)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int row = rbase + rb * 32 + 8 * (r >> 2) + (r & 3);
-        const int col = cbase + cb * 32;
-        if (row < n && col < n && col >= row) {
-          int v = smod_i((int)acc[rb][cb][r], m, inv_m, hm);  // 16-bit forms: an exact integer < 2^24
-          if constexpr (REAL) v = smod_i(v * cc.inv2[mod], m, inv_m, hm);  // (P + Q) / 2
-          out[(int64_t)row * ld + col] = (int8_t)v;
+        for (int r = 0; r < 16; ++r)
+          ow[(int64_t)(rb * 32 + 8 * (r >> 2) + (r & 3)) * ld + cb * 32 + lane_off] = residue((double)acc[rb][cb][r]);
+  } else {
+    // (the 8-wave layout keeps per-element bounds: written this way, the 16-bit forms measured
+    // 5 % faster than with the 4-wave epilogue)
+    const int inv2 = REAL ? cc.inv2[mod] : 0;
+    int rbase = row0 + wr * 32 * RB + 4 * qh, cbase = col0 + wc * 128 + g32;
+    asm volatile("" : "+v"(rbase), "+v"(cbase));
+    int8_t* out = res + (int64_t)(mod * NPROD + prod) * ld * ld;
+#pragma unroll
+    for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int row = rbase + rb * 32 + 8 * (r >> 2) + (r & 3);
+          const int col = cbase + cb * 32;
+          if (row < n && col < n && col >= row) {
+            int v = smod_i((int)acc[rb][cb][r], m, inv_m, hm);  // 16-bit forms: an exact integer < 2^24
+            if constexpr (REAL) v = smod_i(v * inv2, m, inv_m, hm);  // (P + Q) / 2
+            out[(int64_t)row * ld + col] = (int8_t)v;
+          }
         }
-      }
+  }
 }
 
 // Recovery of each upper-triangle entry from its residues: per modulus Re = (P + Q) / 2 and
