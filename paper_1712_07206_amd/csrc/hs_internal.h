@@ -176,6 +176,10 @@ struct CrtConsts {
   int inv2j[kCrtMaxModuli];  // (2 j)^{-1} (mod m)
   double h[kCrtMaxModuli];   // y_i / m_i = h_i + l_i, y_i = (M / m_i)^{-1} (mod m_i), h_i on a 2^-42 grid
   double l[kCrtMaxModuli];
+  // the same split of (2^{-1} y_i mod m_i) / m_i and ((2 j)^{-1} y_i mod m_i) / m_i on a 2^-41 grid:
+  // the weights of P + Q and P - Q, whose residues need no reduction
+  double h_re[kCrtMaxModuli], l_re[kCrtMaxModuli];
+  double h_im[kCrtMaxModuli], l_im[kCrtMaxModuli];
   double M;                  // product of the moduli (rounded)
   double bound;              // largest 2-norm of a scaled integer column: bound^2 < M/2 (1 - 2^-10)
 };

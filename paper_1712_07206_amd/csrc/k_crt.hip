@@ -465,11 +465,14 @@ __global__ void __launch_bounds__(WAVES * 64, 1) k_hs_crt(const u4* __restrict__
   }
 }
 
-// Recovery of each upper-triangle entry from its residues: per modulus Re = (P + Q) / 2 and
-// Im = (P - Q) / (2 j) (mod m) (the real form: its one product), then
-// value = M * frac(sum_i r_i y_i / m_i), times 2^-(f_row + f_col).  sum r_i h_i is exact (h_i on a
-// 2^-42 grid, |r_i| < 2^7, n <= 13 terms), so the rounding to the nearest integer is exact and
-// the fraction keeps FP64 precision.  One thread per four consecutive columns of a row (4-byte
+// Recovery of each upper-triangle entry from its residues: value = M * frac(sum_i r_i y_i / m_i),
+// times 2^-(f_row + f_col), with r_i the residue of the real form's one product, or of
+// Re = (P + Q) / 2 and Im = (P - Q) / (2 j) (mod m).  The fraction depends on r_i only modulo m_i,
+// so the complex form takes r_i = P + Q and P - Q as they are (|r_i| <= 240) against the weights
+// 2^{-1} y_i and (2 j)^{-1} y_i (mod m_i), with no reduction.  sum r_i h_i is exact (h_i on a
+// 2^-42 grid with |r_i| < 2^7, or on a 2^-41 grid with |r_i| < 2^8; n <= 13 terms, so the sums
+// stay below 2^12), the rounding to the nearest integer is exact and the fraction keeps FP64
+// precision.  One thread per four consecutive columns of a row (4-byte
 // loads of the residues; the rows are n_res bytes long, so the four are always in the row).
 template <bool REAL>
 __global__ void __launch_bounds__(256) k_crt_combine(CrtConsts cc, const int8_t* __restrict__ res, int64_t ld,
@@ -482,8 +485,8 @@ __global__ void __launch_bounds__(256) k_crt_combine(CrtConsts cc, const int8_t*
   double hr[4] = {0.0, 0.0, 0.0, 0.0}, lr[4] = {0.0, 0.0, 0.0, 0.0};
   double hi[4] = {0.0, 0.0, 0.0, 0.0}, li[4] = {0.0, 0.0, 0.0, 0.0};
   for (int i = 0; i < cc.n_mod; ++i) {
-    const double h = cc.h[i], l = cc.l[i];
     if constexpr (REAL) {
+      const double h = cc.h[i], l = cc.l[i];
       const unsigned v = *(const unsigned*)(res + i * mstride + e);
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
@@ -494,17 +497,15 @@ __global__ void __launch_bounds__(256) k_crt_combine(CrtConsts cc, const int8_t*
     } else {
       const unsigned vp = *(const unsigned*)(res + (2 * i) * mstride + e);
       const unsigned vq = *(const unsigned*)(res + (2 * i + 1) * mstride + e);
-      const int m = cc.m[i], hm = (m - 1) / 2;
-      const double inv_m = 1.0 / (double)m;
+      const double h_re = cc.h_re[i], l_re = cc.l_re[i], h_im = cc.h_im[i], l_im = cc.l_im[i];
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         const int p = (int8_t)(vp >> (8 * u)), q = (int8_t)(vq >> (8 * u));
-        const double r = (double)smod_i((p + q) * cc.inv2[i], m, inv_m, hm);
-        const double t = (double)smod_i((p - q) * cc.inv2j[i], m, inv_m, hm);
-        hr[u] += r * h;
-        lr[u] += r * l;
-        hi[u] += t * h;
-        li[u] += t * l;
+        const double r = (double)(p + q), t = (double)(p - q);
+        hr[u] += r * h_re;
+        lr[u] += r * l_re;
+        hi[u] += t * h_im;
+        li[u] += t * l_im;
       }
     }
   }
@@ -571,9 +572,15 @@ bool crt_make_consts(int n_mod, CrtConsts* cc) {
     for (int t = 0; t < n_mod; ++t)
       if (t != i) c = c * (cc->m[t] % mi) % mi;
     const int y = inverse_mod(c, mi);
-    const double hh = std::ldexp(std::rint(std::ldexp((double)y / mi, 42)), -42);
-    cc->h[i] = hh;
-    cc->l[i] = ((double)y - hh * mi) / mi;  // y - h m_i is exact: h has 42 fractional bits, m_i 8 bits
+    // w / m_i = h + l with h on a 2^-bits grid; w - h m_i is exact (h has at most 42 fractional
+    // bits, m_i 8 bits)
+    auto split = [mi](int w, int bits, double& h, double& l) {
+      h = std::ldexp(std::rint(std::ldexp((double)w / mi, bits)), -bits);
+      l = ((double)w - h * mi) / mi;
+    };
+    split(y, 42, cc->h[i], cc->l[i]);
+    split(cc->inv2[i] * y % mi, 41, cc->h_re[i], cc->l_re[i]);
+    split(cc->inv2j[i] * y % mi, 41, cc->h_im[i], cc->l_im[i]);
   }
   cc->M = M;
   cc->bound = std::sqrt(0.5 * M * (1.0 - 0x1p-10));
