@@ -421,7 +421,9 @@ def small_leg(args) -> dict:
     reps = max(10, 4 * args.steps)
     out = {"workload": case["name"], "n_g": n, "k_c": k_c, "flops_per_step": flops,
            "algorithmic_flops_per_launch": flops_exec}
-    for mode, key in ((1, "split_k_auto"), (0, "one_pass")):
+    # auto: the stream-K contraction (equal shares of (tile, chunk) units per workgroup); 2: the
+    # stacked index in two segments; 0: one pass
+    for mode, key in ((1, "split_k_auto"), (2, "segments_2"), (0, "one_pass")):
         b.set_option(N.HSB_OPT_SPLIT_K, mode)
         wsb = b.workspace_bytes(N.HSB_MODE_FORWARD, [n])
         ws = torch.empty(wsb, dtype=torch.uint8, device="cuda")
@@ -447,11 +449,12 @@ def small_leg(args) -> dict:
         out[key] = {"ms_per_step": round(ms, 4), "tflops": round(flops / (ms * 1e-3) / 1e12, 4),
                     "stages_ms": {"coefficients": round(st[0], 4), "t_products": round(st[1], 4),
                                   "hs_contraction": round(st[2], 4), "segment_sum": round(st[3], 4)},
-                    "roofline": {"kernel": "k_hs_fp64_sk" if mode else "k_hs_fp64", "bound": "mfma",
+                    "roofline": {"kernel": {1: "k_hs_fp64_stream", 2: "k_hs_fp64_sk", 0: "k_hs_fp64"}[mode],
+                                 "bound": "mfma",
                                  "achieved": round(achieved, 4), "peak": FP64_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
                                  "frac": round(achieved / FP64_MFMA_PEAK_TFLOPS, 4)}}
         log("N_G 3000 cell (%s): %.3f ms per forward, contraction %.3f ms = %.1f TFLOP/s executed (%.3f of peak), "
-            "segment sum %.3f ms" % (key, ms, st[2], achieved, achieved / FP64_MFMA_PEAK_TFLOPS, st[3]))
+            "partial-tile sum %.3f ms" % (key, ms, st[2], achieved, achieved / FP64_MFMA_PEAK_TFLOPS, st[3]))
     b.close()
     torch.cuda.empty_cache()
     return out

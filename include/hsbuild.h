@@ -295,14 +295,18 @@ int hsbuild_stage_times(hsbuild_t h, double* ms_avg, int32_t* n_calls);
  * takes two stages per 64 rows), beyond which the 8-wave layout runs; the
  * 16-bit residue forms run the 8-wave layout only (their default is 8).  All
  * give bitwise the same H and S.
- * HSB_OPT_SPLIT_K: 1 (default) lets the 8-wave FP64 forward cut the stacked
- * index into segments when the upper triangle has fewer than 4 tiles per
- * compute unit (2..8 segments of at least 256 rows, chosen by a model of the
- * rounds of workgroups): partial tiles go to the workspace
- * (hsbuild_workspace_bytes includes them) and are added in a fixed order, so
- * small bases fill the GPU; the results agree with the one-pass contraction to
- * FP64 rounding, not bitwise, and repeat bitwise.  0 never splits; k = 2..8
- * always cuts k segments (fewer if the stacked index is too short).
+ * HSB_OPT_SPLIT_K: 1 (default) lets the 8-wave FP64 forward run in stream-K
+ * form when the upper triangle has fewer than 4 tiles per compute unit and a
+ * time model puts it ahead of one pass: the units (128 x 64 tile, 16 stacked
+ * rows) are dealt to at most one workgroup per compute unit in equal
+ * contiguous shares of at least 256 rows, in a fixed tile order, so small
+ * bases fill the GPU; tiles shared between workgroups are summed from their
+ * pieces in stacked-row order (the pieces live in the workspace, which
+ * hsbuild_workspace_bytes includes).
+ * The results agree with the one-pass contraction to FP64 rounding, not
+ * bitwise, and repeat bitwise on a device with the same compute-unit count.
+ * 0 never splits; k = 2..8 cuts the stacked index into k segments (fewer if
+ * it is too short), summed in order.
  * Setting HSB_OPT_TILE_GROUP or HSB_OPT_HS_WAVES drops a captured batch graph
  * (the batch contraction never splits). */
 enum { HSB_OPT_TILE_GROUP = 1, HSB_OPT_HS_WAVES = 2, HSB_OPT_SPLIT_K = 3 };

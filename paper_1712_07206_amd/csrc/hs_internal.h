@@ -52,7 +52,8 @@ struct Layout {
   size_t W = 0, Y = 0, ang = 0, ab = 0, kv = 0, lam = 0, consts = 0, end = 0;
   size_t WL = 0;  // lam W (the FP64 contraction's S operand), forward in FP64 only
   int ns = 1;              // FP64 forward: segments of the stacked index (split contraction when > 1)
-  size_t skH = 0, skS = 0;  // FP64 forward with ns > 1: partial H and S per segment
+  int nsh = 0;             // FP64 forward: workgroups of the stream-K contraction (0: not used)
+  size_t skH = 0, skS = 0;  // partial H and S: per segment (ns > 1), or the stream-K slots (nsh > 0)
   size_t PH = 0, PS = 0, partT = 0, partTau = 0;  // backward only
   size_t WT = 0, gHp = 0, gSp = 0;                // backward: operands of the 3M products
   size_t TT = 0;                                  // T^T per type, zero-padded (T products)
@@ -119,10 +120,21 @@ hipError_t launch_tprod3m(const CellArgs& c, const double2* TT, const double2* W
 hipError_t launch_hs_fp64(const double2* W, const double2* WL, const double2* Y, const double* lam, int K_pad, int n,
                           int n_pad, int gr, int waves, double2* H, double2* S, int64_t ldh, hipStream_t s);
 
-// Segments of the stacked index the 8-wave FP64 contraction is cut into (1: none) when the upper
-// triangle has fewer than 4 tiles per compute unit: the count (up to 8, segments of at least 256
-// rows) with the least rounds of workgroups times (rows per segment + 128).
-int hs_split_k(int n_pad, int K_pad, int num_cus);
+// Stream-K form of the 8-wave FP64 contraction, for an upper triangle of fewer than 4 tiles per
+// compute unit: the number of workgroups (shares, each of at least 256 stacked rows, at most one
+// per compute unit) when a time model puts it ahead of one pass, else 0.
+int hs_stream_shares(int n_pad, int K_pad, int num_cus);
+// Elements of each of its partial-tile buffers Hp, Sp: two 128 x 64 slots per share.
+size_t hs_stream_slot_elems(int nsh);
+// The (tile, 16-row chunk) units in nsh equal contiguous shares: whole tiles into H, S (ldh), the
+// pieces of tiles shared between workgroups into Hp, Sp; launch_stream_fixup adds each shared
+// tile's pieces in chunk order into H, S (upper triangle, row <= col < n).  The tiles are taken in
+// one fixed order, so the results do not depend on the tile-order option.
+hipError_t launch_hs_fp64_stream(const double2* W, const double2* WL, const double2* Y, int K_pad, int nsh, int n,
+                                 int n_pad, double2* H, double2* S, int64_t ldh, double2* Hp, double2* Sp,
+                                 hipStream_t s);
+hipError_t launch_stream_fixup(int K_pad, int nsh, int n, int n_pad, const double2* Hp, const double2* Sp,
+                               double2* H, double2* S, int64_t ldh, hipStream_t s);
 // Rows per segment (a multiple of the 16-row chunk; the last segment takes the rest).
 int hs_split_rows(int K_pad, int ns);
 // The 8-wave (3M) contraction in ns segments of the stacked index: partial tiles into Hp, Sp

@@ -168,8 +168,14 @@ Layout make_layout(const hsbuild_s& h, int ng, int mode) {
   }
   if ((mode == HSB_MODE_FORWARD || mode == HSB_MODE_REAL) && h.precision == HSB_FP64)
     L.WL = take((size_t)L.K_pad * np * sizeof(double2));
-  if (mode == HSB_MODE_FORWARD && h.precision == HSB_FP64 && h.hs_waves == 8 && h.split_k) {
-    L.ns = h.split_k == 1 ? hs_split_k(L.n_pad, L.K_pad, h.num_cus) : h.split_k;
+  if (mode == HSB_MODE_FORWARD && h.precision == HSB_FP64 && h.hs_waves == 8 && h.split_k == 1) {
+    L.nsh = hs_stream_shares(L.n_pad, L.K_pad, h.num_cus);
+    if (L.nsh > 0) {
+      L.skH = take(hs_stream_slot_elems(L.nsh) * sizeof(double2));
+      L.skS = take(hs_stream_slot_elems(L.nsh) * sizeof(double2));
+    }
+  } else if (mode == HSB_MODE_FORWARD && h.precision == HSB_FP64 && h.hs_waves == 8 && h.split_k > 1) {
+    L.ns = h.split_k;
     while (L.ns > 1 && hs_split_rows(L.K_pad, L.ns) * (L.ns - 1) >= L.K_pad) --L.ns;  // every segment holds rows
     if (L.ns > 1) {
       L.skH = take((size_t)L.ns * np * np * sizeof(double2));
@@ -317,7 +323,16 @@ int enqueue_operands(hsbuild_t h, const Layout& L, const double k_frac[3], const
 int enqueue_fp64_hs(hsbuild_t h, const Layout& L, char* w, int ng, void* H, void* S, hipStream_t s) {
   const double2 *W = (const double2*)(w + L.W), *WL = (const double2*)(w + L.WL), *Y = (const double2*)(w + L.Y);
   int rc;
-  if (L.ns > 1) {
+  if (L.nsh > 0) {
+    double2 *Hp = (double2*)(w + L.skH), *Sp = (double2*)(w + L.skS);
+    rc = launched(h, launch_hs_fp64_stream(W, WL, Y, L.K_pad, L.nsh, ng, L.n_pad, (double2*)H, (double2*)S, ng, Hp,
+                                           Sp, s),
+                  "k_hs_fp64_stream");
+    mark(h, 3, s);
+    if (!rc)
+      rc = launched(h, launch_stream_fixup(L.K_pad, L.nsh, ng, L.n_pad, Hp, Sp, (double2*)H, (double2*)S, ng, s),
+                    "k_stream_fixup");
+  } else if (L.ns > 1) {
     double2 *Hp = (double2*)(w + L.skH), *Sp = (double2*)(w + L.skS);
     rc = launched(h, launch_hs_fp64_sk(W, WL, Y, L.K_pad, L.ns, ng, L.n_pad, h->tile_group, Hp, Sp, s),
                   "k_hs_fp64_sk");

@@ -399,6 +399,83 @@ __global__ void __launch_bounds__(256) k_sk_reduce(const d2* __restrict__ Hp, co
   S[(int64_t)row * ldh + col] = sv;
 }
 
+// Stream-K form of the 8-wave contraction: the units (tile t, 16-row chunk of the stacked
+// index), tile-major, are dealt to nsh workgroups in equal contiguous shares, so every
+// workgroup does the same number of MFMAs whatever the tile count.  A share holds the end of
+// one tile, whole tiles and the start of another: whole tiles are stored into H and S, the
+// piece a share starts with into its slot 0 and the piece it ends with into its slot 1
+// (128 x 64 each, in Hp and Sp), and k_stream_fixup adds the pieces of each shared tile in
+// chunk order, so results repeat bitwise.  Share c: units [units c / nsh, units (c + 1) / nsh).
+__device__ inline int64_t stream_start(int64_t units, int nsh, int c) { return units * c / nsh; }
+// the share holding unit u
+__device__ inline int stream_share(int64_t units, int nsh, int64_t u) { return (int)(((u + 1) * nsh - 1) / units); }
+
+__global__ void __launch_bounds__(512, 1) k_hs_fp64_stream(const d2* __restrict__ W, const d2* __restrict__ WL,
+                                                           const d2* __restrict__ Y, int K_pad, int n, int n_pad,
+                                                           int nbr, int num_tiles, int nsh, int gr,
+                                                           d2* __restrict__ H, d2* __restrict__ S, int64_t ldh,
+                                                           d2* __restrict__ Hp, d2* __restrict__ Sp) {
+  __shared__ Smem sm;
+  const int x = blockIdx.x % kXcds;
+  int start, len;
+  xcd_range(x, nsh, start, len);
+  const int c = start + blockIdx.x / kXcds;  // consecutive shares, neighbouring tiles, on one XCD
+  const int nk = K_pad / BK;
+  const int64_t units = (int64_t)num_tiles * nk;
+  const int64_t u0 = stream_start(units, nsh, c), u1 = stream_start(units, nsh, c + 1);
+  for (int64_t u = u0; u < u1;) {
+    const int t = (int)(u / nk);
+    const int k0 = (int)(u - (int64_t)t * nk);
+    const int k1 = (int)min((int64_t)nk, k0 + (u1 - u));
+    // The tile routine's first copies go to LDS buffer 0, which the previous piece may still
+    // be reading (its last chunk is there when its chunk count is odd).
+    if (u != u0) __syncthreads();
+    int row0, col0;
+    tile_origin(t, nbr, gr, row0, col0);
+    if (col0 < n) {  // uniform across the workgroup
+      if (k0 == 0 && k1 == nk) {
+        hs_tile3m<4, true>(sm, W, WL, Y, K_pad, n_pad, n_pad, row0, col0, n, n, true, H, S, ldh);
+      } else {
+        // element (row, col) of the piece at slot + (row - row0) * BN + (col - col0)
+        const int64_t slot = (int64_t)(2 * c + (u == u0 ? 0 : 1)) * BM * BN - ((int64_t)row0 * BN + col0);
+        const int64_t off = (int64_t)k0 * BK * n_pad;
+        hs_tile3m<4, true>(sm, W + off, WL + off, Y + off, (k1 - k0) * BK, n_pad, n_pad, row0, col0, n, n, true,
+                           (d2*)((uintptr_t)Hp + slot * (int64_t)sizeof(d2)),
+                           (d2*)((uintptr_t)Sp + slot * (int64_t)sizeof(d2)), BN);
+      }
+    }
+    u = (int64_t)t * nk + k1;
+  }
+}
+
+// One workgroup per tile: a tile that lies in one share was stored whole; a shared one is the
+// sum, in share (= chunk) order, of its pieces: slot 0 of the shares that start inside it,
+// slot 1 of the one that starts before it.  Stored: row < n, col < n, col >= row.
+__global__ void __launch_bounds__(256) k_stream_fixup(int K_pad, int n, int nbr, int num_tiles, int nsh, int gr,
+                                                      const d2* __restrict__ Hp, const d2* __restrict__ Sp,
+                                                      d2* __restrict__ H, d2* __restrict__ S, int64_t ldh) {
+  const int t = blockIdx.x;
+  const int nk = K_pad / BK;
+  const int64_t units = (int64_t)num_tiles * nk;
+  const int c0 = stream_share(units, nsh, (int64_t)t * nk), c1 = stream_share(units, nsh, (int64_t)t * nk + nk - 1);
+  if (c0 == c1) return;
+  int row0, col0;
+  tile_origin(t, nbr, gr, row0, col0);
+  if (col0 >= n) return;
+  for (int e = threadIdx.x; e < BM * BN; e += 256) {
+    const int row = row0 + e / BN, col = col0 + e % BN;
+    if (row >= n || col >= n || col < row) continue;
+    d2 h = d2{0.0, 0.0}, sv = d2{0.0, 0.0};
+    for (int c = c0; c <= c1; ++c) {
+      const int slot = 2 * c + (stream_start(units, nsh, c) >= (int64_t)t * nk ? 0 : 1);
+      h += Hp[(int64_t)slot * BM * BN + e];
+      sv += Sp[(int64_t)slot * BM * BN + e];
+    }
+    H[(int64_t)row * ldh + col] = h;
+    S[(int64_t)row * ldh + col] = sv;
+  }
+}
+
 template <int WR>
 __global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64_batch(const d2* __restrict__ ws, const double* __restrict__ lam,
                                                            int K_pad, const BatchMeta* __restrict__ meta, int n_k,
@@ -409,6 +486,7 @@ __global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64_batch(const d2* __restr
   const int per_xcd = gridDim.x / kXcds;  // the grid is a multiple of the XCD count
   int start, len;
   xcd_range(x, total, start, len);
+  bool computed = false;  // a tile has been computed by this workgroup
   for (int i = blockIdx.x / kXcds; i < len; i += per_xcd) {
     const int t = start + i;
     int lo = 0, hi = n_k - 1;  // last k with tile_start <= t
@@ -421,6 +499,10 @@ __global__ void __launch_bounds__(128 * WR, 1) k_hs_fp64_batch(const d2* __restr
     int row0, col0;
     tile_origin(t - m.tile_start, m.nbr, gr, row0, col0);
     if (col0 >= m.n) continue;  // uniform across the workgroup
+    // The tile routine's first copies go to LDS buffer 0, which the previous tile may still be
+    // reading (its last chunk is there when the chunk count K_pad / 16 is odd).
+    if (computed) __syncthreads();
+    computed = true;
     if constexpr (WR == 4)
       hs_tile3m<WR, true>(sm, ws + m.w_off, ws + m.wl_off, ws + m.y_off, K_pad, m.n_pad, m.n_pad, row0, col0, m.n,
                           m.n, true, H + m.out_off, S + m.out_off, m.n);
@@ -632,20 +714,27 @@ hipError_t launch_hs_fp64(const double2* W, const double2* WL, const double2* Y,
   return hipGetLastError();
 }
 
-int hs_split_k(int n_pad, int K_pad, int num_cus) {
-  // time model: rounds of workgroups on the compute units times (rows per segment + a fixed
-  // cost of a workgroup worth about 128 rows: the pipeline start and the tile's stores)
+int hs_stream_shares(int n_pad, int K_pad, int num_cus) {
+  // time model, in stacked rows: a workgroup costs its rows plus about 128 per tile piece (the
+  // pipeline start and the stores).  One pass: rounds of whole tiles on the compute units;
+  // stream-K: the largest share, whose units span whole tiles and up to two partial ones.
   const int tiles = hs_tiles(n_pad);
-  if (tiles >= 4 * num_cus || num_cus < 1) return 1;
-  auto cost = [&](int ns) {
-    const double rounds = std::ceil((double)tiles * ns / num_cus);
-    return rounds * (hs_split_rows(K_pad, ns) + 128.0);
-  };
-  int best = 1;
-  for (int ns = 2; ns <= 8 && hs_split_rows(K_pad, ns) >= 256; ++ns)
-    if (cost(ns) < cost(best)) best = ns;
-  return best;
+  if (tiles >= 4 * num_cus || num_cus < 1) return 0;
+  const int nk = K_pad / BK;
+  const int64_t units = (int64_t)tiles * nk;
+  const int nsh = (int)std::min<int64_t>(num_cus, units / 16);  // shares of at least 16 chunks (256 rows)
+  if (nsh < 2) return 0;
+  const double one_pass = std::ceil((double)tiles / num_cus) * (K_pad + 128.0);
+  const double share = std::ceil((double)units / nsh);
+  const double stream = share * BK + 128.0 * (std::ceil(share / nk) + 1.0);
+  return stream < one_pass ? nsh : 0;
 }
+
+size_t hs_stream_slot_elems(int nsh) { return (size_t)2 * nsh * BM * BN; }
+
+// The stream-K units follow one fixed tile order (super-rows 8 at a time): where the shares cut
+// tiles, and so the rounding, must not depend on the tile-order option.
+constexpr int kStreamGroup = 8;
 
 int hs_split_rows(int K_pad, int ns) { return (int)round_up((K_pad + ns - 1) / ns, BK); }
 
@@ -657,6 +746,28 @@ hipError_t launch_hs_fp64_sk(const double2* W, const double2* WL, const double2*
   if (K_pad % BK || kseg * (ns - 1) >= K_pad) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_hs_fp64_sk, dim3(total), dim3(512), 0, s, (const d2*)W, (const d2*)WL, (const d2*)Y, K_pad,
                      kseg, n, n_pad, nbr, num_wg, total, gr, (d2*)Hp, (d2*)Sp);
+  return hipGetLastError();
+}
+
+hipError_t launch_hs_fp64_stream(const double2* W, const double2* WL, const double2* Y, int K_pad, int nsh, int n,
+                                 int n_pad, double2* H, double2* S, int64_t ldh, double2* Hp, double2* Sp,
+                                 hipStream_t s) {
+  const int gr = kStreamGroup;
+  const int nbr = n_pad / BM;
+  const int num_tiles = hs_tiles(n_pad);
+  if (K_pad % BK || nsh < 1 || (int64_t)num_tiles * (K_pad / BK) < nsh) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_hs_fp64_stream, dim3(nsh), dim3(512), 0, s, (const d2*)W, (const d2*)WL, (const d2*)Y, K_pad,
+                     n, n_pad, nbr, num_tiles, nsh, gr, (d2*)H, (d2*)S, ldh, (d2*)Hp, (d2*)Sp);
+  return hipGetLastError();
+}
+
+hipError_t launch_stream_fixup(int K_pad, int nsh, int n, int n_pad, const double2* Hp, const double2* Sp,
+                               double2* H, double2* S, int64_t ldh, hipStream_t s) {
+  const int gr = kStreamGroup;
+  const int nbr = n_pad / BM;
+  const int num_tiles = hs_tiles(n_pad);
+  hipLaunchKernelGGL(k_stream_fixup, dim3(num_tiles), dim3(256), 0, s, K_pad, n, nbr, num_tiles, nsh, gr,
+                     (const d2*)Hp, (const d2*)Sp, (d2*)H, (d2*)S, ldh);
   return hipGetLastError();
 }
 
