@@ -401,9 +401,9 @@ def real_leg(args) -> dict:
 
 def small_leg(args) -> dict:
     """One k-point of the 16-atom l_max 8 cell at N_G = 3000 (k_c = 1296): the whole
-    forward, its contraction against the FP64 MFMA roofline (executed 3M flops), with
-    the automatic split of the stacked index (600 tiles: fewer than 4 per compute unit)
-    and without it."""
+    forward, its contraction against the FP64 MFMA roofline (executed 3M flops), in the
+    library's default stream-K form (600 tiles: fewer than 4 per compute unit), with the
+    stacked index in two segments, and in one pass."""
     import torch
 
     from flapw_cells import make_case
@@ -527,7 +527,7 @@ def batch_leg(args) -> dict:
     torch.cuda.synchronize()
     ms_graph = e0.elapsed_time(e1) / reps
     # sequential: one forward per k on the same stream, outputs written in place, with the
-    # library's default split of the stacked index (small bases) and with the one-pass form
+    # library's default (stream-K on these small bases) and with the one-pass form
     outs = [(H[int(off[k]): int(off[k]) + ng[k] ** 2].view(ng[k], ng[k]),
              S[int(off[k]): int(off[k]) + ng[k] ** 2].view(ng[k], ng[k])) for k in range(n_k)]
     seq = {}
