@@ -797,7 +797,7 @@ def main() -> int:
                     help="first run one plain device-to-device copy of this many MiB (calibrates HBM counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (the H/S tiles would be "
+        print("bench.py measures one GPU: the library has no multi-GPU path (the H/S tiles would be "
               "dealt over GPUs with no exchange; see the design notes). Run with --gpus 1.")
         return 2
 

@@ -60,7 +60,7 @@ enum {
   HSB_ERR_SHAPE = -2,       /* inconsistent sizes (e.g. ng > max_ng) */
   HSB_ERR_WORKSPACE = -3,   /* workspace smaller than hsbuild_workspace_bytes() */
   HSB_ERR_DEVICE = -4,      /* no usable gfx950 device, or a launch error */
-  HSB_ERR_UNSUPPORTED = -5, /* valid request this build does not implement */
+  HSB_ERR_UNSUPPORTED = -5, /* valid request the library does not implement */
   HSB_ERR_NUMERIC = -6      /* singular radial Wronskian at create */
 };
 
